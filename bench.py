@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of batched multi-source GOVM against plain single-source GOVM.
+
+Workload (default): directed R-MAT, scale 20 (1,048,576 vertices), edge
+factor 16, a=0.57 b=0.19 c=0.19, uint32 weights uniform in [1,255]; 256
+distinct sources run as one [n x 256] distance tile per step.
+
+One "step" = one dawn_msssp call over the 256 sources: tile reset, seeding,
+every GOVM step until no source changes, and the transposed store of the
+[256 x n] result.  The graph and sources are resident in HBM before timing.
+
+Printed: ONE JSON line.  value = aggregate GTEPS of the batched call
+(sum over sources of the edges reachable from the source, divided by the
+wall time of a step).  Also: sources/s batched and plain, their ratio, the
+roofline of the dominant kernel (the tile's persistent GOVM kernel, timed
+with HIP events on its own stream) and the CPU oracle's rate on a bounded
+sample of the same sources.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def reach_edges(torch, dist, outdeg, inf):
+    """Sum of out-degrees over vertices each row of `dist` reaches (finite)."""
+    tot = []
+    for r0 in range(0, dist.shape[0], 32):
+        blk = dist[r0:r0 + 32]
+        fin = blk != inf
+        tot.append((fin.to(torch.int64) * outdeg).sum(dim=1))
+    return torch.cat(tot).cpu().tolist()
+
+
+def tile_kernel_bytes(info: dict, nseg: int) -> int:
+    """Algorithmic bytes of the tile's GOVM kernel for one launch.
+
+    per union-frontier row: row bounds 8 B + queue id 4 B + mask read and clear
+      2 * 8 B per 64-source segment;
+    per active (row, source): the source's distance at the row, 4 B;
+    per union edge: column id + weight, 8 B;
+    per active (edge, source): the target's distance, 4 B;
+    per improvement: the new distance, 4 B."""
+    return (info["union_rows"] * (12 + 16 * nseg) + 4 * info["frontier_entries"]
+            + 8 * info["union_edges"] + 4 * info["edges_scanned"] + 4 * info["improvements"])
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--k", type=int, default=256)
+    ap.add_argument("--plain", type=int, default=256, help="sources timed one per launch")
+    ap.add_argument("--cpu-sample", type=int, default=32, help="sources timed on the oracle")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "design (sources sharded across GPUs) is not part of this build.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2306_07872_amd as dawn
+    from graphgen import workloads
+
+    torch.cuda.set_device(0)
+    dawn.load()
+    t_gen = time.perf_counter()
+    g, srcs = workloads.rmat20_tile(k=args.k, scale=args.scale)
+    log(f"graph {g.name}: n={g.n} m={g.m} k={len(srcs)} ({time.perf_counter() - t_gen:.1f}s)")
+    csr = dawn.Csr.from_graph(g)
+    src_t = torch.as_tensor(srcs, dtype=torch.int32, device="cuda")
+    k = int(src_t.numel())
+    out = torch.empty((k, g.n), dtype=torch.uint32, device="cuda")
+    ws = dawn.workspace(dawn.msssp_workspace_bytes(g.n, g.m, k))
+    info = dawn.info_tensor()
+    tune = dawn.get_tuning()
+
+    # ---- batched: warmup, then K timed steps --------------------------------
+    for _ in range(args.warmup):
+        dawn.msssp(csr, src_t, out=out, ws=ws, info=info)
+    torch.cuda.synchronize()
+    dawn.kernel_timer(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dawn.msssp(csr, src_t, out=out, ws=ws, info=info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dawn.kernel_timer(False)
+    k_ms, k_launches = dawn.kernel_time()
+    inf = dawn.read_info(info)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    log(f"batched: {ms_step:.3f} ms/step, kernel {k_ms / max(k_launches, 1):.3f} ms/launch, "
+        f"info {inf}")
+
+    outdeg = torch.as_tensor(np.diff(g.rowptr.astype(np.int64)), device="cuda")
+    reach = reach_edges(torch, out, outdeg, 0xFFFFFFFF)
+    work = float(sum(reach))
+    gteps = work / (ms_step * 1e-3) / 1e9
+    srcs_per_s = k / (ms_step * 1e-3)
+
+    # ---- plain single-source on the same sources ------------------------------
+    nplain = min(args.plain, k)
+    out1 = torch.empty(g.n, dtype=torch.uint32, device="cuda")
+    ws1 = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
+    for s in srcs[:3]:
+        dawn.sssp(csr, int(s), out=out1, ws=ws1)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for s in srcs[:nplain]:
+        dawn.sssp(csr, int(s), out=out1, ws=ws1)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    plain_s = (t3 - t2) / nplain
+    plain_gteps = float(sum(reach[:nplain])) / (t3 - t2) / 1e9
+    log(f"plain: {plain_s * 1e3:.3f} ms/source ({nplain} sources)")
+
+    # ---- roofline of the dominant kernel -------------------------------------
+    nseg = (min(k, tune["tile_k"]) + 63) // 64
+    kbytes = tile_kernel_bytes(inf, nseg)
+    avg_kms = k_ms / max(k_launches, 1)
+    # each timed step launches the tile kernel once per tile of tile_k sources
+    tiles = (k + tune["tile_k"] - 1) // tune["tile_k"]
+    per_launch_bytes = kbytes / tiles
+    achieved = per_launch_bytes / (avg_kms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "tile_persistent_kernel<false>",
+                "kernel_ms": round(avg_kms, 4), "algorithmic_bytes": int(per_launch_bytes)}
+
+    # ---- CPU oracle on a bounded sample ---------------------------------------
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+        sample = [int(s) for s in srcs[:args.cpu_sample]]
+        r = oracle.time_sources(g, sample, threads, "u32")
+        sw = float(sum(reach[:len(sample)]))
+        cpu = {"value": round(sw / r["seconds"] / 1e9, 4), "unit": "GTEPS", "cores": r["threads"],
+               "kind": "oracle",
+               "sample": f"binary-heap Dijkstra (uint64 sums) from the first {len(sample)} of the "
+                         f"{k} sources on the same graph, one source per thread",
+               "sources_per_s": round(len(sample) / r["seconds"], 2),
+               "seconds": round(r["seconds"], 2)}
+        log(f"cpu oracle: {cpu}")
+
+    res = {
+        "metric": "GTEPS & sources/s, batched k-source GOVM vs plain 1-source GOVM; p50/p99 query ms",
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"rmat{args.scale}_ef16_u32_k{k}", "n": g.n, "m": g.m, "k": k,
+                   "weights": "uint32 uniform [1,255]", "sources": "uniform among out-degree>=1"},
+        "sources_per_s": round(srcs_per_s, 1),
+        "plain_sources_per_s": round(1.0 / plain_s, 1),
+        "plain_gteps": round(plain_gteps, 3),
+        "batched_vs_plain_sources_per_s": round(srcs_per_s * plain_s, 2),
+        "steps_max": inf["steps"],
+        "mu_e": round(inf["edges_scanned"] / max(work, 1.0), 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "tuning": tune,
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,260 @@
+/*
+ * dawn.h -- C ABI of the MI355X (gfx950) GOVM library.
+ *
+ * GOVM ("General Optimized Vector-Matrix operation", Section 3.4, Algorithm 2
+ * of Feng, "Expanding the Scope of DAWN: A Novel Version for Weighted Shortest
+ * Path Problem", arXiv 2306.07872) computes single-source shortest paths on a
+ * weighted directed graph stored as CSR.  Each step applies the (min,+)
+ * vector-matrix product  p_j = min_k (p_k + a_kj)  but only over the rows k
+ * whose distance changed in the previous step; it stops after a step with no
+ * change (the paper's "ptr" flag) or after n steps.  Section 3.1 shows the
+ * fixed point is the Floyd-Warshall recurrence's, so for non-negative weights
+ * the output is exactly the shortest-path distance vector:
+ *
+ *   d(v) = min over directed source->v paths of the path weight,
+ *   d(source) = 0, d(v) = INF when v is unreachable.
+ *
+ * Multi-source (MSSP) and all-pairs (APSP) repeat this per source (Section 1,
+ * Section 3.4 "APSP" cost); the library batches sources into a distance tile
+ * because different sources never update the same path (Section 3.5).
+ *
+ * Conventions for every call
+ * --------------------------
+ * - Graph: rowptr int32[n+1] (rowptr[0] = 0, non-decreasing, rowptr[n] = m),
+ *   colidx int32[m] in [0,n), weights[m] of type `wt`.  Rows need not be
+ *   sorted; self-loops and parallel edges are allowed.
+ * - Weights: DAWN_W_U32 = uint32 (any value; sums saturate at 0xFFFFFFFF, so a
+ *   path of total weight >= 2^32-1 reads as unreachable), or DAWN_W_F32 =
+ *   float32, finite with the sign bit clear (no negatives, no -0.0, no NaN).
+ *   fp32 sums are IEEE round-to-nearest-even, no flush to zero.
+ * - Distances: uint32 (INF = 0xFFFFFFFF) or float32 (INF = +inf), matching
+ *   the weight type.
+ * - Pointers named *_dev are DEVICE pointers (hipMalloc'd or torch CUDA
+ *   tensors) owned by the caller.  The library never frees them and keeps no
+ *   pointer after the call's stream work completes, except tile and batch
+ *   sessions, which keep their graph pointers until destroyed.
+ * - Every call is stream-ordered and asynchronous: it validates its scalar
+ *   arguments on the host, enqueues work on `stream` and returns.  The return
+ *   code reports host-side validation and launch errors only; a device fault
+ *   surfaces at the caller's next synchronisation.
+ * - Without a caller workspace, scratch memory is taken with hipMallocAsync
+ *   and released with hipFreeAsync on the same stream.
+ * - With tuning fields out of range a call returns DAWN_E_INVALID.  Tuning
+ *   never changes results: the distances are unique (see above).
+ */
+#ifndef DAWN_H_
+#define DAWN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DAWN_OK = 0,
+  DAWN_E_INVALID = 1,     /* bad argument: n < 1, m < 0, source out of range, k < 1,
+                             null pointer, unknown weight type, tuning out of range */
+  DAWN_E_UNSUPPORTED = 2, /* valid request this build does not handle (mixed weight
+                             types in one batch, k above the tile maximum, ...) */
+  DAWN_E_WORKSPACE = 3,   /* caller workspace smaller than dawn_*_workspace_bytes() */
+  DAWN_E_HIP = 4          /* a HIP runtime call failed (allocation, launch) */
+} dawn_status;
+
+typedef enum { DAWN_W_U32 = 0, DAWN_W_F32 = 1 } dawn_wtype;
+
+/* Device-written run summary (optional output of the *_ws calls).  Counters
+ * follow the paper's cost model (Section 3.4: T = mu(s) * E_wcc(s)):
+ *   steps            iterations of the step loop, including the final step
+ *                    that changes nothing (Algorithm 2's loop count);
+ *   converged        1 = stopped after a step with no change; 0 = stopped at
+ *                    the n-step cap; -1 = input validation failed on the
+ *                    device; -2 = a persistent launch gave up waiting at a grid
+ *                    barrier (the result is then incomplete);
+ *   frontier_entries sum over steps of the rows expanded (changed in the
+ *                    previous step and having out-edges);
+ *   edges_scanned    sum over steps of the out-degrees of those rows;
+ *   improvements     successful strict decreases of a distance.
+ * For a batched call the counters are summed over its sources and `steps` is
+ * the largest per-source step count; union_rows / union_edges count the rows
+ * and edges the tile actually read (each serving every source active there).
+ * For single-source calls they equal frontier_entries / edges_scanned. */
+typedef struct {
+  int32_t steps;
+  int32_t converged;
+  int64_t frontier_entries;
+  int64_t edges_scanned;
+  int64_t improvements;
+  int64_t union_rows;   /* batched calls: rows expanded once for all sources */
+  int64_t union_edges;  /* batched calls: edges read once for all sources */
+} dawn_run_info;
+
+/* Launch tuning, process-wide (set before concurrent use; not thread-safe).
+ * Frontier rows are binned by out-degree d into three tiers:
+ *   lane tier      d <= t_lane   rows packed 64 per wavefront, one edge per lane;
+ *   wave tier      d <= t_wave   one wavefront per row (t_wave >= 64);
+ *   workgroup tier d >  t_wave   the row is cut into chunks of t_chunk edges,
+ *                                one workgroup per chunk.
+ * mode: 0 auto, 1 step launches (one kernel per step, host checks termination
+ * every `host_check` steps), 2 one persistent cooperative launch for all steps.
+ * wg_threads: 256, 512 or 1024.  grid: workgroups per launch, 0 = auto.
+ * tile_k: sources per tile for dawn_msssp / dawn_apsp, a multiple of 64,
+ * at most DAWN_TILE_K_MAX. */
+typedef struct {
+  int32_t t_lane;     /* 1..64, default 16 */
+  int32_t t_wave;     /* max(64,t_lane)..65536, default 2048 */
+  int32_t t_chunk;    /* 256..1<<20, default 8192 */
+  int32_t wg_threads; /* default 256 */
+  int32_t grid;       /* default 0 (auto) */
+  int32_t mode;       /* default 0 (auto) */
+  int32_t host_check; /* 1..4096, default 32 */
+  int32_t tile_k;     /* default 256 */
+  int32_t tile_t_wave;  /* workgroup-tier threshold of the tile kernel, 32..65536, default 256 */
+  int32_t tile_t_chunk; /* edges per workgroup chunk in the tile kernel, 64..65536, default 512 */
+  int32_t validate;     /* 1 = check the CSR on the device before running */
+} dawn_tuning;
+
+#define DAWN_TILE_K_MAX 512
+
+dawn_status dawn_get_tuning(dawn_tuning* out);
+dawn_status dawn_set_tuning(const dawn_tuning* in); /* NULL restores the defaults */
+
+const char* dawn_status_str(dawn_status s);
+/* Last error text of this thread (HIP error string or validation message). */
+const char* dawn_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Single source (Algorithm 2).  dist_out_dev: n elements (uint32 or float32
+ * per wt), fully written.
+ * ------------------------------------------------------------------------- */
+dawn_status dawn_sssp(const int32_t* rowptr_dev, const int32_t* colidx_dev,
+                      const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
+                      int32_t source, void* dist_out_dev, hipStream_t stream);
+
+/* Bytes of scratch a single-source call needs for this graph. */
+size_t dawn_sssp_workspace_bytes(int32_t n, int32_t m);
+
+/* Same, with caller scratch (>= dawn_sssp_workspace_bytes, 256-byte aligned
+ * device memory, contents ignored) and an optional DEVICE pointer to a
+ * dawn_run_info the device fills. */
+dawn_status dawn_sssp_ws(const int32_t* rowptr_dev, const int32_t* colidx_dev,
+                         const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
+                         int32_t source, void* dist_out_dev, void* ws_dev, size_t ws_bytes,
+                         dawn_run_info* info_dev, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Multi source.  sources_dev: int32[k] on the device (duplicates allowed).
+ * dist_out_dev: k x n row-major, row j = distances from sources[j].  Sources
+ * are processed in tiles of tile_k columns of an [n x tile_k] distance tile,
+ * so every edge read from memory serves up to tile_k relaxations.
+ * ------------------------------------------------------------------------- */
+dawn_status dawn_msssp(const int32_t* rowptr_dev, const int32_t* colidx_dev,
+                       const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
+                       const int32_t* sources_dev, int32_t k, void* dist_out_dev,
+                       hipStream_t stream);
+
+size_t dawn_msssp_workspace_bytes(int32_t n, int32_t m, int32_t k);
+
+dawn_status dawn_msssp_ws(const int32_t* rowptr_dev, const int32_t* colidx_dev,
+                          const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
+                          const int32_t* sources_dev, int32_t k, void* dist_out_dev,
+                          void* ws_dev, size_t ws_bytes, dawn_run_info* info_dev,
+                          hipStream_t stream);
+
+/* All pairs: dist_out_dev is n x n row-major (row s = distances from s).
+ * DAWN_E_INVALID if n*n elements overflow size_t. */
+dawn_status dawn_apsp(const int32_t* rowptr_dev, const int32_t* colidx_dev,
+                      const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
+                      void* dist_out_dev, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Many graphs in one launch.  A batch concatenates `count` CSR graphs of one
+ * weight type into a single disjoint union held in library-owned device memory
+ * (vertex ids and edge positions offset by a graph-offset table), so one GOVM
+ * run seeded with one source per graph solves all of them at once.  The run
+ * can be captured once into a HIP graph and replayed with new sources.
+ * ------------------------------------------------------------------------- */
+typedef struct dawn_batch dawn_batch;
+
+/* Arrays of `count` device pointers / sizes, read on the host during the
+ * call; the graph data is copied, so the caller may free it afterwards. */
+dawn_status dawn_batch_create(dawn_batch** out, int32_t count, const int32_t* const* rowptr_devs,
+                              const int32_t* const* colidx_devs, const void* const* weight_devs,
+                              const int32_t* ns, const int32_t* ms, dawn_wtype wt,
+                              hipStream_t stream);
+/* Totals of the union: sum of n and of m. */
+dawn_status dawn_batch_sizes(const dawn_batch* b, int64_t* total_n, int64_t* total_m);
+/* Vertex offset of graph i inside the union (host value). */
+int64_t dawn_batch_vertex_offset(const dawn_batch* b, int32_t i);
+/* sources_dev: int32[count], LOCAL vertex id of each graph's source.
+ * dist_out_dev: total_n elements; graph i's distances start at its vertex
+ * offset.  info_dev optional (summed over graphs). */
+dawn_status dawn_batch_run(dawn_batch* b, const int32_t* sources_dev, void* dist_out_dev,
+                           dawn_run_info* info_dev, hipStream_t stream);
+/* Capture dawn_batch_run(b, sources_dev, dist_out_dev, info_dev) into a HIP
+ * graph once; dawn_batch_replay launches it again (the device buffers named
+ * at capture are re-read, so new source ids written there take effect). */
+dawn_status dawn_batch_capture(dawn_batch* b, const int32_t* sources_dev, void* dist_out_dev,
+                               dawn_run_info* info_dev, hipStream_t stream);
+dawn_status dawn_batch_replay(dawn_batch* b, hipStream_t stream);
+void dawn_batch_destroy(dawn_batch* b);
+
+/* ---------------------------------------------------------------------------
+ * Tile sessions (continuous batching).  A tile holds per-query distance state
+ * for up to k queries on one resident graph as an [n x k] column tile.  Queries
+ * are admitted into free columns between runs, advance together one GOVM step
+ * at a time, and are read out when done; each column's arithmetic is the same
+ * as a lone query's, so results do not depend on what else shares the tile.
+ * ------------------------------------------------------------------------- */
+typedef struct dawn_tile dawn_tile;
+
+/* Device bytes a tile of k columns needs (allocated by dawn_tile_create). */
+size_t dawn_tile_bytes(int32_t n, int32_t m, int32_t k);
+/* k: 1..DAWN_TILE_K_MAX (rounded up to a multiple of 64 internally).  The CSR
+ * arrays must stay valid until dawn_tile_destroy. */
+dawn_status dawn_tile_create(dawn_tile** out, const int32_t* rowptr_dev, const int32_t* colidx_dev,
+                             const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
+                             int32_t k, hipStream_t stream);
+/* Start query `source` in free column col (0..k-1). */
+dawn_status dawn_tile_admit(dawn_tile* t, int32_t col, int32_t source, hipStream_t stream);
+/* Run up to max_steps GOVM steps for every admitted column (steps stop early
+ * on the device once no column is active).  If done_bits_dev is non-NULL it
+ * receives k bits (uint32 words, bit j of word j/32) set for admitted columns
+ * that have finished. */
+dawn_status dawn_tile_run(dawn_tile* t, int32_t max_steps, uint32_t* done_bits_dev,
+                          hipStream_t stream);
+/* Copy column col (n distances) to dist_out_dev; valid once the column is done. */
+dawn_status dawn_tile_read(dawn_tile* t, int32_t col, void* dist_out_dev, hipStream_t stream);
+/* Per-column step counts (int32[k]) to steps_out_dev. */
+dawn_status dawn_tile_steps(dawn_tile* t, int32_t* steps_out_dev, hipStream_t stream);
+/* Cancel the query in column col (its column becomes free). */
+dawn_status dawn_tile_evict(dawn_tile* t, int32_t col, hipStream_t stream);
+void dawn_tile_destroy(dawn_tile* t);
+
+/* Kernel timer for measurement.  While enabled, every main GOVM launch (the
+ * persistent kernel, or a run of step launches) is bracketed by HIP events on
+ * the stream it runs on.  dawn_kernel_timer(1) clears and starts recording,
+ * dawn_kernel_timer(0) stops; dawn_kernel_time waits for the recorded events
+ * and returns their summed elapsed milliseconds and how many launches they
+ * cover.  Not recorded under HIP graph capture. */
+dawn_status dawn_kernel_timer(int32_t enable);
+dawn_status dawn_kernel_time(double* total_ms, int32_t* launches);
+
+/* Device query for tuning, about the current device: out[0] = compute units,
+ * out[1] = cooperative launch supported (0/1), out[2] / out[3] = workgroups
+ * per compute unit the single-source / tile persistent kernels can hold at the
+ * current wg_threads, out[4] / out[5] = the persistent grid each would use,
+ * out[6] = device id, out[7] = wg_threads.  `out` is a host array of 8. */
+dawn_status dawn_device_query(int32_t* out);
+
+/* Build information: "gfx950 <compile options>". */
+const char* dawn_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DAWN_H_ */

@@ -217,7 +217,8 @@ def f32_tolerance_violations(g, s: int, d_gpu: np.ndarray, d64=None, h64=None, d
     bad = inf_ref != inf_gpu
     fin = ~inf_ref & ~inf_gpu
     tol = np.ldexp(1.0, -22) * hops * d64
-    err = np.abs(d_gpu - d64)
+    with np.errstate(invalid="ignore"):
+        err = np.where(fin, np.abs(d_gpu - np.where(fin, d64, 0.0)), 0.0)
     bad |= fin & (err > tol)
     if d_gpu[s] != 0.0:
         bad[s] = True

@@ -1,0 +1,253 @@
+// govm_device.hpp -- device-side building blocks of the GOVM kernels (gfx950).
+//
+// GOVM (Section 3.4, Algorithm 2) keeps three vectors: alpha (distances),
+// delta (rows to expand this step) and beta (rows changed this step).  Here:
+//   alpha -> the caller's distance array (uint32, or fp32 kept as its bits);
+//   delta -> per-tier frontier queues of vertex ids (compacted, no dense scan);
+//   beta  -> a bitmap that deduplicates the next frontier, whose first setter
+//            of each bit appends the vertex to the next queues with a
+//            wavefront ballot + prefix count (one atomic per wavefront);
+//   ptr   -> a per-step "something improved" flag.
+// Distances only decrease, so the relaxation is an atomic min; for
+// non-negative fp32 values the bit patterns order like uint32, so one uint32
+// atomic min serves both weight types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dawn {
+
+constexpr uint32_t kInfU32 = 0xFFFFFFFFu;
+constexpr uint32_t kInfF32 = 0x7F800000u;  // +inf bits
+constexpr int kWave = 64;
+constexpr int kMaxWavesPerBlock = 16;      // 1024-thread workgroups
+constexpr int kRot = 4;                    // rotation of per-step counters
+constexpr int kSegMax = 8;                 // 8 x 64 = 512 tile columns
+
+// Per-run control block in device memory (zeroed before a run).
+struct alignas(256) SsCtl {
+  uint32_t cnt[kRot][4];      // [step % 4][tier]: lane, wave, workgroup-chunk records
+  uint32_t upd[kRot];         // [step % 4]: any improvement during the previous step
+  uint32_t step;              // next step to run
+  uint32_t done;              // 1 once the loop has stopped
+  int32_t converged;          // see dawn_run_info
+  uint32_t bar;               // grid barrier arrivals (monotone within a launch)
+  uint32_t abort;             // set when a barrier wait gives up
+  uint32_t blocks_done;       // last-block detection of step launches
+  uint32_t overflow;          // a queue capacity was exceeded (cannot happen on valid input)
+  uint32_t bar_base;          // value of `bar` when the next persistent launch starts
+  unsigned long long fe, es, im;  // frontier rows, edges scanned, improvements
+};
+
+struct alignas(256) TileCtl {
+  uint32_t cnt[kRot][4];               // [step % 4][tier]: -, wave, workgroup-chunk
+  unsigned long long colact[kRot][kSegMax];  // [step % 4]: columns improved in step-1
+  unsigned long long live[kSegMax];    // admitted columns
+  uint32_t step, done;
+  int32_t converged;
+  uint32_t bar, abort, blocks_done, overflow, bar_base;
+  unsigned long long fe, es, im, sa, se;  // union rows, union edges, improvements,
+                                          // per-source rows, per-source edges
+  int32_t colsteps[kSegMax * 64];
+};
+
+struct Acc {
+  unsigned long long fe = 0, es = 0, im = 0, sa = 0, se = 0;
+};
+
+// ---------------------------------------------------------------------------
+// arithmetic: d (+) w
+// ---------------------------------------------------------------------------
+template <bool F32>
+__device__ __forceinline__ uint32_t relax_add(uint32_t d, uint32_t w) {
+  if constexpr (F32) {
+    // One IEEE fp32 add, round to nearest even (no FMA: nothing to contract).
+    return __float_as_uint(__uint_as_float(d) + __uint_as_float(w));
+  } else {
+    const uint32_t s = d + w;
+    return s < d ? kInfU32 : s;  // saturate
+  }
+}
+
+template <bool F32>
+__device__ __forceinline__ constexpr uint32_t inf_bits() {
+  return F32 ? kInfF32 : kInfU32;
+}
+
+// ---------------------------------------------------------------------------
+// memory-model helpers (agent scope = the whole device, all XCDs)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_agent64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// wavefront helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Number of set bits of `mask` in lanes below this one.
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+  return x;
+}
+
+// Orders this wavefront's LDS writes before its own later LDS reads.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Append `val` for every lane with `pred` set: one atomic per wavefront
+// reserves the range, each lane writes at base + (number of lanes below it).
+// Must be reached by the whole wavefront.
+__device__ __forceinline__ void wave_push(bool pred, int32_t val, int32_t* q, uint32_t* count,
+                                          uint32_t cap, uint32_t* overflow) {
+  const unsigned long long b = __ballot(pred);
+  if (b == 0) return;
+  const int leader = __ffsll((long long)b) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(b));
+  base = __shfl(base, leader, kWave);
+  if (pred) {
+    const uint32_t pos = base + lanes_below(b);
+    if (pos < cap) q[pos] = val;
+    else atomicOr(overflow, 1u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// grid barrier for persistent launches
+//
+// Arrivals increment one monotone counter; a block waits until the counter
+// reaches base + epoch * nblocks (`base` = the counter's value when the launch
+// started, so the counter is never reset while a block may still be waiting).  Release/acquire fences at agent scope make every
+// write before the barrier visible to every read after it, across the L2s of
+// all XCDs.  The wait is bounded by wall-clock time (s_memrealtime runs at
+// 100 MHz): past the bound the block raises `abort` and every block leaves, so
+// the kernel always terminates.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kBarrierTimeoutTicks = 400000000ull;  // 4 s at 100 MHz
+
+__device__ __forceinline__ bool grid_sync(uint32_t* bar, uint32_t* abort_flag, uint32_t nblocks,
+                                          uint32_t base, uint32_t& epoch) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    epoch += 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t target = base + epoch * nblocks;
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    int ok = 1;
+    for (;;) {
+      const uint32_t cur = ld_agent(bar);
+      if ((int32_t)(cur - target) >= 0) break;
+      if (ld_agent(abort_flag)) { ok = 0; break; }
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks) {
+        st_agent(abort_flag, 1u);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// Last-block detection for step launches: returns true in thread 0 of the
+// block that finishes last (after all others' writes are visible).
+__device__ __forceinline__ bool last_block_done(uint32_t* blocks_done) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t prev = __hip_atomic_fetch_add(blocks_done, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (prev == gridDim.x - 1);
+    if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  return s_last != 0 && threadIdx.x == 0;
+}
+
+// Sum per-thread counters over the block and add them to the control block.
+__device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* fe,
+                                          unsigned long long* es, unsigned long long* im,
+                                          unsigned long long* sa, unsigned long long* se) {
+  const unsigned long long v0 = wave_sum64(a.fe), v1 = wave_sum64(a.es), v2 = wave_sum64(a.im);
+  const unsigned long long v3 = sa ? wave_sum64(a.sa) : 0ull, v4 = se ? wave_sum64(a.se) : 0ull;
+  if (lane_id() == 0) {
+    if (v0) atomicAdd(fe, v0);
+    if (v1) atomicAdd(es, v1);
+    if (v2) atomicAdd(im, v2);
+    if (sa && v3) atomicAdd(sa, v3);
+    if (se && v4) atomicAdd(se, v4);
+  }
+}
+
+}  // namespace dawn
+
+namespace dawn {
+
+// Kernel arguments of a single-source (or many-seed) GOVM run.
+struct SsArgs {
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const uint32_t* w;      // uint32 weights, or fp32 weights as bits
+  uint32_t* dist;         // alpha
+  int32_t n, m;
+  int32_t src;            // the "index != source" guard; -1 with many seeds
+  int32_t t_lane, t_wave, t_chunk;
+  int32_t* qlane[2];      // delta, lane tier   [step % 2]
+  int32_t* qwave[2];      // delta, wave tier
+  int4* qwg[2];           // delta, workgroup tier: {row, first edge, edges, first chunk?}
+  uint32_t* bm[2];        // beta dedup bitmaps [step % 2]
+  uint32_t cap_v, cap_wg;
+  SsCtl* ctl;
+};
+
+// Kernel arguments of a batched [n x K] distance-tile run (K = 64 * nseg).
+struct TileArgs {
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const uint32_t* w;
+  uint32_t* D;            // [n][K] vertex-major: the K sources of a vertex are contiguous
+  int32_t n, m, K, nseg;
+  int32_t t_wave, t_chunk;
+  unsigned long long* mk[3];  // per-vertex active-source masks [step % 3][n][nseg]
+  int32_t* qwave[3];          // union frontier, wave tier [step % 3]
+  int4* qwg[3];               // union frontier, workgroup-chunk records
+  uint32_t* ubm[2];           // union-frontier dedup bitmaps [step % 2]
+  uint32_t cap_v, cap_wg;
+  TileCtl* ctl;
+};
+
+}  // namespace dawn

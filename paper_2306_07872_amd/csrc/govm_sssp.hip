@@ -1,0 +1,474 @@
+// govm_sssp.hip -- single-source GOVM (Section 3.4, Algorithm 2) on gfx950.
+//
+// One step expands every row in the frontier delta (the rows whose distance
+// changed in the previous step, Algorithm 2's `delta[j] = true and start != end`
+// test): for each out-edge (u, v, w) it forms cand = alpha[u] (+) w and lowers
+// alpha[v] to cand if cand is strictly smaller (with the `index != source`
+// guard).  Every v lowered this step is recorded in beta; beta becomes the next
+// delta and the loop stops after a step that lowers nothing (`ptr` false) or
+// after n steps.
+//
+// Mapping to the device:
+// - delta is kept compacted as three queues binned by out-degree:
+//     lane tier (deg <= t_lane): 64 rows per wavefront; the wavefront's rows are
+//       concatenated through an LDS prefix sum so each lane takes one edge;
+//     wave tier (deg <= t_wave): one wavefront per row, lanes stride the row;
+//     workgroup tier: the row is cut into t_chunk-edge chunks, one workgroup each.
+// - beta is a bitmap; the lane whose atomicOr first sets v's bit appends v to
+//   the right next-step queue (wavefront ballot + mbcnt prefix, one atomicAdd
+//   per wavefront).  The bitmap of the current step is cleared by the lanes
+//   that expand its rows, so no O(n) scan is ever needed.
+// - The relaxation reads alpha[v] with a plain load first (a stale value can
+//   only be higher, so skipping on it is safe) and uses atomicMin only when
+//   the candidate is smaller.  Order of updates inside a step does not matter:
+//   the fixed point is unique (Section 3.5: the method does not care in which
+//   order paths appear).
+// - Step loop: one persistent cooperative launch with a grid barrier per step
+//   (used by default), or one launch per step with last-block bookkeeping.
+#include <stdio.h>
+
+#include <algorithm>
+
+#include "govm_host.hpp"
+
+namespace dawn {
+
+// ---------------------------------------------------------------------------
+// init
+// ---------------------------------------------------------------------------
+template <bool F32>
+__global__ void ss_fill_kernel(uint32_t* dist, int64_t n, uint32_t* bm0, uint32_t* bm1,
+                               int64_t nwords, SsCtl* ctl) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = tid; i < n; i += stride) dist[i] = inf_bits<F32>();
+  for (int64_t i = tid; i < nwords; i += stride) { bm0[i] = 0; bm1[i] = 0; }
+  if (blockIdx.x == 0) {
+    uint32_t* c = reinterpret_cast<uint32_t*>(ctl);
+    for (int i = threadIdx.x; i < (int)(sizeof(SsCtl) / 4); i += blockDim.x) c[i] = 0;
+  }
+}
+
+// CSR checks (tuning field `validate`): rowptr[0] == 0, rowptr[n] == m,
+// non-decreasing rows, column ids in range, fp32 weights finite with the sign
+// bit clear.  A failure marks the run done with converged = -1.
+__global__ void ss_validate_kernel(const int32_t* rowptr, const int32_t* colidx,
+                                   const uint32_t* w, int32_t n, int32_t m, int32_t is_f32,
+                                   uint32_t* done, int32_t* converged) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  if (tid == 0) bad = rowptr[0] != 0 || rowptr[n] != m;
+  for (int64_t i = tid; i < n; i += stride) bad |= rowptr[i + 1] < rowptr[i];
+  for (int64_t e = tid; e < m; e += stride) {
+    const int32_t v = colidx[e];
+    bad |= v < 0 || v >= n;
+    if (is_f32) bad |= (w[e] & 0x80000000u) != 0 || (w[e] & 0x7F800000u) == 0x7F800000u;
+  }
+  if (bad) {
+    *converged = -1;
+    *done = 1;
+  }
+}
+
+// Put the seeds in step 0's delta: alpha[s] = 0, beta bit set, row queued.
+template <bool F32>
+__global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* voff,
+                               int32_t count, int32_t single) {
+  SsCtl* C = A.ctl;
+  if (C->done) return;
+  for (int j = threadIdx.x; j < count; j += blockDim.x) {
+    int64_t s = sources ? (int64_t)sources[j] : (int64_t)single;
+    if (voff) s += voff[j];
+    A.dist[s] = 0u;
+    const uint32_t bit = 1u << (s & 31);
+    const uint32_t old = atomicOr(&A.bm[0][s >> 5], bit);
+    if (old & bit) continue;  // duplicate seed
+    const int32_t start = A.rowptr[s], deg = A.rowptr[s + 1] - start;
+    if (deg == 0) continue;
+    if (deg <= A.t_lane) {
+      const uint32_t p = atomicAdd(&C->cnt[0][0], 1u);
+      A.qlane[0][p] = (int32_t)s;
+    } else if (deg <= A.t_wave) {
+      const uint32_t p = atomicAdd(&C->cnt[0][1], 1u);
+      A.qwave[0][p] = (int32_t)s;
+    } else {
+      const uint32_t nch = (deg + A.t_chunk - 1) / A.t_chunk;
+      const uint32_t p = atomicAdd(&C->cnt[0][2], nch);
+      for (uint32_t c = 0; c < nch; c++) {
+        const int32_t off = (int32_t)c * A.t_chunk;
+        if (p + c < A.cap_wg)
+          A.qwg[0][p + c] = make_int4((int32_t)s, start + off, min(A.t_chunk, deg - off), c == 0);
+      }
+    }
+  }
+}
+
+template <bool F32>
+__global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t conv = C->converged;
+  if (C->abort) conv = -2;
+  info->steps = (int32_t)C->step;
+  info->converged = conv;
+  info->frontier_entries = (int64_t)C->fe;
+  info->edges_scanned = (int64_t)C->es;
+  info->improvements = (int64_t)C->im;
+  info->union_rows = (int64_t)C->fe;
+  info->union_edges = (int64_t)C->es;
+}
+
+// ---------------------------------------------------------------------------
+// one step
+// ---------------------------------------------------------------------------
+
+// Record an improvement of alpha[v] (lanes with imp set): ptr flag, beta
+// bitmap, and for the first setter of v's bit, the next delta queue of v's
+// degree tier.  Reached by the whole wavefront.
+template <bool F32>
+__device__ __forceinline__ void ss_enqueue(const SsArgs& A, bool imp, int32_t v, int nxt, int rn,
+                                           Acc& acc) {
+  const unsigned long long b = __ballot(imp);
+  if (b == 0) return;
+  SsCtl* C = A.ctl;
+  if (lane_id() == __ffsll((long long)b) - 1) st_agent(&C->upd[rn], 1u);
+  bool newv = false;
+  if (imp) {
+    acc.im += 1;
+    const uint32_t bit = 1u << (v & 31);
+    const uint32_t old = atomicOr(&A.bm[nxt][v >> 5], bit);
+    newv = (old & bit) == 0;
+  }
+  int32_t start = 0, deg = 0;
+  if (newv) {
+    start = A.rowptr[v];
+    deg = A.rowptr[v + 1] - start;
+  }
+  const bool tl = newv && deg > 0 && deg <= A.t_lane;
+  const bool tw = newv && deg > A.t_lane && deg <= A.t_wave;
+  const bool tg = newv && deg > A.t_wave;
+  wave_push(tl, v, A.qlane[nxt], &C->cnt[rn][0], A.cap_v, &C->overflow);
+  wave_push(tw, v, A.qwave[nxt], &C->cnt[rn][1], A.cap_v, &C->overflow);
+  if (tg) {
+    const uint32_t nch = (uint32_t)((deg + A.t_chunk - 1) / A.t_chunk);
+    const uint32_t base = atomicAdd(&C->cnt[rn][2], nch);
+    for (uint32_t c = 0; c < nch; c++) {
+      const int32_t off = (int32_t)c * A.t_chunk;
+      if (base + c < A.cap_wg)
+        A.qwg[nxt][base + c] = make_int4(v, start + off, min(A.t_chunk, deg - off), c == 0);
+      else
+        atomicOr(&C->overflow, 1u);
+    }
+  }
+}
+
+// Relax edge e from a row whose distance is du.
+template <bool F32>
+__device__ __forceinline__ bool ss_relax(const SsArgs& A, bool valid, int32_t e, uint32_t du,
+                                         int32_t& v) {
+  bool imp = false;
+  v = 0;
+  if (valid) {
+    v = A.colidx[e];
+    const uint32_t cand = relax_add<F32>(du, A.w[e]);
+    if (cand < A.dist[v] && v != A.src) imp = cand < atomicMin(&A.dist[v], cand);
+  }
+  return imp;
+}
+
+template <bool F32>
+__device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
+                        int* lds) {
+  const int cur = step & 1, nxt = cur ^ 1;
+  const int rc = step % kRot, rn = (step + 1) % kRot;
+  SsCtl* C = A.ctl;
+  const uint32_t nl = ld_agent(&C->cnt[rc][0]);
+  const uint32_t nw = ld_agent(&C->cnt[rc][1]);
+  const uint32_t ng = ld_agent(&C->cnt[rc][2]);
+  const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const uint32_t gw = gb * W + wave, nwv = nb * W;
+
+  // workgroup tier: one chunk of one row per workgroup
+  for (uint32_t i = gb; i < ng; i += nb) {
+    const int4 r = A.qwg[cur][i];
+    const int32_t u = r.x, start = r.y, len = r.z;
+    const uint32_t du = ld_agent(&A.dist[u]);
+    if (threadIdx.x == 0) {
+      acc.es += (unsigned long long)len;
+      if (r.w) {
+        A.bm[cur][u >> 5] = 0u;
+        acc.fe += 1;
+      }
+    }
+    for (int32_t base = 0; base < len; base += (int32_t)blockDim.x) {
+      const int32_t k = base + (int32_t)threadIdx.x;
+      int32_t v;
+      const bool imp = ss_relax<F32>(A, k < len, start + k, du, v);
+      ss_enqueue<F32>(A, imp, v, nxt, rn, acc);
+    }
+  }
+
+  // wave tier: one wavefront per row
+  for (uint32_t i = gw; i < nw; i += nwv) {
+    const int32_t u = A.qwave[cur][i];
+    const int32_t start = A.rowptr[u], end = A.rowptr[u + 1];
+    const uint32_t du = ld_agent(&A.dist[u]);
+    if (lane == 0) {
+      A.bm[cur][u >> 5] = 0u;
+      acc.fe += 1;
+      acc.es += (unsigned long long)(end - start);
+    }
+    for (int32_t base = start; base < end; base += kWave) {
+      const int32_t e = base + lane;
+      int32_t v;
+      const bool imp = ss_relax<F32>(A, e < end, e, du, v);
+      ss_enqueue<F32>(A, imp, v, nxt, rn, acc);
+    }
+  }
+
+  // lane tier: 64 short rows per wavefront, edges dealt one per lane through an
+  // LDS prefix sum of the row lengths
+  int* l_incl = lds + wave * 3 * kWave;
+  int* l_base = l_incl + kWave;
+  int* l_du = l_base + kWave;
+  for (uint32_t bi = gw; (uint64_t)bi * kWave < nl; bi += nwv) {
+    const uint32_t i = bi * kWave + lane;
+    const bool has = i < nl;
+    int32_t u = 0, start = 0, deg = 0;
+    uint32_t du = 0;
+    if (has) {
+      u = A.qlane[cur][i];
+      start = A.rowptr[u];
+      deg = A.rowptr[u + 1] - start;
+      du = ld_agent(&A.dist[u]);
+      A.bm[cur][u >> 5] = 0u;
+      acc.fe += 1;
+      acc.es += (unsigned long long)deg;
+    }
+    const int incl = wave_incl_scan(deg);
+    const int total = __shfl(incl, kWave - 1, kWave);
+    l_incl[lane] = incl;
+    l_base[lane] = start - (incl - deg);
+    l_du[lane] = (int)du;
+    wave_lds_sync();
+    for (int base = 0; base < total; base += kWave) {
+      const int k = base + lane;
+      int owner = 0;  // first lane whose inclusive prefix exceeds k
+#pragma unroll
+      for (int s = 32; s >= 1; s >>= 1)
+        if (l_incl[owner + s - 1] <= k) owner += s;
+      int32_t v;
+      const bool imp = ss_relax<F32>(A, k < total, l_base[owner] + k, (uint32_t)l_du[owner], v);
+      ss_enqueue<F32>(A, imp, v, nxt, rn, acc);
+    }
+    wave_lds_sync();
+  }
+}
+
+__device__ __forceinline__ void ss_zero_rotation(SsCtl* C, uint32_t step) {
+  const int rz = (step + 2) % kRot;
+  C->cnt[rz][0] = 0u;
+  C->cnt[rz][1] = 0u;
+  C->cnt[rz][2] = 0u;
+  C->cnt[rz][3] = 0u;
+  C->upd[rz] = 0u;
+}
+
+// All steps in one cooperative launch.
+template <bool F32>
+__global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
+  __shared__ int lds[kMaxWavesPerBlock * 3 * kWave];
+  SsCtl* C = A.ctl;
+  if (ld_agent(&C->done)) return;
+  Acc acc;
+  uint32_t epoch = 0;
+  const uint32_t bar_base = ld_agent(&C->bar_base);
+  uint32_t step = ld_agent(&C->step);
+  int32_t status = 1;
+  for (;;) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
+    ss_step<F32>(A, step, blockIdx.x, gridDim.x, acc, lds);
+    if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
+      status = -2;
+      break;
+    }
+    const uint32_t upd = ld_agent(&C->upd[(step + 1) % kRot]);
+    step++;
+    if (!upd) { status = 1; break; }
+    if (step >= (uint32_t)A.n) { status = 0; break; }
+  }
+  flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    C->step = step;
+    C->converged = status;
+    C->done = 1;
+    C->bar_base = bar_base + epoch * gridDim.x;
+  }
+}
+
+// One step per launch; the last block to finish advances the step.
+template <bool F32>
+__global__ void __launch_bounds__(1024) ss_step_kernel(SsArgs A) {
+  __shared__ int lds[kMaxWavesPerBlock * 3 * kWave];
+  SsCtl* C = A.ctl;
+  if (C->done) return;
+  const uint32_t step = C->step;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
+  Acc acc;
+  ss_step<F32>(A, step, blockIdx.x, gridDim.x, acc, lds);
+  flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
+  if (last_block_done(&C->blocks_done)) {
+    C->blocks_done = 0;
+    const uint32_t upd = ld_agent(&C->upd[(step + 1) % kRot]);
+    const uint32_t ns = step + 1;
+    C->step = ns;
+    if (!upd) {
+      C->converged = 1;
+      C->done = 1;
+    } else if (ns >= (uint32_t)A.n) {
+      C->converged = 0;
+      C->done = 1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+SsLayout ss_layout(int64_t n, int64_t m) {
+  SsLayout L{};
+  Carver c;
+  L.cap_v = (uint32_t)n;
+  // at most m/65 rows exceed the smallest allowed t_wave (64), each cut into at
+  // most deg/256 + 1 chunks (smallest allowed t_chunk 256)
+  L.cap_wg = (uint32_t)(m / 65 + m / 256 + 2);
+  L.nwords = (n + 31) / 32;
+  L.ctl = c.take(sizeof(SsCtl));
+  for (int i = 0; i < 2; i++) L.qlane[i] = c.take((size_t)n * 4);
+  for (int i = 0; i < 2; i++) L.qwave[i] = c.take((size_t)n * 4);
+  for (int i = 0; i < 2; i++) L.qwg[i] = c.take((size_t)L.cap_wg * 16);
+  for (int i = 0; i < 2; i++) L.bm[i] = c.take((size_t)L.nwords * 4);
+  L.total = c.off;
+  return L;
+}
+
+template <typename K>
+static int persistent_grid(K kernel, int threads, int* per_cu_out = nullptr) {
+  const DevInfo& di = dev_info();
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  // Measured on MI355X: the occupancy query reports twice the workgroups per CU
+  // that are resident together (a 2048-workgroup grid of 256 threads never
+  // completed its first barrier; 1024 did), so a persistent grid takes half.
+  per_cu = std::max(1, per_cu / 2);
+  if (per_cu_out) *per_cu_out = per_cu;
+  return per_cu * di.cus;
+}
+
+void ss_persistent_occupancy(int threads, int* per_cu, int* grid) {
+  *grid = persistent_grid(ss_persistent_kernel<false>, threads, per_cu);
+}
+
+template <bool F32>
+static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_t* colidx,
+                            const SsSeeds& seeds, const SsLayout& L, dawn_run_info* info,
+                            hipStream_t stream, bool capture) {
+  const Tuning& T = tuning();
+  const DevInfo& di = dev_info();
+  const int threads = T.wg_threads;
+  const int fill_blocks = (int)std::min<int64_t>(4096, (A.n + 255) / 256 + 1);
+  hipLaunchKernelGGL(ss_fill_kernel<F32>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
+                     (int64_t)A.n, A.bm[0], A.bm[1], L.nwords, A.ctl);
+  if (T.validate) {
+    const int vb = (int)std::min<int64_t>(4096, ((int64_t)A.m + 255) / 256 + 1);
+    hipLaunchKernelGGL(ss_validate_kernel, dim3(vb), dim3(256), 0, stream, rowptr, colidx, A.w,
+                       A.n, A.m, (int32_t)F32, &A.ctl->done, &A.ctl->converged);
+  }
+  hipLaunchKernelGGL(ss_seed_kernel<F32>, dim3(1), dim3(256), 0, stream, A, seeds.sources_dev,
+                     seeds.voff_dev, seeds.count, seeds.source);
+  dawn_status st = hip_check(hipGetLastError(), "init launch");
+  if (st != DAWN_OK) return st;
+
+  int mode = T.mode;
+  if (mode == 0) mode = 2;
+  if (mode == 2) {
+    int grid = persistent_grid(ss_persistent_kernel<F32>, threads);
+    if (T.grid > 0 && T.grid < grid) grid = T.grid;
+    SsArgs a = A;
+    void* args[] = {&a};
+    hipError_t e;
+    void* tk = capture ? nullptr : ktimer_begin(stream);
+    if (!capture && di.coop) {
+      e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&ss_persistent_kernel<F32>),
+                                     dim3(grid), dim3(threads), args, 0, stream);
+    } else {
+      hipLaunchKernelGGL(ss_persistent_kernel<F32>, dim3(grid), dim3(threads), 0, stream, a);
+      e = hipGetLastError();
+    }
+    ktimer_end(tk, stream, 1);
+    st = hip_check(e, "persistent launch");
+    if (st != DAWN_OK) return st;
+  } else {
+    if (capture) return set_error(DAWN_E_UNSUPPORTED, "step launches cannot be captured");
+    const int grid = T.grid > 0 ? T.grid : 4 * di.cus;
+    uint32_t* h_done = nullptr;
+    if (hipHostMalloc((void**)&h_done, 4, hipHostMallocDefault) != hipSuccess)
+      return set_error(DAWN_E_HIP, "hipHostMalloc failed");
+    *h_done = 0;
+    int64_t launched = 0;
+    const int64_t cap = (int64_t)A.n + 1;
+    while (launched < cap) {
+      const int chunk = (int)std::min<int64_t>(T.host_check, cap - launched);
+      void* tk = ktimer_begin(stream);
+      for (int s = 0; s < chunk; s++)
+        hipLaunchKernelGGL(ss_step_kernel<F32>, dim3(grid), dim3(threads), 0, stream, A);
+      ktimer_end(tk, stream, chunk);
+      launched += chunk;
+      hipMemcpyAsync(h_done, &A.ctl->done, 4, hipMemcpyDeviceToHost, stream);
+      if (hipStreamSynchronize(stream) != hipSuccess) break;
+      if (*h_done) break;
+    }
+    hipHostFree(h_done);
+    st = hip_check(hipGetLastError(), "step launches");
+    if (st != DAWN_OK) return st;
+  }
+  if (info) {
+    hipLaunchKernelGGL(ss_finalize_kernel<F32>, dim3(1), dim3(64), 0, stream, A.ctl, info);
+    st = hip_check(hipGetLastError(), "finalize launch");
+  }
+  return st;
+}
+
+dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, bool f32,
+                   int32_t n, int32_t m, const SsSeeds& seeds, bool guard_source, void* dist,
+                   void* ws, dawn_run_info* info, hipStream_t stream, bool capture) {
+  const Tuning& T = tuning();
+  const SsLayout L = ss_layout(n, m);
+  char* base = static_cast<char*>(ws);
+  SsArgs A{};
+  A.rowptr = rowptr;
+  A.colidx = colidx;
+  A.w = static_cast<const uint32_t*>(w);
+  A.dist = static_cast<uint32_t*>(dist);
+  A.n = n;
+  A.m = m;
+  A.src = guard_source ? seeds.source : -1;
+  A.t_lane = T.t_lane;
+  A.t_wave = T.t_wave;
+  A.t_chunk = T.t_chunk;
+  for (int i = 0; i < 2; i++) {
+    A.qlane[i] = reinterpret_cast<int32_t*>(base + L.qlane[i]);
+    A.qwave[i] = reinterpret_cast<int32_t*>(base + L.qwave[i]);
+    A.qwg[i] = reinterpret_cast<int4*>(base + L.qwg[i]);
+    A.bm[i] = reinterpret_cast<uint32_t*>(base + L.bm[i]);
+  }
+  A.cap_v = L.cap_v;
+  A.cap_wg = L.cap_wg;
+  A.ctl = reinterpret_cast<SsCtl*>(base + L.ctl);
+  if (f32) return ss_run_t<true>(A, rowptr, colidx, seeds, L, info, stream, capture);
+  return ss_run_t<false>(A, rowptr, colidx, seeds, L, info, stream, capture);
+}
+
+}  // namespace dawn

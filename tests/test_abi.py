@@ -1,0 +1,95 @@
+"""The C ABI: the library loads and exports every entry point include/dawn.h
+declares; host-side argument checks work without a GPU (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2306_07872_amd as dawn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dawn.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(dawn_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(dawn.LIB_PATH):
+        from paper_2306_07872_amd import build
+        build.build()
+    return dawn.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(dawn.exported_symbols()) == set(names)
+
+
+def test_status_strings_and_build_info(lib):
+    assert lib.dawn_status_str(0) == b"ok"
+    assert lib.dawn_status_str(3) == b"workspace too small"
+    assert b"gfx950" in lib.dawn_build_info()
+
+
+def test_tuning_roundtrip_and_range_checks(lib):
+    t0 = dawn.get_tuning()
+    assert t0["t_lane"] == 16 and t0["tile_k"] == 256
+    prev = dawn.set_tuning(t_lane=8, tile_k=128)
+    assert dawn.get_tuning()["t_lane"] == 8
+    for bad in (dict(t_lane=0), dict(t_wave=10), dict(wg_threads=300), dict(tile_k=100),
+                dict(tile_k=1024), dict(mode=3), dict(t_chunk=8), dict(tile_t_wave=4)):
+        with pytest.raises(dawn.DawnError) as e:
+            dawn.set_tuning(**bad)
+        assert e.value.status == 1
+    dawn.set_tuning(**prev)
+    dawn.set_tuning(reset=True)
+    assert dawn.get_tuning() == t0
+
+
+def test_host_side_validation_needs_no_gpu(lib):
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    # n < 1
+    assert lib.dawn_sssp(fake, fake, fake, 0, 0, 0, 0, fake, null) == 1
+    # m < 0
+    assert lib.dawn_sssp(fake, fake, fake, 0, 5, -1, 0, fake, null) == 1
+    # source out of range
+    assert lib.dawn_sssp(fake, fake, fake, 0, 5, 3, 5, fake, null) == 1
+    assert lib.dawn_sssp(fake, fake, fake, 0, 5, 3, -1, fake, null) == 1
+    # bad weight type
+    assert lib.dawn_sssp(fake, fake, fake, 7, 5, 3, 0, fake, null) == 1
+    # null pointers
+    assert lib.dawn_sssp(null, fake, fake, 0, 5, 3, 0, fake, null) == 1
+    assert lib.dawn_sssp(fake, null, fake, 0, 5, 3, 0, fake, null) == 1
+    assert lib.dawn_sssp(fake, fake, fake, 0, 5, 3, 0, null, null) == 1
+    # k < 1
+    assert lib.dawn_msssp(fake, fake, fake, 0, 5, 3, fake, 0, fake, null) == 1
+    # workspace too small / misaligned
+    need = lib.dawn_sssp_workspace_bytes(100, 1000)
+    assert need > 0
+    assert lib.dawn_sssp_ws(fake, fake, fake, 0, 100, 1000, 0, fake, ctypes.c_void_p(0x100000),
+                            need - 1, null, null) == 3
+    assert lib.dawn_sssp_ws(fake, fake, fake, 0, 100, 1000, 0, fake, ctypes.c_void_p(0x100010),
+                            need, null, null) == 1
+    assert b"aligned" in lib.dawn_last_error()
+    assert lib.dawn_tile_bytes(100, 1000, 513) == 0
+    assert lib.dawn_tile_bytes(100, 1000, 64) > 400 * 64
+
+
+def test_workspace_sizes_grow_with_graph(lib):
+    a = lib.dawn_sssp_workspace_bytes(1000, 8000)
+    b = lib.dawn_sssp_workspace_bytes(4194304, 67108864)
+    assert 0 < a < b
+    # tile: the [n x K] distance tile dominates
+    t = lib.dawn_msssp_workspace_bytes(1 << 20, 16 << 20, 256)
+    assert t >= (1 << 20) * 256 * 4

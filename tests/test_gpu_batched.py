@@ -1,0 +1,271 @@
+"""GPU parity of the batched paths: multi-source tiles, all pairs, the
+many-graph launch, and tile sessions."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from graphgen import workloads
+from gpu_helpers import announce, assert_sssp_matches, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _msssp(dawn, g, sources, **tune):
+    import torch
+    prev = dawn.set_tuning(**tune) if tune else None
+    try:
+        csr = dawn.Csr.from_graph(g)
+        info = dawn.info_tensor()
+        out = dawn.msssp(csr, sources, info=info)
+        torch.cuda.synchronize()
+        return to_np(out), dawn.read_info(info)
+    finally:
+        if prev is not None:
+            dawn.set_tuning(**prev)
+
+
+@pytest.mark.parametrize("wk", ["u32", "f32lognormal"])
+@pytest.mark.parametrize("k", [1, 37, 64, 130])
+def test_msssp_columns_match_oracle(dawn, wk, k):
+    g = graphgen.rmat(13, 16, 3, weights=wk)
+    srcs = graphgen.pick_sources(g, k, 11)
+    announce("msssp", wk, "k", k)
+    D, info = _msssp(dawn, g, srcs)
+    assert D.shape == (k, g.n)
+    for j in range(0, k, max(1, k // 6)):
+        assert_sssp_matches(g, int(srcs[j]), D[j], tag=f"msssp k={k} col {j}")
+    assert info["converged"] == 1
+
+
+TILE_TUNINGS = [
+    dict(),
+    dict(tile_k=64, tile_t_wave=32, tile_t_chunk=64),
+    dict(tile_k=128, tile_t_wave=65536, wg_threads=1024),
+    dict(tile_k=512, tile_t_wave=40, tile_t_chunk=100, wg_threads=512, grid=5),
+    dict(mode=1, host_check=3, tile_t_wave=32, tile_t_chunk=64),
+]
+
+
+@pytest.mark.parametrize("ti", range(len(TILE_TUNINGS)))
+def test_msssp_tuning_invariance_and_sssp_identity(dawn, ti):
+    """Column j of a tile equals a lone single-source run from sources[j]
+    bit for bit, whatever the tile width, tiers or launch geometry."""
+    import torch
+    g = graphgen.rmat(14, 16, 9, weights="u32")
+    srcs = graphgen.pick_sources(g, 150, ti)
+    srcs = np.concatenate([srcs, srcs[:3]])  # duplicate sources are allowed
+    announce("msssp tuning", TILE_TUNINGS[ti])
+    D, info = _msssp(dawn, g, srcs, **TILE_TUNINGS[ti])
+    csr = dawn.Csr.from_graph(g)
+    for j in (0, 1, 77, 149, 150, 152):
+        lone = to_np(dawn.sssp(csr, int(srcs[j])))
+        torch.cuda.synchronize()
+        assert np.array_equal(D[j].view(np.uint32), lone.view(np.uint32))
+    ref, _ = oracle.sssp(g, int(srcs[5]), "u32")
+    assert np.array_equal(D[5].view(np.uint32), ref)
+
+
+def test_msssp_grid_f32(dawn):
+    g = graphgen.grid(64, 48, 0.01, 3, weights="f32unit")
+    srcs = graphgen.pick_sources(g, 70, 1)
+    announce("msssp grid f32")
+    D, info = _msssp(dawn, g, srcs)
+    for j in (0, 33, 69):
+        assert_sssp_matches(g, int(srcs[j]), D[j], tag=f"grid col {j}")
+
+
+def test_msssp_unit_weight_counters(dawn):
+    """Unit weights: per-source counters are the sums of the per-source exact
+    values (mu = 1 for every source)."""
+    g = graphgen.rmat(12, 8, 4, weights="u32one")
+    srcs = graphgen.pick_sources(g, 40, 2)
+    D, info = _msssp(dawn, g, srcs)
+    exp_edges = sum(oracle.m_reach(g, int(s)) for s in srcs)
+    exp_impr = sum(int((oracle.bfs(g, int(s)) >= 0).sum()) - 1 for s in srcs)
+    exp_steps = max(int(oracle.bfs(g, int(s)).max()) + 1 for s in srcs)
+    assert info["edges_scanned"] == exp_edges
+    assert info["improvements"] == exp_impr
+    assert info["steps"] == exp_steps
+    assert info["union_edges"] <= info["edges_scanned"]
+
+
+def test_apsp_er_small_equals_floyd_warshall(dawn):
+    import torch
+    g, _ = workloads.er_small()
+    csr = dawn.Csr.from_graph(g)
+    announce("apsp er_small")
+    A = to_np(dawn.apsp(csr))
+    torch.cuda.synchronize()
+    F = oracle.fw(g)
+    exp = np.where(F == np.iinfo(np.uint64).max, 0xFFFFFFFF, F).astype(np.uint32)
+    assert np.array_equal(A.view(np.uint32), exp)
+    assert np.all(np.diag(A) == 0)
+
+
+def test_apsp_f32_small(dawn):
+    import torch
+    g = graphgen.er(300, 1500, 8, weights="f32lognormal")
+    csr = dawn.Csr.from_graph(g)
+    A = to_np(dawn.apsp(csr))
+    torch.cuda.synchronize()
+    for s in (0, 150, 299):
+        assert_sssp_matches(g, s, A[s], tag=f"apsp row {s}")
+
+
+def _batch_graphs(count=9, seed=7):
+    return workloads.er_batch(seed=seed, count=count, lo=2.0, hi=3.7)
+
+
+def test_batch_union_matches_each_graph(dawn):
+    import torch
+    gs = _batch_graphs()
+    csrs = [dawn.Csr.from_graph(g) for g, _ in gs]
+    b = dawn.Batch(csrs)
+    srcs = torch.tensor([s for _, s in gs], dtype=torch.int32, device="cuda")
+    info = dawn.info_tensor()
+    announce("batch", len(gs), "graphs, total_n", b.total_n)
+    out = b.run(srcs, info=info)
+    torch.cuda.synchronize()
+    parts = b.split(out)
+    for (g, s), d in zip(gs, parts):
+        assert_sssp_matches(g, s, to_np(d), tag=f"batch {g.name}")
+    assert dawn.read_info(info)["converged"] == 1
+    b.close()
+
+
+def test_batch_graph_capture_replay(dawn):
+    """Captured once, replayed with new sources written into the same buffer;
+    every replay (with eager work in between) matches a fresh eager run."""
+    import torch
+    gs = _batch_graphs(count=6, seed=9)
+    csrs = [dawn.Csr.from_graph(g) for g, _ in gs]
+    b = dawn.Batch(csrs)
+    srcs = torch.tensor([s for _, s in gs], dtype=torch.int32, device="cuda")
+    out = torch.empty(b.total_n, dtype=torch.float32, device="cuda")
+    info = dawn.info_tensor()
+    announce("batch capture")
+    b.capture(srcs, out, info=info)
+    rng = np.random.default_rng(1)
+    for rep in range(4):
+        new = [int(graphgen.pick_sources(g, 1, 100 + rep * 10 + i)[0]) for i, (g, _) in enumerate(gs)]
+        srcs.copy_(torch.tensor(new, dtype=torch.int32))
+        b.replay()
+        torch.cuda.synchronize()
+        eager = b.run(srcs.clone())
+        junk = torch.randn(1000, device="cuda").sum()   # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(to_np(out).view(np.uint32), to_np(eager).view(np.uint32))
+        for (g, _), s, d in zip(gs, new, b.split(out)):
+            assert_sssp_matches(g, s, to_np(d), tag=f"replay {rep}", check_invariants=False)
+        del junk, rng
+        rng = None
+    b.close()
+
+
+def test_batch_rejects_mixed_weight_types(dawn):
+    g1 = graphgen.er(100, 400, 1, weights="u32")
+    g2 = graphgen.er(100, 400, 2, weights="f32lognormal")
+    with pytest.raises(dawn.DawnError):
+        dawn.Batch([dawn.Csr.from_graph(g1), dawn.Csr.from_graph(g2)])
+
+
+def _drain(dawn, tile, steps=4, limit=100000):
+    import torch
+    for _ in range(limit):
+        done = tile.run(steps)
+        torch.cuda.synchronize()
+        if tile_all_done(dawn, tile, done):
+            return
+    raise AssertionError("tile did not finish")
+
+
+def tile_all_done(dawn, tile, done):
+    live = getattr(tile, "_live", set())
+    cols = set(dawn.done_columns(done.cpu().numpy(), tile.k))
+    return live <= cols
+
+
+@pytest.mark.parametrize("wk", ["u32", "f32lognormal"])
+def test_tile_session_mix_equals_alone(dawn, wk):
+    """Queries admitted at different times into a shared tile give exactly
+    the distances of the same query run alone."""
+    import torch
+    g = graphgen.rmat(13, 16, 12, weights=wk)
+    csr = dawn.Csr.from_graph(g)
+    srcs = graphgen.pick_sources(g, 12, 5)
+    tile = dawn.Tile(csr, 8)
+    tile._live = set()
+    results = {}
+    pending = list(enumerate(srcs))
+    free = list(range(8))
+    inflight = {}
+    announce("tile session", wk)
+    step = 0
+    while pending or inflight:
+        while pending and free and (step % 3 == 0 or not inflight):
+            qi, s = pending.pop(0)
+            col = free.pop(0)
+            tile.admit(col, int(s))
+            tile._live.add(col)
+            inflight[col] = (qi, int(s))
+        done = tile.run(2)
+        torch.cuda.synchronize()
+        for col in dawn.done_columns(done.cpu().numpy(), tile.k):
+            if col in inflight:
+                qi, s = inflight.pop(col)
+                results[qi] = to_np(tile.read(col))
+                tile._live.discard(col)
+                free.append(col)
+        step += 1
+        assert step < 100000
+    torch.cuda.synchronize()
+    for qi, s in enumerate(srcs):
+        alone = to_np(dawn.sssp(csr, int(s)))
+        torch.cuda.synchronize()
+        assert np.array_equal(results[qi].view(np.uint32), alone.view(np.uint32)), qi
+        assert_sssp_matches(g, int(s), results[qi], tag=f"tile q{qi}", check_invariants=False)
+    tile.close()
+
+
+def test_tile_evict_and_reuse(dawn):
+    import torch
+    g = graphgen.grid(40, 40, 0.0, 1, weights="f32unit")
+    csr = dawn.Csr.from_graph(g)
+    tile = dawn.Tile(csr, 64)
+    tile._live = {0, 1}
+    tile.admit(0, 0)
+    tile.admit(1, 1599)
+    tile.run(5)
+    tile.evict(1)           # cancel a running query
+    tile._live = {0}
+    _drain(dawn, tile)
+    tile.admit(1, 820)      # reuse the freed column
+    tile._live = {0, 1}
+    _drain(dawn, tile)
+    torch.cuda.synchronize()
+    for col, s in ((0, 0), (1, 820)):
+        assert_sssp_matches(g, s, to_np(tile.read(col)), tag=f"evict col {col}")
+    steps = tile.steps().cpu().numpy()
+    assert steps[0] > 40 and steps[1] > 20
+    tile.close()
+
+
+@pytest.mark.slow
+def test_full_size_tile_rmat20_sampled(dawn):
+    """R-MAT scale 20, k = 256, launched as the benchmark launches it: sampled
+    columns against Dijkstra element by element, invariants on more."""
+    import torch
+    g, srcs = workloads.rmat20_tile()
+    csr = dawn.Csr.from_graph(g)
+    announce("rmat20 tile k=256 full")
+    info = dawn.info_tensor()
+    D = dawn.msssp(csr, srcs, info=info)
+    torch.cuda.synchronize()
+    inf = dawn.read_info(info)
+    assert inf["converged"] == 1
+    for j in (0, 255):
+        assert_sssp_matches(g, int(srcs[j]), to_np(D[j]), tag=f"rmat20 col {j}")
+    for j in (17, 128):
+        rc, v = oracle.check(g, int(srcs[j]), to_np(D[j]))
+        assert rc == 0, f"col {j}: invariant V{rc} at {v}"
