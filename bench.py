@@ -67,6 +67,11 @@ def main() -> int:
     ap.add_argument("--plain", type=int, default=256, help="sources timed one per launch")
     ap.add_argument("--cpu-sample", type=int, default=32, help="sources timed on the oracle")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
+                    help="library tuning field (see dawn_tuning), repeatable")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device-to-device copy of this many MiB (a kernel "
+                         "of known traffic, to scale profiler byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -82,6 +87,16 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     dawn.load()
+    if args.tune:
+        dawn.set_tuning(**{k: int(v) for k, v in (t.split("=", 1) for t in args.tune)})
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(nel, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
+        del a, b
     t_gen = time.perf_counter()
     g, srcs = workloads.rmat20_tile(k=args.k, scale=args.scale)
     log(f"graph {g.name}: n={g.n} m={g.m} k={len(srcs)} ({time.perf_counter() - t_gen:.1f}s)")
@@ -119,32 +134,39 @@ def main() -> int:
 
     # ---- plain single-source on the same sources ------------------------------
     nplain = min(args.plain, k)
-    out1 = torch.empty(g.n, dtype=torch.uint32, device="cuda")
-    ws1 = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
-    for s in srcs[:3]:
-        dawn.sssp(csr, int(s), out=out1, ws=ws1)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for s in srcs[:nplain]:
-        dawn.sssp(csr, int(s), out=out1, ws=ws1)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    plain_s = (t3 - t2) / nplain
-    plain_gteps = float(sum(reach[:nplain])) / (t3 - t2) / 1e9
-    log(f"plain: {plain_s * 1e3:.3f} ms/source ({nplain} sources)")
+    plain_s, plain_gteps = float("nan"), float("nan")
+    if nplain > 0:
+        out1 = torch.empty(g.n, dtype=torch.uint32, device="cuda")
+        ws1 = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
+        for s in srcs[:3]:
+            dawn.sssp(csr, int(s), out=out1, ws=ws1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for s in srcs[:nplain]:
+            dawn.sssp(csr, int(s), out=out1, ws=ws1)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        plain_s = (t3 - t2) / nplain
+        plain_gteps = float(sum(reach[:nplain])) / (t3 - t2) / 1e9
+        log(f"plain: {plain_s * 1e3:.3f} ms/source ({nplain} sources)")
 
     # ---- roofline of the dominant kernel -------------------------------------
+    # The tile's GOVM step kernel: every launch the kernel timer recorded during
+    # the K timed calls (events on the launch stream).  Algorithmic bytes come
+    # from the device counters of the last call; every call does the same work
+    # up to the order of updates inside a step.
     nseg = (min(k, tune["tile_k"]) + 63) // 64
-    kbytes = tile_kernel_bytes(inf, nseg)
+    kbytes_call = tile_kernel_bytes(inf, nseg)
     avg_kms = k_ms / max(k_launches, 1)
-    # each timed step launches the tile kernel once per tile of tile_k sources
-    tiles = (k + tune["tile_k"] - 1) // tune["tile_k"]
-    per_launch_bytes = kbytes / tiles
+    per_launch_bytes = kbytes_call * args.steps / max(k_launches, 1)
     achieved = per_launch_bytes / (avg_kms * 1e-3) / 1e9
+    kname = "tile_step_kernel<false>" if tune["mode"] in (0, 1) else "tile_persistent_kernel<false>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "tile_persistent_kernel<false>",
-                "kernel_ms": round(avg_kms, 4), "algorithmic_bytes": int(per_launch_bytes)}
+                "kernel": kname, "kernel_ms": round(avg_kms, 5),
+                "launches_per_step": round(k_launches / args.steps, 2),
+                "algorithmic_bytes": int(per_launch_bytes),
+                "algorithmic_bytes_per_call": int(kbytes_call)}
 
     # ---- CPU oracle on a bounded sample ---------------------------------------
     cpu = None
@@ -178,9 +200,9 @@ def main() -> int:
         "config": {"workload": f"rmat{args.scale}_ef16_u32_k{k}", "n": g.n, "m": g.m, "k": k,
                    "weights": "uint32 uniform [1,255]", "sources": "uniform among out-degree>=1"},
         "sources_per_s": round(srcs_per_s, 1),
-        "plain_sources_per_s": round(1.0 / plain_s, 1),
-        "plain_gteps": round(plain_gteps, 3),
-        "batched_vs_plain_sources_per_s": round(srcs_per_s * plain_s, 2),
+        "plain_sources_per_s": round(1.0 / plain_s, 1) if nplain else None,
+        "plain_gteps": round(plain_gteps, 3) if nplain else None,
+        "batched_vs_plain_sources_per_s": round(srcs_per_s * plain_s, 2) if nplain else None,
         "steps_max": inf["steps"],
         "mu_e": round(inf["edges_scanned"] / max(work, 1.0), 4),
         "roofline": roofline,

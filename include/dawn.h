@@ -98,23 +98,33 @@ typedef struct {
  *   wave tier      d <= t_wave   one wavefront per row (t_wave >= 64);
  *   workgroup tier d >  t_wave   the row is cut into chunks of t_chunk edges,
  *                                one workgroup per chunk.
- * mode: 0 auto, 1 step launches (one kernel per step, host checks termination
- * every `host_check` steps), 2 one persistent cooperative launch for all steps.
- * wg_threads: 256, 512 or 1024.  grid: workgroups per launch, 0 = auto.
+ * mode: 0 auto (single source and batches of graphs: 2; tiles: 1), 1 step
+ * launches (one kernel per step; the host checks termination every
+ * `host_check` steps, so such a call waits for its stream), 2 one persistent
+ * launch for all steps with a grid
+ * barrier between steps (the barrier gives up after a few seconds, so a grid
+ * that cannot be co-resident ends with converged = -2 instead of hanging).
+ * wg_threads: 256, 512 or 1024, or 0 = auto (single source 1024, tiles 256).
+ * grid: workgroups per launch, 0 = auto (persistent: what the device holds at
+ * once; tile step launches: 16 per compute unit; single-source step launches:
+ * 4 per compute unit).
  * tile_k: sources per tile for dawn_msssp / dawn_apsp, a multiple of 64,
  * at most DAWN_TILE_K_MAX. */
 typedef struct {
   int32_t t_lane;     /* 1..64, default 16 */
   int32_t t_wave;     /* max(64,t_lane)..65536, default 2048 */
   int32_t t_chunk;    /* 256..1<<20, default 8192 */
-  int32_t wg_threads; /* default 256 */
+  int32_t wg_threads; /* default 0 (auto) */
   int32_t grid;       /* default 0 (auto) */
   int32_t mode;       /* default 0 (auto) */
   int32_t host_check; /* 1..4096, default 32 */
   int32_t tile_k;     /* default 256 */
-  int32_t tile_t_wave;  /* workgroup-tier threshold of the tile kernel, 32..65536, default 256 */
-  int32_t tile_t_chunk; /* edges per workgroup chunk in the tile kernel, 64..65536, default 512 */
+  int32_t tile_t_wave;  /* workgroup-tier threshold of the tile kernel, 32..65536, default 64 */
+  int32_t tile_t_chunk; /* edges per workgroup chunk in the tile kernel, 64..65536, default 256 */
   int32_t validate;     /* 1 = check the CSR on the device before running */
+  int32_t coop;         /* 1 = launch persistent kernels with hipLaunchCooperativeKernel;
+                           0 (default) = an ordinary launch of a grid sized to what the
+                           device holds at once (half the occupancy query's figure) */
 } dawn_tuning;
 
 #define DAWN_TILE_K_MAX 512

@@ -59,11 +59,12 @@ const DevInfo& dev_info() {
 static bool tuning_ok(const Tuning& t) {
   return t.t_lane >= 1 && t.t_lane <= 64 && t.t_wave >= std::max(64, t.t_lane) &&
          t.t_wave <= 65536 && t.t_chunk >= 256 && t.t_chunk <= (1 << 20) &&
-         (t.wg_threads == 256 || t.wg_threads == 512 || t.wg_threads == 1024) && t.grid >= 0 &&
+         (t.wg_threads == 0 || t.wg_threads == 256 || t.wg_threads == 512 || t.wg_threads == 1024) && t.grid >= 0 &&
          t.grid <= (1 << 20) && t.mode >= 0 && t.mode <= 2 && t.host_check >= 1 &&
          t.host_check <= 4096 && t.tile_k >= 64 && t.tile_k <= DAWN_TILE_K_MAX &&
          t.tile_k % 64 == 0 && t.tile_t_wave >= 32 && t.tile_t_wave <= 65536 &&
-         t.tile_t_chunk >= 64 && t.tile_t_chunk <= 65536 && (t.validate == 0 || t.validate == 1);
+         t.tile_t_chunk >= 64 && t.tile_t_chunk <= 65536 && (t.validate == 0 || t.validate == 1) &&
+         (t.coop == 0 || t.coop == 1);
 }
 
 static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
@@ -191,7 +192,7 @@ extern "C" dawn_status dawn_device_query(int32_t* out) {
   out[3] = pc;
   out[5] = g;
   out[6] = di.device;
-  out[7] = g_tuning.wg_threads;
+  out[7] = g_tuning.wg_threads;  /* 0 = auto */
   return DAWN_OK;
 }
 
@@ -213,6 +214,7 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->tile_t_wave = t.tile_t_wave;
   out->tile_t_chunk = t.tile_t_chunk;
   out->validate = t.validate;
+  out->coop = t.coop;
   return DAWN_OK;
 }
 
@@ -230,6 +232,7 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.tile_t_wave = in->tile_t_wave;
     t.tile_t_chunk = in->tile_t_chunk;
     t.validate = in->validate;
+    t.coop = in->coop;
   }
   if (!tuning_ok(t)) return set_error(DAWN_E_INVALID, "tuning out of range");
   g_tuning = t;
@@ -312,14 +315,12 @@ static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, cons
   const int32_t kt = std::min(k, g_tuning.tile_k);
   const TileLayout L = tile_layout(n, m, kt);
   const TileArgs A = tile_args(rowptr, colidx, weights, n, m, L, ws);
-  dawn_run_info* part = nullptr;
-  StreamScratch tmp(stream);
+  // per-tile summary, inside the workspace (no allocation on this path)
+  dawn_run_info* part = reinterpret_cast<dawn_run_info*>(static_cast<char*>(ws) + L.info);
   dawn_status st;
-  if (info) {
-    if ((st = tmp.alloc(sizeof(dawn_run_info))) != DAWN_OK) return st;
-    part = static_cast<dawn_run_info*>(tmp.p);
-  }
-  const int mode = g_tuning.mode == 0 ? 2 : g_tuning.mode;
+  // auto: step launches (a tile step has plenty of work to fill the device
+  // at full occupancy, and R-MAT-like graphs take few steps)
+  const int mode = g_tuning.mode == 0 ? 1 : g_tuning.mode;
   for (int32_t j0 = 0; j0 < k; j0 += kt) {
     const int32_t cnt = std::min(kt, k - j0);
     if ((st = tile_reset(A, f32, stream)) != DAWN_OK) return st;

@@ -14,14 +14,15 @@ struct Tuning {
   int32_t t_lane = 16;
   int32_t t_wave = 2048;
   int32_t t_chunk = 8192;
-  int32_t wg_threads = 256;
+  int32_t wg_threads = 0;
   int32_t grid = 0;
   int32_t mode = 0;
   int32_t host_check = 32;
   int32_t tile_k = 256;
-  int32_t tile_t_wave = 256;
-  int32_t tile_t_chunk = 512;
+  int32_t tile_t_wave = 64;
+  int32_t tile_t_chunk = 256;
   int32_t validate = 0;
+  int32_t coop = 0;
 };
 
 Tuning& tuning();
@@ -68,7 +69,7 @@ dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, 
 
 // ----- distance tile ---------------------------------------------------------
 struct TileLayout {
-  size_t ctl, D, mk[3], qwave[3], qwg[3], ubm[2], total;
+  size_t ctl, info, D, mk[3], qwave[3], qwg[3], ubm[2], total;
   uint32_t cap_v, cap_wg;
   int64_t nwords;
   int32_t K, nseg;

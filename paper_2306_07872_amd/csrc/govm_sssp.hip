@@ -122,71 +122,136 @@ __global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info) {
 // one step
 // ---------------------------------------------------------------------------
 
-// Record an improvement of alpha[v] (lanes with imp set): ptr flag, beta
-// bitmap, and for the first setter of v's bit, the next delta queue of v's
-// degree tier.  Reached by the whole wavefront.
-template <bool F32>
-__device__ __forceinline__ void ss_enqueue(const SsArgs& A, bool imp, int32_t v, int nxt, int rn,
-                                           Acc& acc) {
-  const unsigned long long b = __ballot(imp);
+// Next-frontier entries found by a workgroup are gathered in LDS and written
+// to the global queues once at the end of the step with one atomicAdd per
+// tier per workgroup (a queue that fills up spills straight to global memory).
+constexpr int kLdsQLane = 1536;
+constexpr int kLdsQWave = 512;
+constexpr int kUnroll = 4;      // edges in flight per lane (wave and workgroup tiers)
+constexpr int kUnrollLane = 2;  // edges in flight per lane (lane tier)
+
+struct SsShared {
+  int stage[kMaxWavesPerBlock * 3 * kWave];  // lane-tier batch: prefix, row base, distance
+  int32_t ql[kLdsQLane];
+  int32_t qw[kLdsQWave];
+  uint32_t nql, nqw, upd, gbase_l, gbase_w;
+};
+
+// Push `v` for lanes with `pred` into the workgroup's LDS queue; lanes past
+// its capacity go to the global queue.  Reached by the whole wavefront.
+__device__ __forceinline__ void block_push(bool pred, int32_t v, int32_t* sq, uint32_t* sn,
+                                           uint32_t lcap, int32_t* gq, uint32_t* gcnt,
+                                           uint32_t gcap, uint32_t* overflow) {
+  const unsigned long long b = __ballot(pred);
   if (b == 0) return;
+  const int leader = __ffsll((long long)b) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(sn, (uint32_t)__popcll(b));
+  base = __shfl(base, leader, kWave);
+  const uint32_t pos = base + lanes_below(b);
+  const bool spill = pred && pos >= lcap;
+  if (pred && !spill) sq[pos] = v;
+  wave_push(spill, v, gq, gcnt, gcap, overflow);
+}
+
+// Record improvements of alpha[v[i]] (lanes with imp[i]): the ptr flag, the
+// beta bitmap, and for the first setter of a bit, the next-step queue of v's
+// degree tier.  Reached by the whole wavefront.
+template <int U>
+__device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U],
+                                           const int32_t (&v)[U], int nxt, int rn, Acc& acc,
+                                           SsShared& sh) {
+  bool any = false;
+#pragma unroll
+  for (int i = 0; i < U; i++) any |= imp[i];
+  if (__ballot(any) == 0) return;
   SsCtl* C = A.ctl;
-  if (lane_id() == __ffsll((long long)b) - 1) st_agent(&C->upd[rn], 1u);
-  bool newv = false;
-  if (imp) {
-    acc.im += 1;
-    const uint32_t bit = 1u << (v & 31);
-    const uint32_t old = atomicOr(&A.bm[nxt][v >> 5], bit);
-    newv = (old & bit) == 0;
+  if (any) sh.upd = 1u;
+  bool newv[U];
+#pragma unroll
+  for (int i = 0; i < U; i++) {
+    newv[i] = false;
+    if (imp[i]) {
+      acc.im += 1;
+      const uint32_t bit = 1u << (v[i] & 31);
+      newv[i] = (atomicOr(&A.bm[nxt][v[i] >> 5], bit) & bit) == 0u;
+    }
   }
-  int32_t start = 0, deg = 0;
-  if (newv) {
-    start = A.rowptr[v];
-    deg = A.rowptr[v + 1] - start;
+  int32_t start[U], deg[U];
+#pragma unroll
+  for (int i = 0; i < U; i++) {
+    start[i] = 0;
+    deg[i] = 0;
+    if (newv[i]) {
+      start[i] = A.rowptr[v[i]];
+      deg[i] = A.rowptr[v[i] + 1] - start[i];
+    }
   }
-  const bool tl = newv && deg > 0 && deg <= A.t_lane;
-  const bool tw = newv && deg > A.t_lane && deg <= A.t_wave;
-  const bool tg = newv && deg > A.t_wave;
-  wave_push(tl, v, A.qlane[nxt], &C->cnt[rn][0], A.cap_v, &C->overflow);
-  wave_push(tw, v, A.qwave[nxt], &C->cnt[rn][1], A.cap_v, &C->overflow);
-  if (tg) {
-    const uint32_t nch = (uint32_t)((deg + A.t_chunk - 1) / A.t_chunk);
-    const uint32_t base = atomicAdd(&C->cnt[rn][2], nch);
-    for (uint32_t c = 0; c < nch; c++) {
-      const int32_t off = (int32_t)c * A.t_chunk;
-      if (base + c < A.cap_wg)
-        A.qwg[nxt][base + c] = make_int4(v, start + off, min(A.t_chunk, deg - off), c == 0);
-      else
-        atomicOr(&C->overflow, 1u);
+#pragma unroll
+  for (int i = 0; i < U; i++) {
+    const bool tl = newv[i] && deg[i] > 0 && deg[i] <= A.t_lane;
+    const bool tw = newv[i] && deg[i] > A.t_lane && deg[i] <= A.t_wave;
+    block_push(tl, v[i], sh.ql, &sh.nql, kLdsQLane, A.qlane[nxt], &C->cnt[rn][0], A.cap_v,
+               &C->overflow);
+    block_push(tw, v[i], sh.qw, &sh.nqw, kLdsQWave, A.qwave[nxt], &C->cnt[rn][1], A.cap_v,
+               &C->overflow);
+    if (newv[i] && deg[i] > A.t_wave) {
+      const uint32_t nch = (uint32_t)((deg[i] + A.t_chunk - 1) / A.t_chunk);
+      const uint32_t base = atomicAdd(&C->cnt[rn][2], nch);
+      for (uint32_t c = 0; c < nch; c++) {
+        const int32_t off = (int32_t)c * A.t_chunk;
+        if (base + c < A.cap_wg)
+          A.qwg[nxt][base + c] = make_int4(v[i], start[i] + off, min(A.t_chunk, deg[i] - off), c == 0);
+        else
+          atomicOr(&C->overflow, 1u);
+      }
     }
   }
 }
 
-// Relax edge e from a row whose distance is du.
-template <bool F32>
-__device__ __forceinline__ bool ss_relax(const SsArgs& A, bool valid, int32_t e, uint32_t du,
-                                         int32_t& v) {
-  bool imp = false;
-  v = 0;
-  if (valid) {
-    v = A.colidx[e];
-    const uint32_t cand = relax_add<F32>(du, A.w[e]);
-    if (cand < A.dist[v] && v != A.src) imp = cand < atomicMin(&A.dist[v], cand);
+// Relax U edges per lane: all column/weight loads, then all target-distance
+// loads, then the atomic mins of the lanes whose candidate is smaller.
+template <bool F32, int U>
+__device__ __forceinline__ void ss_relax_n(const SsArgs& A, const int32_t (&e)[U],
+                                           const bool (&valid)[U], const uint32_t (&du)[U],
+                                           bool (&imp)[U], int32_t (&v)[U]) {
+  uint32_t cand[U];
+#pragma unroll
+  for (int i = 0; i < U; i++) {
+    v[i] = 0;
+    cand[i] = 0u;
+    if (valid[i]) {
+      v[i] = A.colidx[e[i]];
+      cand[i] = relax_add<F32>(du[i], A.w[e[i]]);
+    }
   }
-  return imp;
+  uint32_t cur[U];
+#pragma unroll
+  for (int i = 0; i < U; i++) cur[i] = valid[i] ? A.dist[v[i]] : 0u;
+#pragma unroll
+  for (int i = 0; i < U; i++) {
+    imp[i] = false;
+    if (valid[i] && cand[i] < cur[i] && v[i] != A.src) imp[i] = cand[i] < atomicMin(&A.dist[v[i]], cand[i]);
+  }
 }
 
 template <bool F32>
 __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
-                        int* lds) {
+                        SsShared& sh) {
   const int cur = step & 1, nxt = cur ^ 1;
   const int rc = step % kRot, rn = (step + 1) % kRot;
   SsCtl* C = A.ctl;
+  const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const uint32_t gw = gb * W + wave, nwv = nb * W;
+  if (threadIdx.x == 0) {
+    sh.nql = 0u;
+    sh.nqw = 0u;
+    sh.upd = 0u;
+  }
+  __syncthreads();
   const uint32_t nl = ld_agent(&C->cnt[rc][0]);
   const uint32_t nw = ld_agent(&C->cnt[rc][1]);
   const uint32_t ng = ld_agent(&C->cnt[rc][2]);
-  const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
-  const uint32_t gw = gb * W + wave, nwv = nb * W;
 
   // workgroup tier: one chunk of one row per workgroup
   for (uint32_t i = gb; i < ng; i += nb) {
@@ -200,11 +265,20 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
         acc.fe += 1;
       }
     }
-    for (int32_t base = 0; base < len; base += (int32_t)blockDim.x) {
-      const int32_t k = base + (int32_t)threadIdx.x;
-      int32_t v;
-      const bool imp = ss_relax<F32>(A, k < len, start + k, du, v);
-      ss_enqueue<F32>(A, imp, v, nxt, rn, acc);
+    const int32_t stride = (int32_t)blockDim.x;
+    for (int32_t base = 0; base < len; base += stride * kUnroll) {
+      int32_t e[kUnroll], v[kUnroll];
+      bool ok[kUnroll], imp[kUnroll];
+      uint32_t d[kUnroll];
+#pragma unroll
+      for (int j = 0; j < kUnroll; j++) {
+        const int32_t k = base + j * stride + (int32_t)threadIdx.x;
+        ok[j] = k < len;
+        e[j] = start + k;
+        d[j] = du;
+      }
+      ss_relax_n<F32, kUnroll>(A, e, ok, d, imp, v);
+      ss_enqueue<kUnroll>(A, imp, v, nxt, rn, acc, sh);
     }
   }
 
@@ -218,17 +292,24 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
       acc.fe += 1;
       acc.es += (unsigned long long)(end - start);
     }
-    for (int32_t base = start; base < end; base += kWave) {
-      const int32_t e = base + lane;
-      int32_t v;
-      const bool imp = ss_relax<F32>(A, e < end, e, du, v);
-      ss_enqueue<F32>(A, imp, v, nxt, rn, acc);
+    for (int32_t base = start; base < end; base += kWave * kUnroll) {
+      int32_t e[kUnroll], v[kUnroll];
+      bool ok[kUnroll], imp[kUnroll];
+      uint32_t d[kUnroll];
+#pragma unroll
+      for (int j = 0; j < kUnroll; j++) {
+        e[j] = base + j * kWave + lane;
+        ok[j] = e[j] < end;
+        d[j] = du;
+      }
+      ss_relax_n<F32, kUnroll>(A, e, ok, d, imp, v);
+      ss_enqueue<kUnroll>(A, imp, v, nxt, rn, acc, sh);
     }
   }
 
-  // lane tier: 64 short rows per wavefront, edges dealt one per lane through an
-  // LDS prefix sum of the row lengths
-  int* l_incl = lds + wave * 3 * kWave;
+  // lane tier: 64 short rows per wavefront, their edges dealt out to the lanes
+  // through an LDS prefix sum of the row lengths
+  int* l_incl = sh.stage + wave * 3 * kWave;
   int* l_base = l_incl + kWave;
   int* l_du = l_base + kWave;
   for (uint32_t bi = gw; (uint64_t)bi * kWave < nl; bi += nwv) {
@@ -251,17 +332,45 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
     l_base[lane] = start - (incl - deg);
     l_du[lane] = (int)du;
     wave_lds_sync();
-    for (int base = 0; base < total; base += kWave) {
-      const int k = base + lane;
-      int owner = 0;  // first lane whose inclusive prefix exceeds k
+    for (int base = 0; base < total; base += kWave * kUnrollLane) {
+      int32_t e[kUnrollLane], v[kUnrollLane];
+      bool ok[kUnrollLane], imp[kUnrollLane];
+      uint32_t d[kUnrollLane];
 #pragma unroll
-      for (int s = 32; s >= 1; s >>= 1)
-        if (l_incl[owner + s - 1] <= k) owner += s;
-      int32_t v;
-      const bool imp = ss_relax<F32>(A, k < total, l_base[owner] + k, (uint32_t)l_du[owner], v);
-      ss_enqueue<F32>(A, imp, v, nxt, rn, acc);
+      for (int j = 0; j < kUnrollLane; j++) {
+        const int k = base + j * kWave + lane;
+        int owner = 0;  // first lane whose inclusive prefix exceeds k
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1)
+          if (l_incl[owner + s - 1] <= k) owner += s;
+        ok[j] = k < total;
+        e[j] = l_base[owner] + k;
+        d[j] = (uint32_t)l_du[owner];
+      }
+      ss_relax_n<F32, kUnrollLane>(A, e, ok, d, imp, v);
+      ss_enqueue<kUnrollLane>(A, imp, v, nxt, rn, acc, sh);
     }
     wave_lds_sync();
+  }
+
+  // publish the workgroup's next-frontier entries and ptr flag
+  __syncthreads();
+  const uint32_t n_l = min(sh.nql, (uint32_t)kLdsQLane), n_w = min(sh.nqw, (uint32_t)kLdsQWave);
+  if (threadIdx.x == 0) {
+    if (n_l) sh.gbase_l = atomicAdd(&C->cnt[rn][0], n_l);
+    if (n_w) sh.gbase_w = atomicAdd(&C->cnt[rn][1], n_w);
+    if (sh.upd) st_agent(&C->upd[rn], 1u);
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < n_l; j += blockDim.x) {
+    const uint32_t p = sh.gbase_l + j;
+    if (p < A.cap_v) A.qlane[nxt][p] = sh.ql[j];
+    else atomicOr(&C->overflow, 1u);
+  }
+  for (uint32_t j = threadIdx.x; j < n_w; j += blockDim.x) {
+    const uint32_t p = sh.gbase_w + j;
+    if (p < A.cap_v) A.qwave[nxt][p] = sh.qw[j];
+    else atomicOr(&C->overflow, 1u);
   }
 }
 
@@ -274,10 +383,11 @@ __device__ __forceinline__ void ss_zero_rotation(SsCtl* C, uint32_t step) {
   C->upd[rz] = 0u;
 }
 
-// All steps in one cooperative launch.
+// All steps in one launch; a grid barrier separates the steps.  The grid must
+// be co-resident (its size comes from the occupancy query, halved).
 template <bool F32>
 __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
-  __shared__ int lds[kMaxWavesPerBlock * 3 * kWave];
+  __shared__ SsShared sh;
   SsCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
   Acc acc;
@@ -287,7 +397,7 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
   int32_t status = 1;
   for (;;) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
-    ss_step<F32>(A, step, blockIdx.x, gridDim.x, acc, lds);
+    ss_step<F32>(A, step, blockIdx.x, gridDim.x, acc, sh);
     if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       break;
@@ -309,13 +419,13 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
 // One step per launch; the last block to finish advances the step.
 template <bool F32>
 __global__ void __launch_bounds__(1024) ss_step_kernel(SsArgs A) {
-  __shared__ int lds[kMaxWavesPerBlock * 3 * kWave];
+  __shared__ SsShared sh;
   SsCtl* C = A.ctl;
   if (C->done) return;
   const uint32_t step = C->step;
   if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
   Acc acc;
-  ss_step<F32>(A, step, blockIdx.x, gridDim.x, acc, lds);
+  ss_step<F32>(A, step, blockIdx.x, gridDim.x, acc, sh);
   flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
   if (last_block_done(&C->blocks_done)) {
     C->blocks_done = 0;
@@ -368,6 +478,7 @@ static int persistent_grid(K kernel, int threads, int* per_cu_out = nullptr) {
 }
 
 void ss_persistent_occupancy(int threads, int* per_cu, int* grid) {
+  if (threads <= 0) threads = 1024;
   *grid = persistent_grid(ss_persistent_kernel<false>, threads, per_cu);
 }
 
@@ -377,7 +488,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
                             hipStream_t stream, bool capture) {
   const Tuning& T = tuning();
   const DevInfo& di = dev_info();
-  const int threads = T.wg_threads;
+  const int threads = T.wg_threads > 0 ? T.wg_threads : 1024;
   const int fill_blocks = (int)std::min<int64_t>(4096, (A.n + 255) / 256 + 1);
   hipLaunchKernelGGL(ss_fill_kernel<F32>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
                      (int64_t)A.n, A.bm[0], A.bm[1], L.nwords, A.ctl);
@@ -400,7 +511,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
     void* args[] = {&a};
     hipError_t e;
     void* tk = capture ? nullptr : ktimer_begin(stream);
-    if (!capture && di.coop) {
+    if (!capture && di.coop && T.coop) {
       e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&ss_persistent_kernel<F32>),
                                      dim3(grid), dim3(threads), args, 0, stream);
     } else {

@@ -82,9 +82,9 @@ __device__ void tile_put_source(const TileArgs& A, int32_t col, int32_t s, uint3
 
 __global__ void tile_seed_kernel(TileArgs A, const int32_t* sources, int32_t count) {
   if (A.ctl->done) return;  // validation failed
-  // one thread: seeds share queue slots and bitmap words
-  if (threadIdx.x != 0) return;
-  for (int32_t j = 0; j < count; j++) tile_put_source(A, j, sources[j], 0u);
+  // one thread per column; shared words are updated with atomics and the
+  // union-bitmap test-and-set picks one thread to queue a repeated source
+  for (int32_t j = threadIdx.x; j < count; j += blockDim.x) tile_put_source(A, j, sources[j], 0u);
 }
 
 template <bool F32>
@@ -124,9 +124,41 @@ __global__ void tile_evict_kernel(TileArgs A, int32_t col) {
 // ---------------------------------------------------------------------------
 // one step
 // ---------------------------------------------------------------------------
+constexpr int kTileLdsQ = 1024;  // next union-frontier entries gathered per workgroup
+constexpr int kTileUnroll = 2;   // (edge, segment) units in flight per 16-lane group
+
+// Dynamic LDS of a tile launch: the distances of each wavefront's current row
+// (K words per wavefront) and of the workgroup's current chunk row (K words).
+__host__ __device__ inline size_t tile_dyn_lds(int K, int waves) {
+  return (size_t)(waves + 1) * (size_t)K * 4u;
+}
+
+struct TileShared {
+  unsigned long long rowmask[kMaxWavesPerBlock][kSegMax];  // masks of each wave's row
+  unsigned long long blkmask[kSegMax];                     // masks of the workgroup's chunk
+  unsigned long long colact[kSegMax];                      // columns improved (this workgroup)
+  int32_t q[kTileLdsQ];
+  uint32_t nq, gbase;
+};
+
+__device__ __forceinline__ void tile_block_push(bool pred, int32_t v, TileShared& sh,
+                                                int32_t* gq, uint32_t* gcnt, uint32_t gcap,
+                                                uint32_t* overflow) {
+  const unsigned long long b = __ballot(pred);
+  if (b == 0) return;
+  const int leader = __ffsll((long long)b) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(&sh.nq, (uint32_t)__popcll(b));
+  base = __shfl(base, leader, kWave);
+  const uint32_t pos = base + lanes_below(b);
+  const bool spill = pred && pos >= (uint32_t)kTileLdsQ;
+  if (pred && !spill) sh.q[pos] = v;
+  wave_push(spill, v, gq, gcnt, gcap, overflow);
+}
+
 template <bool F32>
 __device__ __forceinline__ void tile_enqueue(const TileArgs& A, bool newv, int32_t v, int qn,
-                                             int rn) {
+                                             int rn, TileShared& sh) {
   TileCtl* C = A.ctl;
   int32_t start = 0, deg = 0;
   if (newv) {
@@ -135,7 +167,7 @@ __device__ __forceinline__ void tile_enqueue(const TileArgs& A, bool newv, int32
   }
   const bool tw = newv && deg > 0 && deg <= A.t_wave;
   const bool tg = newv && deg > A.t_wave;
-  wave_push(tw, v, A.qwave[qn], &C->cnt[rn][1], A.cap_v, &C->overflow);
+  tile_block_push(tw, v, sh, A.qwave[qn], &C->cnt[rn][1], A.cap_v, &C->overflow);
   if (tg) {
     const uint32_t nch = (uint32_t)((deg + A.t_chunk - 1) / A.t_chunk);
     const uint32_t base = atomicAdd(&C->cnt[rn][2], nch);
@@ -154,94 +186,102 @@ __device__ __forceinline__ uint32_t elem4(const uint4& x, int i) {
 }
 
 // Process the (edge, active segment) units of edges [start, start+len) of row
-// u.  `ngroups` groups of 16 lanes cooperate (a wavefront: 4; a workgroup:
-// blockDim/16); `gidx` is this lane's group, j16 its lane in the group.  The
-// loop count is uniform over the cooperating lanes.
+// u, whose masks are in `rowmask` (LDS).  `ngroups` groups of 16 lanes
+// cooperate (a wavefront: 4; a workgroup: blockDim/16); `gidx` is this lane's
+// group, j16 its lane in the group.  The loop count is uniform over the
+// cooperating lanes.  Each lane covers 4 consecutive sources of a segment.
 template <bool F32>
-__device__ __forceinline__ void tile_units(const TileArgs& A, int32_t u, int32_t start,
-                                           int32_t len, uint32_t actseg, int nact, int gidx,
-                                           int ngroups, int q, int qn, int rn, int nxt,
-                                           Acc& acc, unsigned long long* s_colact) {
+__device__ __forceinline__ void tile_units(const TileArgs& A, int32_t start, int32_t len,
+                                           const unsigned long long* rowmask,
+                                           const uint32_t* rowdu, uint32_t actseg, int nact,
+                                           int gidx, int ngroups, int qn, int rn, int nxt,
+                                           Acc& acc, TileShared& sh) {
+  constexpr int U = kTileUnroll;
   const int j16 = threadIdx.x & 15;
   const uint32_t units = (uint32_t)len * (uint32_t)nact;
-  const size_t urow = (size_t)u * A.K;
-  for (uint32_t ub = 0; ub < units; ub += (uint32_t)ngroups) {
-    const uint32_t unit = ub + (uint32_t)gidx;
-    const bool valid = unit < units;
-    int32_t v = 0;
-    int s = 0;
-    uint32_t w = 0;
-    unsigned long long segm = 0ull;
-    if (valid) {
-      const uint32_t eo = unit / (uint32_t)nact;
-      uint32_t si = unit - eo * (uint32_t)nact;
-      uint32_t am = actseg;
-      while (si--) am &= am - 1u;
-      s = __ffs(am) - 1;
-      const int32_t e = start + (int32_t)eo;
-      v = A.colidx[e];
-      w = A.w[e];
-      segm = A.mk[q][(size_t)u * A.nseg + s];
-    }
-    const uint32_t bits4 = (uint32_t)(segm >> (4 * j16)) & 0xFu;
-    uint32_t imp4 = 0u;
-    if (bits4) {
-      const int col = s * 64 + 4 * j16;
-      const uint4 du = *reinterpret_cast<const uint4*>(A.D + urow + col);
-      const size_t ov = (size_t)v * A.K + col;
-      const uint4 dv = *reinterpret_cast<const uint4*>(A.D + ov);
+  for (uint32_t ub = 0; ub < units; ub += (uint32_t)(ngroups * U)) {
+    int32_t v[U];
+    int sg[U];
+    uint32_t w[U], bits[U];
 #pragma unroll
-      for (int i = 0; i < 4; i++) {
-        if ((bits4 >> i) & 1u) {
-          const uint32_t c = relax_add<F32>(elem4(du, i), w);
-          if (c < elem4(dv, i) && c < atomicMin(&A.D[ov + i], c)) imp4 |= 1u << i;
+    for (int i = 0; i < U; i++) {
+      const uint32_t unit = ub + (uint32_t)(i * ngroups + gidx);
+      v[i] = 0;
+      sg[i] = 0;
+      w[i] = 0u;
+      bits[i] = 0u;
+      if (unit < units) {
+        const uint32_t eo = unit / (uint32_t)nact;
+        uint32_t si = unit - eo * (uint32_t)nact;
+        uint32_t am = actseg;
+        while (si--) am &= am - 1u;
+        sg[i] = __ffs(am) - 1;
+        const int32_t e = start + (int32_t)eo;
+        v[i] = A.colidx[e];
+        w[i] = A.w[e];
+        bits[i] = (uint32_t)(rowmask[sg[i]] >> (4 * j16)) & 0xFu;
+      }
+    }
+    uint4 du[U], dv[U];
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      if (bits[i]) {
+        const int col = sg[i] * 64 + 4 * j16;
+        du[i] = *reinterpret_cast<const uint4*>(rowdu + col);
+        dv[i] = *reinterpret_cast<const uint4*>(A.D + (size_t)v[i] * A.K + col);
+      } else {
+        du[i] = make_uint4(0u, 0u, 0u, 0u);
+        dv[i] = du[i];
+      }
+    }
+    uint32_t imp[U];
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      imp[i] = 0u;
+      const size_t ov = (size_t)v[i] * A.K + sg[i] * 64 + 4 * j16;
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        if ((bits[i] >> t) & 1u) {
+          const uint32_t c = relax_add<F32>(elem4(du[i], t), w[i]);
+          if (c < elem4(dv[i], t) && c < atomicMin(&A.D[ov + t], c)) imp[i] |= 1u << t;
         }
       }
     }
-    unsigned long long x = (unsigned long long)imp4 << (4 * j16);
-    x |= __shfl_xor(x, 1, kWave);
-    x |= __shfl_xor(x, 2, kWave);
-    x |= __shfl_xor(x, 4, kWave);
-    x |= __shfl_xor(x, 8, kWave);
-    bool newv = false;
-    if (j16 == 0 && x != 0ull) {
-      atomicOr(&A.mk[qn][(size_t)v * A.nseg + s], x);
-      atomicOr(&s_colact[s], x);
-      acc.im += (unsigned long long)__popcll(x);
-      const uint32_t vb = 1u << (v & 31);
-      newv = (atomicOr(&A.ubm[nxt][v >> 5], vb) & vb) == 0u;
+    bool newv[U];
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      unsigned long long x = (unsigned long long)imp[i] << (4 * j16);
+      x |= __shfl_xor(x, 1, kWave);
+      x |= __shfl_xor(x, 2, kWave);
+      x |= __shfl_xor(x, 4, kWave);
+      x |= __shfl_xor(x, 8, kWave);
+      newv[i] = false;
+      if (j16 == 0 && x != 0ull) {
+        atomicOr(&A.mk[qn][(size_t)v[i] * A.nseg + sg[i]], x);
+        atomicOr(&sh.colact[sg[i]], x);
+        acc.im += (unsigned long long)__popcll(x);
+        const uint32_t vb = 1u << (v[i] & 31);
+        newv[i] = (atomicOr(&A.ubm[nxt][v[i] >> 5], vb) & vb) == 0u;
+      }
     }
-    tile_enqueue<F32>(A, newv, v, qn, rn);
+#pragma unroll
+    for (int i = 0; i < U; i++) tile_enqueue<F32>(A, newv[i], v[i], qn, rn, sh);
   }
-}
-
-// Mask words of row u: active segments (bit per segment) and the total of
-// active sources.
-__device__ __forceinline__ uint32_t tile_row_masks(const TileArgs& A, int q, int32_t u,
-                                                   int& nact, int& nsrc) {
-  uint32_t act = 0u;
-  nsrc = 0;
-  const unsigned long long* mp = A.mk[q] + (size_t)u * A.nseg;
-  for (int s = 0; s < A.nseg; s++) {
-    const unsigned long long x = mp[s];
-    if (x) {
-      act |= 1u << s;
-      nsrc += __popcll(x);
-    }
-  }
-  nact = __popc(act);
-  return act;
 }
 
 template <bool F32>
 __device__ void tile_step(const TileArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
-                          unsigned long long* s_colact) {
+                          TileShared& sh, uint32_t* dyn) {
   const int q = step % 3, qn = (step + 1) % 3, qp = (step + 2) % 3;
   const int cur = step & 1, nxt = cur ^ 1;
   const int rc = step % kRot, rn = (step + 1) % kRot, rp = (step + 3) % kRot;
   TileCtl* C = A.ctl;
   const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
   const uint32_t gw = gb * W + wave, nwv = nb * W;
+  const int nseg = A.nseg;
+  if (threadIdx.x < kSegMax) sh.colact[threadIdx.x] = 0ull;
+  if (threadIdx.x == 0) sh.nq = 0u;
+  __syncthreads();
 
   // (a) clear the masks of the previous step's frontier (read one step ago)
   {
@@ -249,17 +289,29 @@ __device__ void tile_step(const TileArgs& A, uint32_t step, uint32_t gb, uint32_
     const uint32_t tot = pw + pg;
     for (uint32_t i = gb * blockDim.x + threadIdx.x; i < tot; i += nb * blockDim.x) {
       const int32_t u = i < pw ? A.qwave[qp][i] : A.qwg[qp][i - pw].x;
-      unsigned long long* mp = A.mk[qp] + (size_t)u * A.nseg;
-      for (int s = 0; s < A.nseg; s++) mp[s] = 0ull;
+      unsigned long long* mp = A.mk[qp] + (size_t)u * nseg;
+      for (int s = 0; s < nseg; s++) mp[s] = 0ull;
     }
   }
 
   // (b) workgroup tier: one chunk of a long row per workgroup
+  uint32_t* bdu = dyn + (size_t)W * A.K;
   const uint32_t ng = ld_agent(&C->cnt[rc][2]);
   for (uint32_t i = gb; i < ng; i += nb) {
     const int4 r = A.qwg[q][i];
-    int nact, nsrc;
-    const uint32_t act = tile_row_masks(A, q, r.x, nact, nsrc);
+    __syncthreads();  // the previous chunk is done with blkmask / bdu
+    if ((int)threadIdx.x < nseg) sh.blkmask[threadIdx.x] = A.mk[q][(size_t)r.x * nseg + threadIdx.x];
+    for (int c = threadIdx.x; c < A.K; c += blockDim.x) bdu[c] = A.D[(size_t)r.x * A.K + c];
+    __syncthreads();
+    uint32_t act = 0u;
+    int nsrc = 0;
+    for (int s = 0; s < nseg; s++) {
+      const unsigned long long x = sh.blkmask[s];
+      if (x) {
+        act |= 1u << s;
+        nsrc += __popcll(x);
+      }
+    }
     if (threadIdx.x == 0) {
       acc.es += (unsigned long long)r.z;
       acc.se += (unsigned long long)r.z * (unsigned long long)nsrc;
@@ -269,17 +321,30 @@ __device__ void tile_step(const TileArgs& A, uint32_t step, uint32_t gb, uint32_
         acc.sa += (unsigned long long)nsrc;
       }
     }
-    tile_units<F32>(A, r.x, r.y, r.z, act, nact, threadIdx.x >> 4, blockDim.x >> 4, q, qn, rn,
-                    nxt, acc, s_colact);
+    tile_units<F32>(A, r.y, r.z, sh.blkmask, bdu, act, __popc(act), threadIdx.x >> 4,
+                    blockDim.x >> 4, qn, rn, nxt, acc, sh);
   }
 
   // (c) wave tier: one wavefront per row
   const uint32_t nw = ld_agent(&C->cnt[rc][1]);
+  unsigned long long* wmask = sh.rowmask[wave];
+  uint32_t* wdu = dyn + (size_t)wave * A.K;
   for (uint32_t i = gw; i < nw; i += nwv) {
     const int32_t u = A.qwave[q][i];
     const int32_t start = A.rowptr[u], deg = A.rowptr[u + 1] - start;
-    int nact, nsrc;
-    const uint32_t act = tile_row_masks(A, q, u, nact, nsrc);
+    unsigned long long x = 0ull;
+    if (lane < nseg) x = A.mk[q][(size_t)u * nseg + lane];
+    const unsigned long long actb = __ballot(x != 0ull);
+    const int cnt = __popcll(x);
+    int nsrc = cnt;
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) nsrc += __shfl_xor(nsrc, off, kWave);
+    nsrc = __shfl(nsrc, 0, kWave);
+    if (lane < nseg) wmask[lane] = x;
+    const uint32_t act = (uint32_t)actb & 0xFFu;
+    for (int sgm = 0; sgm < nseg; sgm++)
+      if ((act >> sgm) & 1u) wdu[sgm * 64 + lane] = A.D[(size_t)u * A.K + sgm * 64 + lane];
+    wave_lds_sync();
     if (lane == 0) {
       A.ubm[cur][u >> 5] = 0u;
       acc.fe += 1;
@@ -287,8 +352,22 @@ __device__ void tile_step(const TileArgs& A, uint32_t step, uint32_t gb, uint32_
       acc.sa += (unsigned long long)nsrc;
       acc.se += (unsigned long long)deg * (unsigned long long)nsrc;
     }
-    tile_units<F32>(A, u, start, deg, act, nact, lane >> 4, kWave / 16, q, qn, rn, nxt, acc,
-                    s_colact);
+    tile_units<F32>(A, start, deg, wmask, wdu, act, __popc(act), lane >> 4, kWave / 16, qn, rn,
+                    nxt, acc, sh);
+    wave_lds_sync();
+  }
+
+  // (d) publish the workgroup's next-frontier entries and column activity
+  __syncthreads();
+  const uint32_t n_q = min(sh.nq, (uint32_t)kTileLdsQ);
+  if (threadIdx.x == 0 && n_q) sh.gbase = atomicAdd(&C->cnt[rn][1], n_q);
+  if ((int)threadIdx.x < nseg && sh.colact[threadIdx.x])
+    atomicOr(&C->colact[rn][threadIdx.x], sh.colact[threadIdx.x]);
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < n_q; j += blockDim.x) {
+    const uint32_t p = sh.gbase + j;
+    if (p < A.cap_v) A.qwave[qn][p] = sh.q[j];
+    else atomicOr(&C->overflow, 1u);
   }
 }
 
@@ -303,31 +382,21 @@ __device__ __forceinline__ void tile_step_prologue(TileCtl* C, uint32_t step, in
   }
 }
 
-__device__ __forceinline__ void flush_colact(TileCtl* C, int rn, int nseg,
-                                             unsigned long long* s_colact) {
-  __syncthreads();
-  if ((int)threadIdx.x < nseg && s_colact[threadIdx.x])
-    atomicOr(&C->colact[rn][threadIdx.x], s_colact[threadIdx.x]);
-  __syncthreads();
-  if ((int)threadIdx.x < kSegMax) s_colact[threadIdx.x] = 0ull;
-  __syncthreads();
-}
-
 __device__ __forceinline__ bool any_active(const TileCtl* C, int rn, int nseg) {
   unsigned long long a = 0ull;
   for (int s = 0; s < nseg; s++) a |= ld_agent64(&C->colact[rn][s]);
   return a != 0ull;
 }
 
-// All steps (up to max_steps, and at most n when cap_n) in one cooperative launch.
+// All steps (up to max_steps, and at most n when cap_n) in one launch with a
+// grid barrier between steps.
 template <bool F32>
 __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32_t max_steps,
                                                                int32_t cap_n) {
-  __shared__ unsigned long long s_colact[kSegMax];
+  __shared__ TileShared sh;
+  extern __shared__ uint32_t tile_dyn[];
   TileCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
-  if (threadIdx.x < kSegMax) s_colact[threadIdx.x] = 0ull;
-  __syncthreads();
   Acc acc;
   uint32_t epoch = 0;
   const uint32_t bar_base = ld_agent(&C->bar_base);
@@ -337,8 +406,7 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   bool finished = false;
   for (;;) {
     tile_step_prologue(C, step, A.K);
-    tile_step<F32>(A, step, blockIdx.x, gridDim.x, acc, s_colact);
-    flush_colact(C, (step + 1) % kRot, A.nseg, s_colact);
+    tile_step<F32>(A, step, blockIdx.x, gridDim.x, acc, sh, tile_dyn);
     if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       finished = true;
@@ -364,16 +432,14 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
 // One step per launch; the last block advances the step.
 template <bool F32>
 __global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap_n) {
-  __shared__ unsigned long long s_colact[kSegMax];
+  __shared__ TileShared sh;
+  extern __shared__ uint32_t tile_dyn[];
   TileCtl* C = A.ctl;
   if (C->done) return;
-  if (threadIdx.x < kSegMax) s_colact[threadIdx.x] = 0ull;
-  __syncthreads();
   const uint32_t step = C->step;
   tile_step_prologue(C, step, A.K);
   Acc acc;
-  tile_step<F32>(A, step, blockIdx.x, gridDim.x, acc, s_colact);
-  flush_colact(C, (step + 1) % kRot, A.nseg, s_colact);
+  tile_step<F32>(A, step, blockIdx.x, gridDim.x, acc, sh, tile_dyn);
   flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
   if (last_block_done(&C->blocks_done)) {
     C->blocks_done = 0;
@@ -470,6 +536,7 @@ TileLayout tile_layout(int64_t n, int64_t m, int32_t k) {
   L.cap_wg = (uint32_t)(m / 33 + m / 64 + 2);
   L.nwords = (n + 31) / 32;
   L.ctl = c.take(sizeof(TileCtl));
+  L.info = c.take(sizeof(dawn_run_info));
   L.D = c.take((size_t)n * L.K * 4);
   for (int i = 0; i < 3; i++) L.mk[i] = c.take((size_t)n * L.nseg * 8);
   for (int i = 0; i < 3; i++) L.qwave[i] = c.take((size_t)n * 4);
@@ -529,7 +596,7 @@ dawn_status tile_seed_all(const TileArgs& a, const int32_t* sources_dev, int32_t
                        a.rowptr, a.colidx, a.w, a.n, a.m, (int32_t)f32, &a.ctl->done,
                        &a.ctl->converged);
   }
-  hipLaunchKernelGGL(tile_seed_kernel, dim3(1), dim3(64), 0, stream, a, sources_dev, count);
+  hipLaunchKernelGGL(tile_seed_kernel, dim3(1), dim3(512), 0, stream, a, sources_dev, count);
   return hip_check(hipGetLastError(), "tile seed");
 }
 
@@ -548,9 +615,9 @@ dawn_status tile_evict(const TileArgs& a, int32_t col, hipStream_t stream) {
 }
 
 template <typename K>
-static int persistent_grid_t(K kernel, int threads, int* per_cu_out = nullptr) {
+static int persistent_grid_t(K kernel, int threads, int* per_cu_out = nullptr, size_t dyn = 0) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, dyn) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   // Measured on MI355X: the occupancy query reports twice the workgroups per CU
@@ -562,38 +629,41 @@ static int persistent_grid_t(K kernel, int threads, int* per_cu_out = nullptr) {
 }
 
 void tile_persistent_occupancy(int threads, int* per_cu, int* grid) {
-  *grid = persistent_grid_t(tile_persistent_kernel<false>, threads, per_cu);
+  if (threads <= 0) threads = 256;
+  *grid = persistent_grid_t(tile_persistent_kernel<false>, threads, per_cu,
+                            tile_dyn_lds(256, threads / 64));
 }
 
 template <bool F32>
 static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_steps,
                                 hipStream_t stream) {
   const Tuning& T = tuning();
-  const int threads = T.wg_threads;
+  const int threads = T.wg_threads > 0 ? T.wg_threads : 256;
   const int32_t cap_n = persistent ? 1 : 0;
+  const size_t dyn = tile_dyn_lds(a.K, threads / 64);
   if (persistent) {
-    int grid = persistent_grid_t(tile_persistent_kernel<F32>, threads);
+    int grid = persistent_grid_t(tile_persistent_kernel<F32>, threads, nullptr, dyn);
     if (T.grid > 0 && T.grid < grid) grid = T.grid;
     TileArgs aa = a;
     int32_t ms = max_steps, cn = cap_n;
     void* args[] = {&aa, &ms, &cn};
     hipError_t e;
     void* tk = ktimer_begin(stream);
-    if (dev_info().coop) {
+    if (dev_info().coop && T.coop) {
       e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&tile_persistent_kernel<F32>),
-                                     dim3(grid), dim3(threads), args, 0, stream);
+                                     dim3(grid), dim3(threads), args, (unsigned)dyn, stream);
     } else {
-      hipLaunchKernelGGL(tile_persistent_kernel<F32>, dim3(grid), dim3(threads), 0, stream, aa,
+      hipLaunchKernelGGL(tile_persistent_kernel<F32>, dim3(grid), dim3(threads), dyn, stream, aa,
                          ms, cn);
       e = hipGetLastError();
     }
     ktimer_end(tk, stream, 1);
     return hip_check(e, "tile persistent launch");
   }
-  const int grid = T.grid > 0 ? T.grid : 4 * dev_info().cus;
+  const int grid = T.grid > 0 ? T.grid : 16 * dev_info().cus;
   void* tk = ktimer_begin(stream);
   for (int s = 0; s < max_steps; s++)
-    hipLaunchKernelGGL(tile_step_kernel<F32>, dim3(grid), dim3(threads), 0, stream, a, 0);
+    hipLaunchKernelGGL(tile_step_kernel<F32>, dim3(grid), dim3(threads), dyn, stream, a, 0);
   ktimer_end(tk, stream, max_steps);
   return hip_check(hipGetLastError(), "tile step launches");
 }
