@@ -1,0 +1,303 @@
+#!/usr/bin/env python3
+"""Measurements of the workloads other than bench.py's headline one.
+
+    python bench_suite.py [--only c1,c2,c3,c4b,c5] [--out results.jsonl]
+
+c1   plain SSSP latency: directed ER n=1000 m=8000, uint32 weights [1,100],
+     source 0; per-call latency percentiles (host-observed, with a device
+     synchronisation after every call) and steps.
+c2   plain single-source GOVM at scale: R-MAT scale 22, edge factor 16, uint32
+     weights [1,255], 16 sources one per launch; GTEPS per source, p50/p99,
+     the single-source kernel's HBM roofline (algorithmic bytes / kernel time).
+c3   high step count: 2048x2048 grid, 1 % of pairs deleted, fp32 weights
+     U(0,1], 8 sources; ms per call, steps, ms per step.
+c4b  64 uneven ER graphs (n = 10^U(4,6), m = 8n, fp32 lognormal), one source
+     each: one persistent launch over the disjoint union, also replayed from a
+     captured HIP graph, against 64 plain calls.
+c5   serving: Poisson arrivals over 32 resident R-MAT graphs (scales 14 + i%9
+     capped at --c5-max-scale, edge factors 8/16/32, half uint32 half fp32
+     lognormal); p50/p99 latency and completed queries/s per offered rate.
+
+Every input is synthetic and seeded (graphgen.workloads).  Each section prints
+one JSON line; --out appends them to a file.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def emit(rec, out):
+    line = json.dumps(rec)
+    print(line, flush=True)
+    if out:
+        with open(out, "a") as f:
+            f.write(line + "\n")
+
+
+def reach_edges(torch, d, outdeg, inf):
+    fin = d != inf
+    return int((fin.to(torch.int64) * outdeg).sum().item())
+
+
+def ss_bytes(info, n):
+    """Algorithmic bytes of a single-source run: per edge scanned 8 (column +
+    weight) + 4 (target distance); per improvement 4; per frontier row 16
+    (queue id, row bounds, own distance); 8 per vertex (init + result)."""
+    return (12 * info["edges_scanned"] + 4 * info["improvements"] + 16 * info["frontier_entries"]
+            + 8 * n)
+
+
+def percentile_ms(xs):
+    import numpy as np
+    a = np.asarray(xs) * 1e3
+    return {"p50_ms": float(np.percentile(a, 50)), "p99_ms": float(np.percentile(a, 99)),
+            "mean_ms": float(a.mean())}
+
+
+def c1(args, dawn, torch, np):
+    from graphgen import workloads
+    g, srcs = workloads.er_small()
+    csr = dawn.Csr.from_graph(g)
+    out = torch.empty(g.n, dtype=torch.uint32, device="cuda")
+    ws = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
+    info = dawn.info_tensor()
+    for _ in range(50):
+        dawn.sssp(csr, 0, out=out, ws=ws, info=info)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(args.c1_reps):
+        t0 = time.perf_counter()
+        dawn.sssp(csr, 0, out=out, ws=ws, info=info)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    i = dawn.read_info(info)
+    rec = {"config": "c1_er_n1000_m8000_u32", "reps": args.c1_reps, "steps": i["steps"]}
+    rec.update({k.replace("_ms", "_us"): v * 1e3 for k, v in percentile_ms(lat).items()})
+    return rec
+
+
+def c2(args, dawn, torch, np):
+    from graphgen import workloads
+    t = time.perf_counter()
+    g, srcs = workloads.rmat22(nsrc=args.c2_sources, scale=args.c2_scale)
+    log(f"c2 graph n={g.n} m={g.m} ({time.perf_counter() - t:.1f}s)")
+    csr = dawn.Csr.from_graph(g)
+    out = torch.empty(g.n, dtype=torch.uint32, device="cuda")
+    ws = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
+    info = dawn.info_tensor()
+    outdeg = torch.as_tensor(np.diff(g.rowptr.astype(np.int64)), device="cuda")
+    dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info)
+    torch.cuda.synchronize()
+    per, gteps, mu, steps, kb, kms = [], [], [], [], 0, 0.0
+    for s in srcs:
+        dawn.kernel_timer(True)
+        t0 = time.perf_counter()
+        dawn.sssp(csr, int(s), out=out, ws=ws, info=info)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        dawn.kernel_timer(False)
+        ms, _ = dawn.kernel_time()
+        i = dawn.read_info(info)
+        r = reach_edges(torch, out, outdeg, 0xFFFFFFFF)
+        per.append(dt)
+        gteps.append(r / dt / 1e9)
+        mu.append(i["edges_scanned"] / max(r, 1))
+        steps.append(i["steps"])
+        kb += ss_bytes(i, g.n)
+        kms += ms
+    rec = {"config": f"c2_rmat{args.c2_scale}_ef16_u32_plain", "n": g.n, "m": g.m,
+           "sources": len(srcs), "gteps_per_source_mean": float(np.mean(gteps)),
+           "gteps_per_source_min": float(np.min(gteps)), "mu_e_mean": float(np.mean(mu)),
+           "steps_mean": float(np.mean(steps)),
+           "roofline": {"bound": "hbm", "kernel": "ss_persistent_kernel<false>",
+                        "achieved": kb / (kms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                        "frac": kb / (kms * 1e-3) / 1e9 / 8000.0}}
+    rec.update(percentile_ms(per))
+    return rec
+
+
+def c3(args, dawn, torch, np):
+    from graphgen import workloads
+    g, srcs = workloads.grid2048(nsrc=args.c3_sources, side=args.c3_side)
+    csr = dawn.Csr.from_graph(g)
+    out = torch.empty(g.n, dtype=torch.float32, device="cuda")
+    ws = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
+    info = dawn.info_tensor()
+    outdeg = torch.as_tensor(np.diff(g.rowptr.astype(np.int64)), device="cuda")
+    dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info)
+    torch.cuda.synchronize()
+    per, steps, gteps = [], [], []
+    for s in srcs:
+        t0 = time.perf_counter()
+        dawn.sssp(csr, int(s), out=out, ws=ws, info=info)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        i = dawn.read_info(info)
+        fin = torch.isfinite(out)
+        r = int((fin.to(torch.int64) * outdeg).sum().item())
+        per.append(dt)
+        steps.append(i["steps"])
+        gteps.append(r / dt / 1e9)
+    rec = {"config": f"c3_grid{args.c3_side}_f32", "n": g.n, "m": g.m, "sources": len(srcs),
+           "steps_mean": float(np.mean(steps)),
+           "ms_per_step": float(np.mean([p * 1e3 / s for p, s in zip(per, steps)])),
+           "gteps_mean": float(np.mean(gteps))}
+    rec.update(percentile_ms(per))
+    return rec
+
+
+def c4b(args, dawn, torch, np):
+    from graphgen import workloads
+    t = time.perf_counter()
+    gs = workloads.er_batch(count=args.c4b_graphs)
+    log(f"c4b {len(gs)} graphs generated ({time.perf_counter() - t:.1f}s)")
+    csrs = [dawn.Csr.from_graph(g) for g, _ in gs]
+    b = dawn.Batch(csrs)
+    srcs = torch.tensor([s for _, s in gs], dtype=torch.int32, device="cuda")
+    out = torch.empty(b.total_n, dtype=torch.float32, device="cuda")
+    info = dawn.info_tensor()
+    b.run(srcs, out=out, info=info)
+    torch.cuda.synchronize()
+    reps = args.c4b_reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.run(srcs, out=out, info=info)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    i = dawn.read_info(info)
+    b.capture(srcs, out, info=info)
+    b.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    # reachable edges per graph, from the batched result
+    work = 0
+    for (g, _), d in zip(gs, b.split(out)):
+        od = torch.as_tensor(np.diff(g.rowptr.astype(np.int64)), device="cuda")
+        work += int((torch.isfinite(d).to(torch.int64) * od).sum().item())
+    # plain: one call per graph
+    wss = [dawn.workspace(dawn.sssp_workspace_bytes(c.n, c.m)) for c in csrs]
+    outs = [torch.empty(c.n, dtype=torch.float32, device="cuda") for c in csrs]
+    for c, (_, s), w, o in zip(csrs, gs, wss, outs):
+        dawn.sssp(c, s, out=o, ws=w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for c, (_, s), w, o in zip(csrs, gs, wss, outs):
+            dawn.sssp(c, s, out=o, ws=w)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    b.close()
+    return {"config": f"c4b_er_batch{len(gs)}_f32lognormal", "total_n": b.total_n,
+            "total_m": b.total_m, "steps": i["steps"],
+            "batch_ms": t_batch * 1e3, "graph_replay_ms": t_graph * 1e3, "plain_ms": t_plain * 1e3,
+            "graphs_per_s_batch": len(gs) / t_batch, "graphs_per_s_replay": len(gs) / t_graph,
+            "graphs_per_s_plain": len(gs) / t_plain,
+            "aggregate_gteps_batch": work / t_batch / 1e9,
+            "aggregate_gteps_plain": work / t_plain / 1e9}
+
+
+def c5(args, dawn, torch, np):
+    import graphgen
+    from graphgen import workloads
+    from paper_2306_07872_amd import serve
+    t = time.perf_counter()
+    graphs = [workloads.serving_graph(i, args.c5_max_scale) for i in range(args.c5_graphs)]
+    log(f"c5 {len(graphs)} graphs ({sum(g.m for g in graphs) / 1e6:.0f}M edges, "
+        f"{time.perf_counter() - t:.1f}s)")
+    csrs = [dawn.Csr.from_graph(g) for g in graphs]
+    src_pool = [graphgen.pick_sources(g, 64, 900 + i) for i, g in enumerate(graphs)]
+
+    def requests(nq, seed):
+        u = graphgen.uniform(2 * nq, seed)
+        out = []
+        for j in range(nq):
+            gi = min(int(u[2 * j] * len(graphs)), len(graphs) - 1)
+            pool = src_pool[gi]
+            out.append((gi, int(pool[min(int(u[2 * j + 1] * len(pool)), len(pool) - 1)])))
+        return out
+
+    def new_server():
+        srv = serve.Server(tile_k=args.c5_tile_k, steps_per_tick=args.c5_steps_per_tick,
+                           max_tiles_per_graph=2)
+        for i, c in enumerate(csrs):
+            srv.add_graph(i, c)
+        return srv
+
+    # closed loop: everything submitted at once -> capacity
+    srv = new_server()
+    reqs = requests(args.c5_queries, 5)
+    warm = [srv.submit(gi, s) for gi, s in reqs[:len(graphs)]]
+    srv.run_until_idle()
+    t0 = time.perf_counter()
+    qs = [srv.submit(gi, s) for gi, s in reqs]
+    srv.run_until_idle()
+    cap = len(qs) / (time.perf_counter() - t0)
+    closed = serve.percentiles([q.latency for q in qs])
+    recs = [{"config": "c5_serving_closed_loop", "graphs": len(graphs), "queries": len(qs),
+             "capacity_qps": cap, **closed}]
+    log(f"c5 closed-loop capacity {cap:.1f} queries/s")
+    for frac in args.c5_rates:
+        rate = frac * cap
+        u = graphgen.uniform(args.c5_queries, 17 + int(frac * 100))
+        arr = serve.poisson_arrivals(rate, args.c5_queries, u)
+        res = serve.serve_open_loop(srv, arr, requests(args.c5_queries, 31 + int(frac * 100)))
+        rec = {"config": "c5_serving_poisson", "offered_fraction": frac, "offered_qps": rate, **res}
+        log(f"c5 rate {frac:.2f}x: {rec}")
+        recs.append(rec)
+    srv.close()
+    return recs
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--only", default="c1,c2,c3,c4b,c5")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--c1-reps", type=int, default=1000)
+    ap.add_argument("--c2-scale", type=int, default=22)
+    ap.add_argument("--c2-sources", type=int, default=16)
+    ap.add_argument("--c3-side", type=int, default=2048)
+    ap.add_argument("--c3-sources", type=int, default=8)
+    ap.add_argument("--c4b-graphs", type=int, default=64)
+    ap.add_argument("--c4b-reps", type=int, default=3)
+    ap.add_argument("--c5-graphs", type=int, default=32)
+    ap.add_argument("--c5-max-scale", type=int, default=22)
+    ap.add_argument("--c5-queries", type=int, default=2000)
+    ap.add_argument("--c5-tile-k", type=int, default=64)
+    ap.add_argument("--c5-steps-per-tick", type=int, default=4)
+    ap.add_argument("--c5-rates", default="0.1,0.25,0.5,0.7,0.8,0.9,1.0,1.2")
+    args = ap.parse_args()
+    args.c5_rates = [float(x) for x in args.c5_rates.split(",")]
+    import numpy as np
+    import torch
+
+    import paper_2306_07872_amd as dawn
+    torch.cuda.set_device(0)
+    dawn.load()
+    for name in args.only.split(","):
+        fn = {"c1": c1, "c2": c2, "c3": c3, "c4b": c4b, "c5": c5}[name]
+        log(f"== {name}")
+        t = time.perf_counter()
+        recs = fn(args, dawn, torch, np)
+        for r in (recs if isinstance(recs, list) else [recs]):
+            r["section_s"] = round(time.perf_counter() - t, 1)
+            emit(r, args.out)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

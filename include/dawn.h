@@ -232,13 +232,13 @@ dawn_status dawn_tile_create(dawn_tile** out, const int32_t* rowptr_dev, const i
 dawn_status dawn_tile_admit(dawn_tile* t, int32_t col, int32_t source, hipStream_t stream);
 /* Run up to max_steps GOVM steps for every admitted column (steps stop early
  * on the device once no column is active).  If done_bits_dev is non-NULL it
- * receives k bits (uint32 words, bit j of word j/32) set for admitted columns
- * that have finished. */
+ * receives ceil(k/32) uint32 words (bit j of word j/32) with the bits of
+ * admitted columns that have finished set. */
 dawn_status dawn_tile_run(dawn_tile* t, int32_t max_steps, uint32_t* done_bits_dev,
                           hipStream_t stream);
 /* Copy column col (n distances) to dist_out_dev; valid once the column is done. */
 dawn_status dawn_tile_read(dawn_tile* t, int32_t col, void* dist_out_dev, hipStream_t stream);
-/* Per-column step counts (int32[k]) to steps_out_dev. */
+/* Per-column step counts (int32[k], k as given to dawn_tile_create) to steps_out_dev. */
 dawn_status dawn_tile_steps(dawn_tile* t, int32_t* steps_out_dev, hipStream_t stream);
 /* Cancel the query in column col (its column becomes free). */
 dawn_status dawn_tile_evict(dawn_tile* t, int32_t col, hipStream_t stream);

@@ -655,7 +655,7 @@ extern "C" dawn_status dawn_tile_run(dawn_tile* t, int32_t max_steps, uint32_t* 
   if (max_steps < 1) return set_error(DAWN_E_INVALID, "max_steps must be >= 1");
   dawn_status st = tile_steps(t->A, t->f32, false, max_steps, stream);
   if (st != DAWN_OK) return st;
-  if (done_bits) st = tile_done_bits(t->A, done_bits, stream);
+  if (done_bits) st = tile_done_bits(t->A, t->k, done_bits, stream);
   return st;
 }
 
@@ -668,7 +668,7 @@ extern "C" dawn_status dawn_tile_read(dawn_tile* t, int32_t col, void* dist_out,
 
 extern "C" dawn_status dawn_tile_steps(dawn_tile* t, int32_t* steps_out, hipStream_t stream) {
   if (!t || !steps_out) return set_error(DAWN_E_INVALID, "null pointer");
-  return tile_col_steps(t->A, steps_out, stream);
+  return tile_col_steps(t->A, t->k, steps_out, stream);
 }
 
 extern "C" dawn_status dawn_tile_evict(dawn_tile* t, int32_t col, hipStream_t stream) {

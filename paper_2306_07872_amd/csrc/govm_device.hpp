@@ -77,6 +77,12 @@ __device__ __forceinline__ constexpr uint32_t inf_bits() {
 
 // ---------------------------------------------------------------------------
 // memory-model helpers (agent scope = the whole device, all XCDs)
+//
+// Control state (step counter, done flag, per-step counts and column-activity
+// words) is written by one kernel and read by later, often tiny, kernels that
+// may run on any XCD.  Every such access goes through these agent-scope atomic
+// loads and stores, so no read can be served from a cache line another XCD
+// holds from before the write.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -86,6 +92,23 @@ __device__ __forceinline__ unsigned long long ld_agent64(const unsigned long lon
 }
 __device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent64(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_agent_i(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent_i(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Queue entries are rewritten every step and often read at a wave- or
+// block-uniform address, which a plain load may serve from the scalar cache;
+// these loads always go to the coherent level.
+__device__ __forceinline__ int32_t ld_queue(const int32_t* p) { return ld_agent_i(p); }
+__device__ __forceinline__ int4 ld_queue4(const int4* p) {
+  const int32_t* q = reinterpret_cast<const int32_t*>(p);
+  return make_int4(ld_agent_i(q), ld_agent_i(q + 1), ld_agent_i(q + 2), ld_agent_i(q + 3));
 }
 
 // ---------------------------------------------------------------------------

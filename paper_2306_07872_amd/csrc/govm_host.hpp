@@ -90,12 +90,12 @@ dawn_status tile_evict(const TileArgs& a, int32_t col, hipStream_t stream);
 // Run steps: persistent (all until done) or `max_steps` step launches.
 dawn_status tile_steps(const TileArgs& a, bool f32, bool persistent, int32_t max_steps,
                        hipStream_t stream);
-dawn_status tile_done_bits(const TileArgs& a, uint32_t* done_bits, hipStream_t stream);
+dawn_status tile_done_bits(const TileArgs& a, int32_t k, uint32_t* done_bits, hipStream_t stream);
 dawn_status tile_store(const TileArgs& a, int32_t col0, int32_t count, void* out, int64_t ld,
                        hipStream_t stream);
 dawn_status tile_read_col(const TileArgs& a, int32_t col, void* out, hipStream_t stream);
 dawn_status tile_info(const TileArgs& a, dawn_run_info* info, hipStream_t stream);
-dawn_status tile_col_steps(const TileArgs& a, int32_t* out, hipStream_t stream);
+dawn_status tile_col_steps(const TileArgs& a, int32_t k, int32_t* out, hipStream_t stream);
 
 // Persistent grid sizes (workgroups per CU, total) at `threads` per workgroup.
 void ss_persistent_occupancy(int threads, int* per_cu, int* grid);

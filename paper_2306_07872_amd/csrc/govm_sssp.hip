@@ -66,8 +66,8 @@ __global__ void ss_validate_kernel(const int32_t* rowptr, const int32_t* colidx,
     if (is_f32) bad |= (w[e] & 0x80000000u) != 0 || (w[e] & 0x7F800000u) == 0x7F800000u;
   }
   if (bad) {
-    *converged = -1;
-    *done = 1;
+    st_agent_i(converged, -1);
+    st_agent(done, 1u);
   }
 }
 
@@ -76,7 +76,7 @@ template <bool F32>
 __global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* voff,
                                int32_t count, int32_t single) {
   SsCtl* C = A.ctl;
-  if (C->done) return;
+  if (ld_agent(&C->done)) return;
   for (int j = threadIdx.x; j < count; j += blockDim.x) {
     int64_t s = sources ? (int64_t)sources[j] : (int64_t)single;
     if (voff) s += voff[j];
@@ -107,15 +107,15 @@ __global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* 
 template <bool F32>
 __global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int32_t conv = C->converged;
-  if (C->abort) conv = -2;
-  info->steps = (int32_t)C->step;
+  int32_t conv = ld_agent_i(&C->converged);
+  if (ld_agent(&C->abort)) conv = -2;
+  info->steps = (int32_t)ld_agent(&C->step);
   info->converged = conv;
-  info->frontier_entries = (int64_t)C->fe;
-  info->edges_scanned = (int64_t)C->es;
-  info->improvements = (int64_t)C->im;
-  info->union_rows = (int64_t)C->fe;
-  info->union_edges = (int64_t)C->es;
+  info->frontier_entries = (int64_t)ld_agent64(&C->fe);
+  info->edges_scanned = (int64_t)ld_agent64(&C->es);
+  info->improvements = (int64_t)ld_agent64(&C->im);
+  info->union_rows = (int64_t)ld_agent64(&C->fe);
+  info->union_edges = (int64_t)ld_agent64(&C->es);
 }
 
 // ---------------------------------------------------------------------------
@@ -255,7 +255,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
 
   // workgroup tier: one chunk of one row per workgroup
   for (uint32_t i = gb; i < ng; i += nb) {
-    const int4 r = A.qwg[cur][i];
+    const int4 r = ld_queue4(&A.qwg[cur][i]);
     const int32_t u = r.x, start = r.y, len = r.z;
     const uint32_t du = ld_agent(&A.dist[u]);
     if (threadIdx.x == 0) {
@@ -284,7 +284,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
 
   // wave tier: one wavefront per row
   for (uint32_t i = gw; i < nw; i += nwv) {
-    const int32_t u = A.qwave[cur][i];
+    const int32_t u = ld_queue(&A.qwave[cur][i]);
     const int32_t start = A.rowptr[u], end = A.rowptr[u + 1];
     const uint32_t du = ld_agent(&A.dist[u]);
     if (lane == 0) {
@@ -318,7 +318,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
     int32_t u = 0, start = 0, deg = 0;
     uint32_t du = 0;
     if (has) {
-      u = A.qlane[cur][i];
+      u = ld_queue(&A.qlane[cur][i]);
       start = A.rowptr[u];
       deg = A.rowptr[u + 1] - start;
       du = ld_agent(&A.dist[u]);
@@ -376,11 +376,8 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
 
 __device__ __forceinline__ void ss_zero_rotation(SsCtl* C, uint32_t step) {
   const int rz = (step + 2) % kRot;
-  C->cnt[rz][0] = 0u;
-  C->cnt[rz][1] = 0u;
-  C->cnt[rz][2] = 0u;
-  C->cnt[rz][3] = 0u;
-  C->upd[rz] = 0u;
+  for (int t = 0; t < 4; t++) st_agent(&C->cnt[rz][t], 0u);
+  st_agent(&C->upd[rz], 0u);
 }
 
 // All steps in one launch; a grid barrier separates the steps.  The grid must
@@ -409,10 +406,10 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
   }
   flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    C->step = step;
-    C->converged = status;
-    C->done = 1;
-    C->bar_base = bar_base + epoch * gridDim.x;
+    st_agent(&C->step, step);
+    st_agent_i(&C->converged, status);
+    st_agent(&C->done, 1u);
+    st_agent(&C->bar_base, bar_base + epoch * gridDim.x);
   }
 }
 
@@ -421,23 +418,23 @@ template <bool F32>
 __global__ void __launch_bounds__(1024) ss_step_kernel(SsArgs A) {
   __shared__ SsShared sh;
   SsCtl* C = A.ctl;
-  if (C->done) return;
-  const uint32_t step = C->step;
+  if (ld_agent(&C->done)) return;
+  const uint32_t step = ld_agent(&C->step);
   if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
   Acc acc;
   ss_step<F32>(A, step, blockIdx.x, gridDim.x, acc, sh);
   flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
   if (last_block_done(&C->blocks_done)) {
-    C->blocks_done = 0;
+    st_agent(&C->blocks_done, 0u);
     const uint32_t upd = ld_agent(&C->upd[(step + 1) % kRot]);
     const uint32_t ns = step + 1;
-    C->step = ns;
+    st_agent(&C->step, ns);
     if (!upd) {
-      C->converged = 1;
-      C->done = 1;
+      st_agent_i(&C->converged, 1);
+      st_agent(&C->done, 1u);
     } else if (ns >= (uint32_t)A.n) {
-      C->converged = 0;
-      C->done = 1;
+      st_agent_i(&C->converged, 0);
+      st_agent(&C->done, 1u);
     }
   }
 }

@@ -60,7 +60,7 @@ __device__ void tile_put_source(const TileArgs& A, int32_t col, int32_t s, uint3
   atomicOr(&A.mk[q][(size_t)s * A.nseg + seg], bit);
   atomicOr(&C->colact[rc][seg], bit);
   atomicOr(&C->live[seg], bit);
-  C->colsteps[col] = 0;
+  st_agent_i(&C->colsteps[col], 0);
   const uint32_t vb = 1u << (s & 31);
   if (atomicOr(&A.ubm[cur][s >> 5], vb) & vb) return;  // already in the union frontier
   const int32_t start = A.rowptr[s], deg = A.rowptr[s + 1] - start;
@@ -81,7 +81,7 @@ __device__ void tile_put_source(const TileArgs& A, int32_t col, int32_t s, uint3
 }
 
 __global__ void tile_seed_kernel(TileArgs A, const int32_t* sources, int32_t count) {
-  if (A.ctl->done) return;  // validation failed
+  if (ld_agent(&A.ctl->done)) return;  // validation failed
   // one thread per column; shared words are updated with atomics and the
   // union-bitmap test-and-set picks one thread to queue a repeated source
   for (int32_t j = threadIdx.x; j < count; j += blockDim.x) tile_put_source(A, j, sources[j], 0u);
@@ -97,22 +97,22 @@ __global__ void tile_col_fill_kernel(TileArgs A, int32_t col) {
 __global__ void tile_admit_kernel(TileArgs A, int32_t col, int32_t s) {
   if (threadIdx.x != 0) return;
   TileCtl* C = A.ctl;
-  tile_put_source(A, col, s, C->step);
-  C->done = 0;
-  C->converged = 0;
+  tile_put_source(A, col, s, ld_agent(&C->step));
+  st_agent(&C->done, 0u);
+  st_agent_i(&C->converged, 0);
 }
 
 // Cancel column col: drop its bit from every mask of the current frontier.
 __global__ void tile_evict_kernel(TileArgs A, int32_t col) {
   TileCtl* C = A.ctl;
-  const uint32_t t = C->step;
+  const uint32_t t = ld_agent(&C->step);
   const int q = t % 3, rc = t % kRot;
   const int seg = col >> 6;
   const unsigned long long keep = ~(1ull << (col & 63));
-  const uint32_t nw = C->cnt[rc][1], ng = C->cnt[rc][2];
+  const uint32_t nw = ld_agent(&C->cnt[rc][1]), ng = ld_agent(&C->cnt[rc][2]);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nw + ng; i += stride) {
-    const int32_t u = i < nw ? A.qwave[q][i] : A.qwg[q][i - nw].x;
+    const int32_t u = i < nw ? ld_queue(&A.qwave[q][i]) : ld_queue(&A.qwg[q][i - nw].x);
     atomicAnd(&A.mk[q][(size_t)u * A.nseg + seg], keep);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -288,7 +288,7 @@ __device__ void tile_step(const TileArgs& A, uint32_t step, uint32_t gb, uint32_
     const uint32_t pw = ld_agent(&C->cnt[rp][1]), pg = ld_agent(&C->cnt[rp][2]);
     const uint32_t tot = pw + pg;
     for (uint32_t i = gb * blockDim.x + threadIdx.x; i < tot; i += nb * blockDim.x) {
-      const int32_t u = i < pw ? A.qwave[qp][i] : A.qwg[qp][i - pw].x;
+      const int32_t u = i < pw ? ld_queue(&A.qwave[qp][i]) : ld_queue(&A.qwg[qp][i - pw].x);
       unsigned long long* mp = A.mk[qp] + (size_t)u * nseg;
       for (int s = 0; s < nseg; s++) mp[s] = 0ull;
     }
@@ -298,7 +298,7 @@ __device__ void tile_step(const TileArgs& A, uint32_t step, uint32_t gb, uint32_
   uint32_t* bdu = dyn + (size_t)W * A.K;
   const uint32_t ng = ld_agent(&C->cnt[rc][2]);
   for (uint32_t i = gb; i < ng; i += nb) {
-    const int4 r = A.qwg[q][i];
+    const int4 r = ld_queue4(&A.qwg[q][i]);
     __syncthreads();  // the previous chunk is done with blkmask / bdu
     if ((int)threadIdx.x < nseg) sh.blkmask[threadIdx.x] = A.mk[q][(size_t)r.x * nseg + threadIdx.x];
     for (int c = threadIdx.x; c < A.K; c += blockDim.x) bdu[c] = A.D[(size_t)r.x * A.K + c];
@@ -330,7 +330,7 @@ __device__ void tile_step(const TileArgs& A, uint32_t step, uint32_t gb, uint32_
   unsigned long long* wmask = sh.rowmask[wave];
   uint32_t* wdu = dyn + (size_t)wave * A.K;
   for (uint32_t i = gw; i < nw; i += nwv) {
-    const int32_t u = A.qwave[q][i];
+    const int32_t u = ld_queue(&A.qwave[q][i]);
     const int32_t start = A.rowptr[u], deg = A.rowptr[u + 1] - start;
     unsigned long long x = 0ull;
     if (lane < nseg) x = A.mk[q][(size_t)u * nseg + lane];
@@ -375,10 +375,11 @@ __device__ __forceinline__ void tile_step_prologue(TileCtl* C, uint32_t step, in
   // zero the counters two steps ahead and count this step for active columns
   if (blockIdx.x == 0) {
     const int rz = (step + 2) % kRot, rc = step % kRot;
-    if (threadIdx.x < 4) C->cnt[rz][threadIdx.x] = 0u;
-    if (threadIdx.x < kSegMax) C->colact[rz][threadIdx.x] = 0ull;
+    if (threadIdx.x < 4) st_agent(&C->cnt[rz][threadIdx.x], 0u);
+    if (threadIdx.x < kSegMax) st_agent64(&C->colact[rz][threadIdx.x], 0ull);
     for (int j = threadIdx.x; j < K; j += blockDim.x)
-      if ((C->colact[rc][j >> 6] >> (j & 63)) & 1ull) C->colsteps[j] += 1;
+      if ((ld_agent64(&C->colact[rc][j >> 6]) >> (j & 63)) & 1ull)
+        st_agent_i(&C->colsteps[j], ld_agent_i(&C->colsteps[j]) + 1);
   }
 }
 
@@ -420,11 +421,11 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   }
   flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    C->step = step;
-    C->bar_base = bar_base + epoch * gridDim.x;
+    st_agent(&C->step, step);
+    st_agent(&C->bar_base, bar_base + epoch * gridDim.x);
     if (finished) {
-      C->converged = status;
-      C->done = 1;
+      st_agent_i(&C->converged, status);
+      st_agent(&C->done, 1u);
     }
   }
 }
@@ -435,23 +436,23 @@ __global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap
   __shared__ TileShared sh;
   extern __shared__ uint32_t tile_dyn[];
   TileCtl* C = A.ctl;
-  if (C->done) return;
-  const uint32_t step = C->step;
+  if (ld_agent(&C->done)) return;
+  const uint32_t step = ld_agent(&C->step);
   tile_step_prologue(C, step, A.K);
   Acc acc;
   tile_step<F32>(A, step, blockIdx.x, gridDim.x, acc, sh, tile_dyn);
   flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
   if (last_block_done(&C->blocks_done)) {
-    C->blocks_done = 0;
+    st_agent(&C->blocks_done, 0u);
     const bool act = any_active(C, (step + 1) % kRot, A.nseg);
     const uint32_t ns = step + 1;
-    C->step = ns;
+    st_agent(&C->step, ns);
     if (!act) {
-      C->converged = 1;
-      C->done = 1;
+      st_agent_i(&C->converged, 1);
+      st_agent(&C->done, 1u);
     } else if (cap_n && ns >= (uint32_t)A.n) {
-      C->converged = 0;
-      C->done = 1;
+      st_agent_i(&C->converged, 0);
+      st_agent(&C->done, 1u);
     }
   }
 }
@@ -488,14 +489,15 @@ __global__ void tile_read_col_kernel(const uint32_t* D, int32_t n, int32_t K, in
     out[v] = D[(size_t)v * K + col];
 }
 
-__global__ void tile_done_bits_kernel(const TileCtl* C, int32_t K, uint32_t* done) {
-  const int w = threadIdx.x;  // 32-bit words
-  if (w >= (K + 31) / 32) return;
-  const int rc = C->step % kRot;
+__global__ void tile_done_bits_kernel(const TileCtl* C, int32_t k, uint32_t* done) {
+  const int w = threadIdx.x;  // 32-bit words of the caller's k columns
+  if (w >= (k + 31) / 32) return;
+  const int rc = ld_agent(&C->step) % kRot;
   const int seg = w >> 1, half = (w & 1) * 32;
-  const uint32_t live = (uint32_t)(C->live[seg] >> half);
-  const uint32_t act = (uint32_t)(C->colact[rc][seg] >> half);
-  done[w] = live & ~act;
+  const uint32_t live = (uint32_t)(ld_agent64(&C->live[seg]) >> half);
+  const uint32_t act = (uint32_t)(ld_agent64(&C->colact[rc][seg]) >> half);
+  const uint32_t valid = (w == (k - 1) / 32 && (k & 31)) ? ((1u << (k & 31)) - 1u) : ~0u;
+  done[w] = live & ~act & valid;
 }
 
 __global__ void tile_info_kernel(const TileCtl* C, int32_t K, dawn_run_info* info) {
@@ -503,23 +505,23 @@ __global__ void tile_info_kernel(const TileCtl* C, int32_t K, dawn_run_info* inf
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
   int32_t mx = 0;
-  for (int j = threadIdx.x; j < K; j += blockDim.x) mx = max(mx, C->colsteps[j]);
+  for (int j = threadIdx.x; j < K; j += blockDim.x) mx = max(mx, ld_agent_i(&C->colsteps[j]));
   atomicMax(&s_max, mx);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  int32_t conv = C->converged;
-  if (C->abort) conv = -2;
+  int32_t conv = ld_agent_i(&C->converged);
+  if (ld_agent(&C->abort)) conv = -2;
   info->steps = s_max;
   info->converged = conv;
-  info->frontier_entries = (int64_t)C->sa;
-  info->edges_scanned = (int64_t)C->se;
-  info->improvements = (int64_t)C->im;
-  info->union_rows = (int64_t)C->fe;
-  info->union_edges = (int64_t)C->es;
+  info->frontier_entries = (int64_t)ld_agent64(&C->sa);
+  info->edges_scanned = (int64_t)ld_agent64(&C->se);
+  info->improvements = (int64_t)ld_agent64(&C->im);
+  info->union_rows = (int64_t)ld_agent64(&C->fe);
+  info->union_edges = (int64_t)ld_agent64(&C->es);
 }
 
-__global__ void tile_col_steps_kernel(const TileCtl* C, int32_t K, int32_t* out) {
-  for (int j = threadIdx.x; j < K; j += blockDim.x) out[j] = C->colsteps[j];
+__global__ void tile_col_steps_kernel(const TileCtl* C, int32_t k, int32_t* out) {
+  for (int j = threadIdx.x; j < k; j += blockDim.x) out[j] = ld_agent_i(&C->colsteps[j]);
 }
 
 // ---------------------------------------------------------------------------
@@ -674,8 +676,8 @@ dawn_status tile_steps(const TileArgs& a, bool f32, bool persistent, int32_t max
              : tile_steps_t<false>(a, persistent, max_steps, stream);
 }
 
-dawn_status tile_done_bits(const TileArgs& a, uint32_t* done_bits, hipStream_t stream) {
-  hipLaunchKernelGGL(tile_done_bits_kernel, dim3(1), dim3(64), 0, stream, a.ctl, a.K, done_bits);
+dawn_status tile_done_bits(const TileArgs& a, int32_t k, uint32_t* done_bits, hipStream_t stream) {
+  hipLaunchKernelGGL(tile_done_bits_kernel, dim3(1), dim3(64), 0, stream, a.ctl, k, done_bits);
   return hip_check(hipGetLastError(), "tile done bits");
 }
 
@@ -698,8 +700,8 @@ dawn_status tile_info(const TileArgs& a, dawn_run_info* info, hipStream_t stream
   return hip_check(hipGetLastError(), "tile info");
 }
 
-dawn_status tile_col_steps(const TileArgs& a, int32_t* out, hipStream_t stream) {
-  hipLaunchKernelGGL(tile_col_steps_kernel, dim3(1), dim3(256), 0, stream, a.ctl, a.K, out);
+dawn_status tile_col_steps(const TileArgs& a, int32_t k, int32_t* out, hipStream_t stream) {
+  hipLaunchKernelGGL(tile_col_steps_kernel, dim3(1), dim3(256), 0, stream, a.ctl, k, out);
   return hip_check(hipGetLastError(), "tile steps");
 }
 

@@ -1,0 +1,349 @@
+"""Continuous-batching SSSP server on resident graphs.
+
+Queries (graph id, source) are served from per-graph tile sessions
+(``dawn_tile_*``): a tile holds the distance state of up to `tile_k` queries
+of one graph as the columns of an [n x K] tile in HBM.  The scheduler works in
+ticks:
+
+1. collect: tiles whose last run has finished report their done columns; each
+   finished column is copied out (device -> pinned host) and the column is
+   freed as soon as the copy is enqueued;
+2. admit: waiting queries (FIFO per graph) take free columns of a tile of
+   their graph; a graph without a free column gets a new tile if the HBM
+   budget still holds it, otherwise its queries wait;
+3. run: every tile with live columns that is not already running gets
+   `steps_per_tick` GOVM steps enqueued on its own stream, followed by an
+   asynchronous copy of its done bits and an event.
+
+A tile takes new columns only while no run of it is in flight, so the done
+bits a run reports always belong to columns admitted before that run.
+
+Columns join and leave a running tile between step chunks; the arithmetic of
+a column does not depend on the other columns (different sources never update
+the same path, Section 3.5), so each answer is the same alone and in the mix.
+The host never waits on the device: it polls events.
+
+The executor is pluggable (``tile_factory``) so the scheduling logic can be
+exercised without a GPU; the default executor is the HIP tile session.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import Csr, Tile, dist_dtype, done_columns, tile_bytes
+
+
+@dataclass
+class Query:
+    qid: int
+    gid: int
+    source: int
+    t_arrive: float
+    t_admit: float | None = None
+    t_done: float | None = None
+    state: str = "waiting"        # waiting | running | reading | done | cancelled
+    result: object = None         # host numpy array once done
+    steps: int | None = None
+    _col: int | None = None
+    _tile: object = None
+    _read: object = None
+
+    @property
+    def latency(self) -> float | None:
+        return None if self.t_done is None else self.t_done - self.t_arrive
+
+
+class GpuTileExecutor:
+    """One HIP tile session with its own stream, pinned host buffers and events."""
+
+    def __init__(self, csr: Csr, k: int, device="cuda"):
+        import torch
+        self.torch = torch
+        self.csr = csr
+        self.k = k
+        self.stream = torch.cuda.Stream(device=device)   # default priority
+        with torch.cuda.stream(self.stream):
+            self.tile = Tile(csr, k, stream=self.stream)
+        self.done_host = torch.zeros((k + 31) // 32, dtype=torch.int32, pin_memory=True)
+        self.nbytes = tile_bytes(csr.n, csr.m, k)
+        self._run_event = None
+
+    # -- steps ---------------------------------------------------------------
+    def admit(self, col: int, source: int):
+        self.tile.admit(col, source, stream=self.stream)
+
+    def evict(self, col: int):
+        self.tile.evict(col, stream=self.stream)
+
+    def launch(self, steps: int):
+        torch = self.torch
+        done = self.tile.run(steps, stream=self.stream)
+        with torch.cuda.stream(self.stream):
+            self.done_host.copy_(done, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        self._run_event = ev
+
+    def running(self) -> bool:
+        return self._run_event is not None and not self._run_event.query()
+
+    def finished_run(self) -> bool:
+        return self._run_event is not None and self._run_event.query()
+
+    def idle(self) -> bool:
+        """No run in flight and none waiting to be collected."""
+        return self._run_event is None
+
+    def done_cols(self) -> list[int]:
+        self._run_event = None
+        return done_columns(self.done_host.numpy(), self.k)
+
+    # -- results ---------------------------------------------------------------
+    def read(self, col: int):
+        """Enqueue the copy of column col to pinned host memory; returns a
+        handle with ready() / value()."""
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            dev = self.tile.read(col, stream=self.stream)
+            host = torch.empty(self.csr.n, dtype=dist_dtype(self.csr.wtype), pin_memory=True)
+            host.copy_(dev, non_blocking=True)
+            steps = self.tile.steps(stream=self.stream)
+            steps_host = torch.empty_like(steps, device="cpu", pin_memory=True)
+            steps_host.copy_(steps, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        return _ReadHandle(ev, host, steps_host, col, keep=(dev, steps))
+
+    def close(self):
+        self.stream.synchronize()
+        self.tile.close()
+
+
+class _ReadHandle:
+    def __init__(self, ev, host, steps_host, col, keep):
+        self.ev, self.host, self.steps_host, self.col, self._keep = ev, host, steps_host, col, keep
+
+    def ready(self) -> bool:
+        return self.ev.query()
+
+    def value(self):
+        return self.host.numpy(), int(self.steps_host.numpy()[self.col])
+
+
+class _TileSlot:
+    def __init__(self, gid: int, ex):
+        self.gid = gid
+        self.ex = ex
+        self.free = list(range(ex.k))
+        self.live: dict[int, Query] = {}
+        self.idle_ticks = 0
+
+
+class Server:
+    """Continuous-batching SSSP over resident graphs (see module docstring)."""
+
+    def __init__(self, hbm_budget: int | None = None, tile_k: int = 64, steps_per_tick: int = 4,
+                 max_tiles_per_graph: int = 4, tile_factory=None, clock=time.perf_counter,
+                 device="cuda"):
+        self.graphs: dict[int, Csr] = {}
+        self.tile_k = tile_k
+        self.steps_per_tick = steps_per_tick
+        self.max_tiles_per_graph = max_tiles_per_graph
+        self.device = device
+        self.clock = clock
+        self.tile_factory = tile_factory or (lambda csr, k: GpuTileExecutor(csr, k, device))
+        if hbm_budget is None:
+            import torch
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = int(free * 0.8)
+        self.hbm_budget = int(hbm_budget)
+        self.hbm_used = 0
+        self.tiles: dict[int, list[_TileSlot]] = collections.defaultdict(list)
+        self.waiting: collections.deque[Query] = collections.deque()
+        self.reading: list[Query] = []
+        self.done: list[Query] = []
+        self._next_qid = 0
+        self.refused_tiles = 0
+
+    # -- graphs and queries -------------------------------------------------
+    def add_graph(self, gid: int, csr: Csr):
+        self.graphs[gid] = csr
+
+    def tile_cost(self, gid: int) -> int:
+        c = self.graphs[gid]
+        return tile_bytes(c.n, c.m, self.tile_k)
+
+    def submit(self, gid: int, source: int, t_arrive: float | None = None) -> Query:
+        if gid not in self.graphs:
+            raise KeyError(f"graph {gid} is not resident")
+        if not 0 <= source < self.graphs[gid].n:
+            raise ValueError("source out of range")
+        q = Query(self._next_qid, gid, int(source), self.clock() if t_arrive is None else t_arrive)
+        self._next_qid += 1
+        self.waiting.append(q)
+        return q
+
+    def cancel(self, q: Query):
+        if q.state == "waiting":
+            self.waiting.remove(q)
+            q.state = "cancelled"
+        elif q.state == "running":
+            slot = q._tile
+            slot.ex.evict(q._col)
+            del slot.live[q._col]
+            slot.free.append(q._col)
+            q.state = "cancelled"
+
+    # -- scheduling -----------------------------------------------------------
+    def _collect(self):
+        now = None
+        for gid, slots in self.tiles.items():
+            for slot in slots:
+                if not slot.ex.finished_run():
+                    continue
+                for col in slot.ex.done_cols():
+                    q = slot.live.pop(col, None)
+                    if q is None:
+                        continue
+                    q._read = slot.ex.read(col)
+                    q.state = "reading"
+                    slot.free.append(col)   # the read is enqueued before any later admit
+                    self.reading.append(q)
+        still = []
+        for q in self.reading:
+            if q._read.ready():
+                now = self.clock() if now is None else now
+                q.result, q.steps = q._read.value()
+                q._read = None
+                q.t_done = now
+                q.state = "done"
+                self.done.append(q)
+            else:
+                still.append(q)
+        self.reading = still
+
+    def _slot_for(self, gid: int):
+        # Only tiles with no run in flight take new columns: the done bits of a
+        # run enqueued before an admission must not speak for the new column.
+        for slot in self.tiles[gid]:
+            if slot.free and slot.ex.idle():
+                return slot
+        if len(self.tiles[gid]) >= self.max_tiles_per_graph:
+            return None
+        cost = self.tile_cost(gid)
+        if self.hbm_used + cost > self.hbm_budget:
+            self._reclaim(cost)
+        if self.hbm_used + cost > self.hbm_budget:
+            self.refused_tiles += 1
+            return None
+        slot = _TileSlot(gid, self.tile_factory(self.graphs[gid], self.tile_k))
+        self.hbm_used += cost
+        self.tiles[gid].append(slot)
+        return slot
+
+    def _reclaim(self, need: int):
+        """Destroy idle tiles (no live columns, not running) until `need` fits."""
+        for gid, slots in self.tiles.items():
+            for slot in list(slots):
+                if self.hbm_used + need <= self.hbm_budget:
+                    return
+                if not slot.live and slot.ex.idle() and len(slot.free) == slot.ex.k:
+                    slot.ex.close()
+                    slots.remove(slot)
+                    self.hbm_used -= self.tile_cost(gid)
+
+    def _admit(self):
+        now = self.clock()
+        blocked = set()
+        keep = collections.deque()
+        while self.waiting:
+            q = self.waiting.popleft()
+            if q.gid in blocked:
+                keep.append(q)
+                continue
+            slot = self._slot_for(q.gid)
+            if slot is None:
+                blocked.add(q.gid)
+                keep.append(q)
+                continue
+            col = slot.free.pop(0)
+            slot.ex.admit(col, q.source)
+            slot.live[col] = q
+            q._col, q._tile = col, slot
+            q.state, q.t_admit = "running", now
+        self.waiting = keep
+
+    def _run(self):
+        # a tile is launched again only after its previous run was collected
+        for slots in self.tiles.values():
+            for slot in slots:
+                if slot.live and slot.ex.idle():
+                    slot.ex.launch(self.steps_per_tick)
+
+    def tick(self) -> int:
+        """One scheduling round; returns how many queries finished in it."""
+        before = len(self.done)
+        self._collect()
+        self._admit()
+        self._run()
+        return len(self.done) - before
+
+    def busy(self) -> bool:
+        return bool(self.waiting or self.reading or
+                    any(s.live for slots in self.tiles.values() for s in slots))
+
+    def run_until_idle(self, max_ticks: int = 10_000_000):
+        for _ in range(max_ticks):
+            if not self.busy():
+                return
+            self.tick()
+        raise RuntimeError("server did not drain")
+
+    def close(self):
+        for slots in self.tiles.values():
+            for slot in slots:
+                slot.ex.close()
+        self.tiles.clear()
+        self.hbm_used = 0
+
+
+def poisson_arrivals(rate_per_s: float, count: int, uniforms: np.ndarray) -> np.ndarray:
+    """Arrival times (s) of a Poisson process from `count` uniforms in [0,1)."""
+    gaps = -np.log1p(-uniforms[:count]) / rate_per_s
+    return np.cumsum(gaps)
+
+
+def percentiles(lat_s) -> dict:
+    a = np.asarray(lat_s, dtype=np.float64) * 1e3
+    if a.size == 0:
+        return {"p50_ms": None, "p99_ms": None, "mean_ms": None}
+    return {"p50_ms": float(np.percentile(a, 50)), "p99_ms": float(np.percentile(a, 99)),
+            "mean_ms": float(a.mean())}
+
+
+def serve_open_loop(server: Server, arrivals, requests, clock=time.perf_counter) -> dict:
+    """Replay (time, gid, source) requests against `server` in real time:
+    each request is submitted when its arrival time has passed.  Returns
+    latency percentiles and throughput."""
+    order = np.argsort(arrivals, kind="stable")
+    t0 = clock()
+    i = 0
+    qs = []
+    while i < len(order) or server.busy():
+        now = clock() - t0
+        while i < len(order) and arrivals[order[i]] <= now:
+            gid, src = requests[order[i]]
+            qs.append(server.submit(gid, src, t_arrive=t0 + arrivals[order[i]]))
+            i += 1
+        server.tick()
+    t1 = clock()
+    lat = [q.latency for q in qs if q.state == "done"]
+    out = percentiles(lat)
+    out["completed"] = len(lat)
+    out["queries_per_s"] = len(lat) / (t1 - t0) if t1 > t0 else None
+    out["wall_s"] = t1 - t0
+    return out

@@ -1,0 +1,193 @@
+"""Serving scheduler logic on the CPU, with an oracle-backed fake executor.
+
+The fake stands in for a HIP tile session: a column admitted with source s
+finishes after a number of step launches and then reads back the oracle's
+distances.  The tests check admission by HBM budget, FIFO service, column
+reuse, cancellation, and that a tile never takes a new column while a run of
+it is in flight.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from paper_2306_07872_amd import serve
+
+
+class FakeCsr:
+    def __init__(self, g):
+        self.g = g
+        self.n, self.m, self.wtype = g.n, g.m, g.wtype
+
+
+class FakeRead:
+    def __init__(self, value, steps):
+        self._v, self._s, self.polls = value, steps, 0
+
+    def ready(self):
+        self.polls += 1
+        return self.polls >= 2
+
+    def value(self):
+        return self._v, self._s
+
+
+class FakeExecutor:
+    created = 0
+
+    def __init__(self, csr, k, lag=1):
+        FakeExecutor.created += 1
+        self.csr, self.k, self.lag = csr, k, lag
+        self.nbytes = 1
+        self.cols = {}          # col -> [source, steps left, steps taken]
+        self.run_polls = None
+        self.admit_while_running = 0
+        self.closed = False
+
+    def admit(self, col, source):
+        if self.run_polls is not None:
+            self.admit_while_running += 1
+        need = 1 + (source % 5)
+        self.cols[col] = [source, need, 0]
+
+    def evict(self, col):
+        self.cols.pop(col, None)
+
+    def launch(self, steps):
+        for c in self.cols.values():
+            take = min(steps, c[1])
+            c[1] -= take
+            c[2] += take
+        self.run_polls = 0
+
+    def running(self):
+        if self.run_polls is None:
+            return False
+        self.run_polls += 1
+        return self.run_polls <= self.lag
+
+    def finished_run(self):
+        if self.run_polls is None:
+            return False
+        self.run_polls += 1
+        return self.run_polls > self.lag
+
+    def idle(self):
+        return self.run_polls is None
+
+    def done_cols(self):
+        self.run_polls = None
+        return [col for col, c in self.cols.items() if c[1] == 0]
+
+    def read(self, col):
+        src, _, taken = self.cols.pop(col)
+        d, _ = oracle.sssp(self.csr.g, src)
+        return FakeRead(d, taken)
+
+    def close(self):
+        self.closed = True
+
+
+def make_server(budget, tile_k=4, steps=2, max_tiles=3, lag=1):
+    import itertools
+    ticks = itertools.count()
+    clock = lambda: next(ticks) * 1e-3
+    return serve.Server(hbm_budget=budget, tile_k=tile_k, steps_per_tick=steps,
+                        max_tiles_per_graph=max_tiles,
+                        tile_factory=lambda csr, k: FakeExecutor(csr, k, lag), clock=clock)
+
+
+@pytest.fixture
+def graphs():
+    return [graphgen.er(60, 300, 1 + i, weights="u32" if i % 2 == 0 else "f32lognormal")
+            for i in range(3)]
+
+
+def _patch_cost(srv, cost):
+    srv.tile_cost = lambda gid: cost
+
+
+def test_all_queries_complete_with_oracle_answers(graphs):
+    srv = make_server(budget=10)
+    _patch_cost(srv, 1)
+    for i, g in enumerate(graphs):
+        srv.add_graph(i, FakeCsr(g))
+    rng = np.random.default_rng(0)
+    qs = [srv.submit(int(rng.integers(0, 3)), int(rng.integers(0, 60))) for _ in range(40)]
+    srv.run_until_idle()
+    for q in qs:
+        assert q.state == "done"
+        ref, _ = oracle.sssp(graphs[q.gid], q.source)
+        assert np.array_equal(q.result, ref)
+        assert q.steps == 1 + (q.source % 5)
+        assert q.t_done >= q.t_admit >= q.t_arrive
+
+
+def test_budget_limits_tiles_and_idle_tiles_are_reclaimed(graphs):
+    srv = make_server(budget=1)   # room for one tile at a time
+    _patch_cost(srv, 1)
+    for i, g in enumerate(graphs):
+        srv.add_graph(i, FakeCsr(g))
+    qs = [srv.submit(i % 3, i) for i in range(12)]
+    peak = 0
+    while srv.busy():
+        srv.tick()
+        peak = max(peak, srv.hbm_used)
+        assert srv.hbm_used <= srv.hbm_budget
+    assert peak == 1
+    assert all(q.state == "done" for q in qs)
+    assert srv.refused_tiles > 0
+
+
+def test_fifo_within_a_graph(graphs):
+    srv = make_server(budget=1, tile_k=2, max_tiles=1)
+    _patch_cost(srv, 1)
+    srv.add_graph(0, FakeCsr(graphs[0]))
+    qs = [srv.submit(0, 5 * i) for i in range(8)]   # equal step counts
+    srv.run_until_idle()
+    admit_order = sorted(qs, key=lambda q: (q.t_admit, q.qid))
+    assert [q.qid for q in admit_order] == [q.qid for q in qs]
+
+
+def test_cancel_waiting_and_running(graphs):
+    srv = make_server(budget=1, tile_k=2, max_tiles=1, steps=1)
+    _patch_cost(srv, 1)
+    srv.add_graph(0, FakeCsr(graphs[0]))
+    a = srv.submit(0, 4)    # 5 steps
+    b = srv.submit(0, 9)
+    c = srv.submit(0, 3)    # waits: no free column
+    srv.tick()
+    assert a.state == b.state == "running" and c.state == "waiting"
+    srv.cancel(c)
+    assert c.state == "cancelled"
+    srv.tick()
+    srv.tick()
+    assert a.state == "running"
+    srv.cancel(a)
+    assert a.state == "cancelled"
+    srv.run_until_idle()
+    assert b.state == "done" and a.result is None and c.result is None
+
+
+def test_no_admission_into_a_running_tile(graphs):
+    srv = make_server(budget=5, tile_k=8, max_tiles=1, lag=3)
+    _patch_cost(srv, 1)
+    srv.add_graph(0, FakeCsr(graphs[0]))
+    srv.submit(0, 1)
+    srv.tick()                      # admits and launches
+    for i in range(10):             # arrivals while the run is in flight
+        srv.submit(0, 10 + i)
+        srv.tick()
+    srv.run_until_idle()
+    ex = srv.tiles[0][0].ex
+    assert ex.admit_while_running == 0
+    assert all(q.state == "done" for q in srv.done) and len(srv.done) == 11
+
+
+def test_poisson_arrivals_and_percentiles():
+    u = np.linspace(0.01, 0.99, 1000)
+    t = serve.poisson_arrivals(100.0, 1000, u)
+    assert np.all(np.diff(t) > 0)
+    assert abs(t[-1] / 1000 - 1 / 100.0) < 0.005
+    p = serve.percentiles([0.001, 0.002, 0.003])
+    assert abs(p["p50_ms"] - 2.0) < 1e-9
