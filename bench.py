@@ -65,7 +65,7 @@ def main() -> int:
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--k", type=int, default=256)
     ap.add_argument("--plain", type=int, default=256, help="sources timed one per launch")
-    ap.add_argument("--cpu-sample", type=int, default=32, help="sources timed on the oracle")
+    ap.add_argument("--cpu-sample", type=int, default=256, help="sources timed on the oracle")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
                     help="library tuning field (see dawn_tuning), repeatable")
