@@ -12,13 +12,20 @@ every GOVM step until no source changes, and the transposed store of the
 Printed: ONE JSON line.  value = aggregate GTEPS of the batched call
 (sum over sources of the edges reachable from the source, divided by the
 wall time of a step).  Also: sources/s batched and plain, their ratio, the
-roofline of the dominant kernel (the tile's persistent GOVM kernel, timed
-with HIP events on its own stream) and the CPU oracle's rate on a bounded
-sample of the same sources.
+roofline of the dominant kernel (the tile's relaxation kernel, timed with HIP
+events on its launch stream) and the CPU oracle's rate on a bounded sample of
+the same sources.
+
+roofline.traffic is the relaxation kernel's measured HBM bytes per launch
+(rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by what the counters read for a
+copy of known size), read from the committed counter summary under
+profiles/; it is reported only while the kernel sources, the tuning and the
+workload are the ones the counters were taken with, and is null otherwise.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +35,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "tile_step_kernel_rmat20_k256_traffic.md")
+KERNEL_SOURCES = ("paper_2306_07872_amd/csrc/govm_tile.hip",
+                  "paper_2306_07872_amd/csrc/govm_device.hpp",
+                  "paper_2306_07872_amd/csrc/govm_host.hpp")
+
+
+def kernel_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(tuning: dict, workload: str):
+    """HBM bytes per relaxation launch from the committed counter summary, or
+    None when it was taken with other kernel sources, tuning or workload."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip("`")] = v.strip().strip("`")
+    try:
+        if (fields["kernel_sources_sha256"] != kernel_sources_sha256()
+                or json.loads(fields["tuning"]) != tuning or fields["workload"] != workload):
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -44,16 +85,18 @@ def reach_edges(torch, dist, outdeg, inf):
     return torch.cat(tot).cpu().tolist()
 
 
-def tile_kernel_bytes(info: dict, nseg: int) -> int:
-    """Algorithmic bytes of the tile's GOVM kernel for one launch.
+def tile_kernel_bytes(info: dict, nseg: int, skip: bool) -> int:
+    """Algorithmic bytes of the tile's relaxation kernel over one call.
 
-    per union-frontier row: row bounds 8 B + queue id 4 B + mask read and clear
-      2 * 8 B per 64-source segment;
+    per union-frontier row: row bounds 8 B + queue id 4 B + its mask words read
+      and cleared, 2 * 8 B per 64-source segment (3 * 8 B when the next-step
+      mask is read to skip pairs already lowered again);
     per active (row, source): the source's distance at the row, 4 B;
     per union edge: column id + weight, 8 B;
     per active (edge, source): the target's distance, 4 B;
     per improvement: the new distance, 4 B."""
-    return (info["union_rows"] * (12 + 16 * nseg) + 4 * info["frontier_entries"]
+    per_row = 12 + (24 if skip else 16) * nseg
+    return (info["union_rows"] * per_row + 4 * info["frontier_entries"]
             + 8 * info["union_edges"] + 4 * info["edges_scanned"] + 4 * info["improvements"])
 
 
@@ -156,13 +199,14 @@ def main() -> int:
     # from the device counters of the last call; every call does the same work
     # up to the order of updates inside a step.
     nseg = (min(k, tune["tile_k"]) + 63) // 64
-    kbytes_call = tile_kernel_bytes(inf, nseg)
+    kbytes_call = tile_kernel_bytes(inf, nseg, bool(tune["tile_skip"]))
     avg_kms = k_ms / max(k_launches, 1)
     per_launch_bytes = kbytes_call * args.steps / max(k_launches, 1)
     achieved = per_launch_bytes / (avg_kms * 1e-3) / 1e9
     kname = "tile_step_kernel<false>" if tune["mode"] in (0, 1) else "tile_persistent_kernel<false>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(tune, f"rmat{args.scale}_ef16_u32_k{k}"),
                 "kernel": kname, "kernel_ms": round(avg_kms, 5),
                 "launches_per_step": round(k_launches / args.steps, 2),
                 "algorithmic_bytes": int(per_launch_bytes),

@@ -80,8 +80,13 @@ typedef enum { DAWN_W_U32 = 0, DAWN_W_F32 = 1 } dawn_wtype;
  *   improvements     successful strict decreases of a distance.
  * For a batched call the counters are summed over its sources and `steps` is
  * the largest per-source step count; union_rows / union_edges count the rows
- * and edges the tile actually read (each serving every source active there).
- * For single-source calls they equal frontier_entries / edges_scanned. */
+ * and edges the tile actually read (each serving every source active there);
+ * improvements counts, per step, the (vertex, source) pairs whose distance
+ * the step lowered (two decreases of one pair in one step count once); with
+ * tile_skip = 1 a (row, source) pair lowered again within the step it was to
+ * be expanded in is expanded only in the next step, and is counted there.
+ * For single-source calls union_rows / union_edges equal frontier_entries /
+ * edges_scanned. */
 typedef struct {
   int32_t steps;
   int32_t converged;
@@ -98,7 +103,8 @@ typedef struct {
  *   wave tier      d <= t_wave   one wavefront per row (t_wave >= 64);
  *   workgroup tier d >  t_wave   the row is cut into chunks of t_chunk edges,
  *                                one workgroup per chunk.
- * mode: 0 auto (single source and batches of graphs: 2; tiles: 1), 1 step
+ * mode: 0 auto (single source and batches of graphs: one workgroup when
+ * m <= small_m, else 2; tiles: 1), 1 step
  * launches (one kernel per step; the host checks termination every
  * `host_check` steps, so such a call waits for its stream), 2 one persistent
  * launch for all steps with a grid
@@ -125,6 +131,15 @@ typedef struct {
   int32_t coop;         /* 1 = launch persistent kernels with hipLaunchCooperativeKernel;
                            0 (default) = an ordinary launch of a grid sized to what the
                            device holds at once (half the occupancy query's figure) */
+  int32_t tile_t_group; /* tile rows of out-degree <= this go one per 16-lane group,
+                           0..64, default 8 (0: none) */
+  int32_t tile_skip;    /* 1 (default): in a tile step, a (row, source) pair whose distance
+                           was already lowered again in the same step is not expanded
+                           (it is expanded next step with the lower value); 0: every
+                           pair of the frontier is expanded, as Algorithm 2 states */
+  int32_t small_m;      /* single-source and batch runs with mode 0 and m <= small_m run in
+                           one workgroup, one launch (no grid barrier); default 131072,
+                           0 = never */
 } dawn_tuning;
 
 #define DAWN_TILE_K_MAX 512

@@ -45,7 +45,8 @@ class RunInfo(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
                 ("t_lane", "t_wave", "t_chunk", "wg_threads", "grid", "mode", "host_check",
-                 "tile_k", "tile_t_wave", "tile_t_chunk", "validate", "coop")]
+                 "tile_k", "tile_t_wave", "tile_t_chunk", "validate", "coop", "tile_t_group",
+                 "tile_skip", "small_m")]
 
 
 INFO_BYTES = ctypes.sizeof(RunInfo)

@@ -64,7 +64,9 @@ static bool tuning_ok(const Tuning& t) {
          t.host_check <= 4096 && t.tile_k >= 64 && t.tile_k <= DAWN_TILE_K_MAX &&
          t.tile_k % 64 == 0 && t.tile_t_wave >= 32 && t.tile_t_wave <= 65536 &&
          t.tile_t_chunk >= 64 && t.tile_t_chunk <= 65536 && (t.validate == 0 || t.validate == 1) &&
-         (t.coop == 0 || t.coop == 1);
+         (t.coop == 0 || t.coop == 1) && t.tile_t_group >= 0 && t.tile_t_group <= 64 &&
+         t.tile_t_group < t.tile_t_wave && (t.tile_skip == 0 || t.tile_skip == 1) &&
+         t.small_m >= 0;
 }
 
 static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
@@ -215,6 +217,9 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->tile_t_chunk = t.tile_t_chunk;
   out->validate = t.validate;
   out->coop = t.coop;
+  out->tile_t_group = t.tile_t_group;
+  out->tile_skip = t.tile_skip;
+  out->small_m = t.small_m;
   return DAWN_OK;
 }
 
@@ -233,6 +238,9 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.tile_t_chunk = in->tile_t_chunk;
     t.validate = in->validate;
     t.coop = in->coop;
+    t.tile_t_group = in->tile_t_group;
+    t.tile_skip = in->tile_skip;
+    t.small_m = in->small_m;
   }
   if (!tuning_ok(t)) return set_error(DAWN_E_INVALID, "tuning out of range");
   g_tuning = t;
@@ -674,7 +682,7 @@ extern "C" dawn_status dawn_tile_steps(dawn_tile* t, int32_t* steps_out, hipStre
 extern "C" dawn_status dawn_tile_evict(dawn_tile* t, int32_t col, hipStream_t stream) {
   if (!t) return set_error(DAWN_E_INVALID, "null tile");
   if (col < 0 || col >= t->k) return set_error(DAWN_E_INVALID, "column %d out of range", col);
-  return tile_evict(t->A, col, stream);
+  return tile_evict(t->A, t->f32, col, stream);
 }
 
 extern "C" void dawn_tile_destroy(dawn_tile* t) {

@@ -41,7 +41,7 @@ struct alignas(256) SsCtl {
 };
 
 struct alignas(256) TileCtl {
-  uint32_t cnt[kRot][4];               // [step % 4][tier]: -, wave, workgroup-chunk
+  uint32_t cnt[kRot][4];               // [step % 4][tier]: group, wave, workgroup-chunk
   unsigned long long colact[kRot][kSegMax];  // [step % 4]: columns improved in step-1
   unsigned long long live[kSegMax];    // admitted columns
   uint32_t step, done;
@@ -264,11 +264,12 @@ struct TileArgs {
   const uint32_t* w;
   uint32_t* D;            // [n][K] vertex-major: the K sources of a vertex are contiguous
   int32_t n, m, K, nseg;
-  int32_t t_wave, t_chunk;
+  int32_t t_group, t_wave, t_chunk;
+  int32_t skip;               // skip (row, source) pairs already lowered again this step
   unsigned long long* mk[3];  // per-vertex active-source masks [step % 3][n][nseg]
-  int32_t* qwave[3];          // union frontier, wave tier [step % 3]
+  int32_t* qgrp[3];           // union frontier, 16-lane-group tier [step % 3]
+  int32_t* qwave[3];          // union frontier, wave tier
   int4* qwg[3];               // union frontier, workgroup-chunk records
-  uint32_t* ubm[2];           // union-frontier dedup bitmaps [step % 2]
   uint32_t cap_v, cap_wg;
   TileCtl* ctl;
 };

@@ -23,6 +23,9 @@ struct Tuning {
   int32_t tile_t_chunk = 256;
   int32_t validate = 0;
   int32_t coop = 0;
+  int32_t tile_t_group = 8;
+  int32_t tile_skip = 1;
+  int32_t small_m = 131072;
 };
 
 Tuning& tuning();
@@ -69,9 +72,8 @@ dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, 
 
 // ----- distance tile ---------------------------------------------------------
 struct TileLayout {
-  size_t ctl, info, D, mk[3], qwave[3], qwg[3], ubm[2], total;
+  size_t ctl, info, D, mk[3], qgrp[3], qwave[3], qwg[3], total;
   uint32_t cap_v, cap_wg;
-  int64_t nwords;
   int32_t K, nseg;
 };
 TileLayout tile_layout(int64_t n, int64_t m, int32_t k);
@@ -86,7 +88,7 @@ dawn_status tile_seed_all(const TileArgs& a, const int32_t* sources_dev, int32_t
 // Admit one query into column col (between steps).
 dawn_status tile_admit(const TileArgs& a, bool f32, int32_t col, int32_t source,
                        hipStream_t stream);
-dawn_status tile_evict(const TileArgs& a, int32_t col, hipStream_t stream);
+dawn_status tile_evict(const TileArgs& a, bool f32, int32_t col, hipStream_t stream);
 // Run steps: persistent (all until done) or `max_steps` step launches.
 dawn_status tile_steps(const TileArgs& a, bool f32, bool persistent, int32_t max_steps,
                        hipStream_t stream);

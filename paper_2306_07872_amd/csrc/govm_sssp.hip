@@ -440,6 +440,174 @@ __global__ void __launch_bounds__(1024) ss_step_kernel(SsArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// small graphs: one workgroup runs the whole loop
+//
+// When the edge list is short, a step's work is a few microseconds and the
+// grid barrier between steps (device-scope fences over the L2s of all XCDs)
+// would dominate.  One workgroup then runs init, seeding and every step in a
+// single launch, with a workgroup barrier between steps.  delta is one queue:
+// each wavefront takes 64 rows and deals their edges out to its lanes through
+// an LDS prefix sum of the row lengths (the lane tier's scheme, any degree).
+// Data that one step writes and a later step reads (distances, the beta
+// bitmaps, queue entries) go through device-scope atomics, as in the other
+// kernels; the queue length and the ptr flag live in LDS.
+// ---------------------------------------------------------------------------
+struct SsSmallShared {
+  int stage[kMaxWavesPerBlock * 3 * kWave];  // per wavefront: prefix, row base, distance
+  uint32_t cnt_next, upd;
+};
+
+template <bool F32>
+__global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t* sources,
+                                                        const int64_t* voff, int32_t count,
+                                                        int32_t single, int32_t check_valid,
+                                                        dawn_run_info* info) {
+  __shared__ SsSmallShared sh;
+  SsCtl* C = A.ctl;
+  const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int64_t n = A.n, nwords = (n + 31) / 32;
+  uint32_t step = 0;
+  int32_t status = 1;
+  Acc acc;
+  if (check_valid && ld_agent(&C->done)) {
+    status = -1;
+  } else {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) A.dist[i] = inf_bits<F32>();
+    for (int64_t i = threadIdx.x; i < nwords; i += blockDim.x) {
+      A.bm[0][i] = 0u;
+      A.bm[1][i] = 0u;
+    }
+    if (threadIdx.x == 0) {
+      sh.cnt_next = 0u;
+      sh.upd = 0u;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // seeds: alpha = 0, queued once (a repeated seed finds its bit set)
+    for (int j = threadIdx.x; j < count; j += blockDim.x) {
+      int64_t s = sources ? (int64_t)sources[j] : (int64_t)single;
+      if (voff) s += voff[j];
+      st_agent(&A.dist[s], 0u);
+      const uint32_t bit = 1u << (s & 31);
+      if (atomicOr(&A.bm[0][s >> 5], bit) & bit) continue;
+      st_agent_i(&A.qlane[0][atomicAdd(&sh.cnt_next, 1u)], (int32_t)s);
+    }
+    __syncthreads();
+    uint32_t cnt = sh.cnt_next;
+    __syncthreads();
+    if (threadIdx.x == 0) sh.cnt_next = 0u;
+    __syncthreads();
+    int* l_incl = sh.stage + wave * 3 * kWave;
+    int* l_base = l_incl + kWave;
+    int* l_du = l_base + kWave;
+    for (;;) {
+      const int cur = step & 1, nxt = cur ^ 1;
+      for (uint32_t bi = wave; (uint64_t)bi * kWave < cnt; bi += W) {
+        const uint32_t i = bi * kWave + lane;
+        int32_t u = 0, start = 0, deg = 0;
+        uint32_t du = 0;
+        if (i < cnt) {
+          u = ld_queue(&A.qlane[cur][i]);
+          start = A.rowptr[u];
+          deg = A.rowptr[u + 1] - start;
+          du = ld_agent(&A.dist[u]);
+          st_agent(&A.bm[cur][u >> 5], 0u);
+          if (deg > 0) {
+            acc.fe += 1;
+            acc.es += (unsigned long long)deg;
+          }
+        }
+        const int incl = wave_incl_scan(deg);
+        const int total = __shfl(incl, kWave - 1, kWave);
+        l_incl[lane] = incl;
+        l_base[lane] = start - (incl - deg);
+        l_du[lane] = (int)du;
+        wave_lds_sync();
+        for (int base = 0; base < total; base += kWave * kUnrollLane) {
+          int32_t e[kUnrollLane], v[kUnrollLane];
+          bool ok[kUnrollLane], imp[kUnrollLane];
+          uint32_t d[kUnrollLane];
+#pragma unroll
+          for (int j = 0; j < kUnrollLane; j++) {
+            const int k = base + j * kWave + lane;
+            int owner = 0;  // first lane whose inclusive prefix exceeds k
+#pragma unroll
+            for (int s = 32; s >= 1; s >>= 1)
+              if (l_incl[owner + s - 1] <= k) owner += s;
+            ok[j] = k < total;
+            e[j] = l_base[owner] + k;
+            d[j] = (uint32_t)l_du[owner];
+          }
+          ss_relax_n<F32, kUnrollLane>(A, e, ok, d, imp, v);
+#pragma unroll
+          for (int j = 0; j < kUnrollLane; j++) {
+            bool newv = false;
+            if (imp[j]) {
+              acc.im += 1;
+              sh.upd = 1u;
+              const uint32_t bit = 1u << (v[j] & 31);
+              newv = (atomicOr(&A.bm[nxt][v[j] >> 5], bit) & bit) == 0u;
+            }
+            const unsigned long long b = __ballot(newv);
+            if (b != 0ull) {
+              const int leader = __ffsll((long long)b) - 1;
+              uint32_t pos = 0;
+              if (lane == leader) pos = atomicAdd(&sh.cnt_next, (uint32_t)__popcll(b));
+              pos = __shfl(pos, leader, kWave) + lanes_below(b);
+              if (newv) {
+                if (pos < A.cap_v) st_agent_i(&A.qlane[nxt][pos], v[j]);
+                else atomicOr(&C->overflow, 1u);
+              }
+            }
+          }
+        }
+        wave_lds_sync();
+      }
+      __syncthreads();
+      const uint32_t upd = sh.upd, cn = min(sh.cnt_next, A.cap_v);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        sh.upd = 0u;
+        sh.cnt_next = 0u;
+      }
+      __syncthreads();
+      step++;
+      cnt = cn;
+      if (!upd) { status = 1; break; }
+      if (step >= (uint32_t)A.n) { status = 0; break; }
+    }
+  }
+  // counters, state and run info
+  if (threadIdx.x == 0) {
+    st_agent64(&C->fe, 0ull);
+    st_agent64(&C->es, 0ull);
+    st_agent64(&C->im, 0ull);
+  }
+  __syncthreads();
+  flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (status != -1) {
+      st_agent(&C->step, step);
+      st_agent_i(&C->converged, status);
+      st_agent(&C->done, 1u);
+    }
+    if (info) {
+      info->steps = (int32_t)ld_agent(&C->step);
+      info->converged = ld_agent_i(&C->converged);
+      info->frontier_entries = (int64_t)ld_agent64(&C->fe);
+      info->edges_scanned = (int64_t)ld_agent64(&C->es);
+      info->improvements = (int64_t)ld_agent64(&C->im);
+      info->union_rows = info->frontier_entries;
+      info->union_edges = info->edges_scanned;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 SsLayout ss_layout(int64_t n, int64_t m) {
@@ -487,6 +655,22 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
   const DevInfo& di = dev_info();
   const int threads = T.wg_threads > 0 ? T.wg_threads : 1024;
   const int fill_blocks = (int)std::min<int64_t>(4096, (A.n + 255) / 256 + 1);
+  if (T.mode == 0 && (int64_t)A.m <= (int64_t)T.small_m) {
+    // one workgroup, one launch (after the optional device validation)
+    if (T.validate) {
+      hipLaunchKernelGGL(ss_fill_kernel<F32>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
+                         (int64_t)A.n, A.bm[0], A.bm[1], L.nwords, A.ctl);
+      const int vb = (int)std::min<int64_t>(4096, ((int64_t)A.m + 255) / 256 + 1);
+      hipLaunchKernelGGL(ss_validate_kernel, dim3(vb), dim3(256), 0, stream, rowptr, colidx, A.w,
+                         A.n, A.m, (int32_t)F32, &A.ctl->done, &A.ctl->converged);
+    }
+    void* tk = capture ? nullptr : ktimer_begin(stream);
+    hipLaunchKernelGGL(ss_small_kernel<F32>, dim3(1), dim3(threads), 0, stream, A,
+                       seeds.sources_dev, seeds.voff_dev, seeds.count, seeds.source,
+                       (int32_t)(T.validate != 0), info);
+    ktimer_end(tk, stream, 1);
+    return hip_check(hipGetLastError(), "small-graph launch");
+  }
   hipLaunchKernelGGL(ss_fill_kernel<F32>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
                      (int64_t)A.n, A.bm[0], A.bm[1], L.nwords, A.ctl);
   if (T.validate) {

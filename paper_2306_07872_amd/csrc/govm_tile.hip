@@ -10,27 +10,38 @@
 //
 // Layout: D is vertex-major (the K distances of a vertex are contiguous, 4*K
 // bytes), so for an edge (u, v) the active sources of one 64-column segment
-// are served by 16 lanes loading 16 bytes each from D[u] and D[v] -- two
-// coalesced 256-byte reads per (edge, segment) -- and segments with no active
-// source at u are skipped.  Improvements use atomicMin per element; the
-// 16 lanes OR their improvement bits into one 64-bit word that is atomically
-// OR-ed into v's next-step mask, and the first improvement of v in a step
-// appends v to the next union frontier (bitmap dedup + wavefront ballot).
+// are served by 16 lanes loading 16 bytes each from D[v] -- one coalesced
+// 256-byte read per (edge, segment) -- and segments with no active source at u
+// are skipped.
 //
-// Buffers rotate with the step: masks and queues over three slots (a slot is
-// cleared one step after it was read), the union dedup bitmap over two,
-// per-step counters and column-activity words over four.
+// A step is two launches:
+//  1. compaction: every vertex with a mask bit in the step's slot joins the
+//     union frontier, binned by out-degree into a 16-lane-group tier, a
+//     wavefront tier and workgroup chunks;
+//  2. relaxation: for each frontier row and active segment, lanes hold the
+//     row's distances of their 4 sources in registers and stream the row's
+//     edges, 4 edges in flight per 16-lane group.  A candidate below the
+//     target's distance (read with a plain load) is written with a
+//     non-returning atomicMin and sets the target's bit in the next step's
+//     mask.  No lane waits for an atomic: the plain value read is at least
+//     the value just before the atomic (distances only decrease), so every
+//     real improvement sets its bit; when another lane got there first, that
+//     lane set the bit too.
+// Masks and queues rotate over three slots (a slot is cleared one step after
+// it was read), per-step counters and column-activity words over four.
 #include <algorithm>
 
 #include "govm_host.hpp"
 
 namespace dawn {
 
+constexpr int kTileU = 4;  // edges in flight per 16-lane group
+
 // ---------------------------------------------------------------------------
 // reset / seed / admit / evict
 // ---------------------------------------------------------------------------
 template <bool F32>
-__global__ void tile_fill_kernel(TileArgs A, int64_t nwords) {
+__global__ void tile_fill_kernel(TileArgs A) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t nd4 = (int64_t)A.n * A.K / 4;
@@ -40,50 +51,27 @@ __global__ void tile_fill_kernel(TileArgs A, int64_t nwords) {
   const int64_t nm = (int64_t)A.n * A.nseg;
   for (int r = 0; r < 3; r++)
     for (int64_t i = tid; i < nm; i += stride) A.mk[r][i] = 0ull;
-  for (int64_t i = tid; i < nwords; i += stride) {
-    A.ubm[0][i] = 0u;
-    A.ubm[1][i] = 0u;
-  }
   if (blockIdx.x == 0) {
     uint32_t* c = reinterpret_cast<uint32_t*>(A.ctl);
     for (int i = threadIdx.x; i < (int)(sizeof(TileCtl) / 4); i += blockDim.x) c[i] = 0u;
   }
 }
 
-// Put source s into column col at step `t` (the next step to run).
+// Put source s into column col before step t (the next step to run): alpha = 0
+// at s and s active for col; the compaction of step t picks s up.
 __device__ void tile_put_source(const TileArgs& A, int32_t col, int32_t s, uint32_t t) {
   TileCtl* C = A.ctl;
-  const int q = t % 3, rc = t % kRot, cur = t & 1;
   const int seg = col >> 6;
   const unsigned long long bit = 1ull << (col & 63);
   A.D[(size_t)s * A.K + col] = 0u;
-  atomicOr(&A.mk[q][(size_t)s * A.nseg + seg], bit);
-  atomicOr(&C->colact[rc][seg], bit);
+  atomicOr(&A.mk[t % 3][(size_t)s * A.nseg + seg], bit);
+  atomicOr(&C->colact[t % kRot][seg], bit);
   atomicOr(&C->live[seg], bit);
   st_agent_i(&C->colsteps[col], 0);
-  const uint32_t vb = 1u << (s & 31);
-  if (atomicOr(&A.ubm[cur][s >> 5], vb) & vb) return;  // already in the union frontier
-  const int32_t start = A.rowptr[s], deg = A.rowptr[s + 1] - start;
-  if (deg == 0) return;
-  if (deg <= A.t_wave) {
-    const uint32_t p = atomicAdd(&C->cnt[rc][1], 1u);
-    if (p < A.cap_v) A.qwave[q][p] = s;
-    else atomicOr(&C->overflow, 1u);
-  } else {
-    const uint32_t nch = (uint32_t)((deg + A.t_chunk - 1) / A.t_chunk);
-    const uint32_t p = atomicAdd(&C->cnt[rc][2], nch);
-    for (uint32_t c = 0; c < nch; c++) {
-      const int32_t off = (int32_t)c * A.t_chunk;
-      if (p + c < A.cap_wg) A.qwg[q][p + c] = make_int4(s, start + off, min(A.t_chunk, deg - off), c == 0);
-      else atomicOr(&C->overflow, 1u);
-    }
-  }
 }
 
 __global__ void tile_seed_kernel(TileArgs A, const int32_t* sources, int32_t count) {
   if (ld_agent(&A.ctl->done)) return;  // validation failed
-  // one thread per column; shared words are updated with atomics and the
-  // union-bitmap test-and-set picks one thread to queue a repeated source
   for (int32_t j = threadIdx.x; j < count; j += blockDim.x) tile_put_source(A, j, sources[j], 0u);
 }
 
@@ -102,285 +90,284 @@ __global__ void tile_admit_kernel(TileArgs A, int32_t col, int32_t s) {
   st_agent_i(&C->converged, 0);
 }
 
-// Cancel column col: drop its bit from every mask of the current frontier.
+// Cancel column col.  Its distances were just reset to INF (tile_col_fill),
+// so whatever mask bits it still has produce no candidate below INF and the
+// column falls silent within one step; here it leaves the live and active sets.
 __global__ void tile_evict_kernel(TileArgs A, int32_t col) {
+  if (threadIdx.x != 0) return;
   TileCtl* C = A.ctl;
   const uint32_t t = ld_agent(&C->step);
-  const int q = t % 3, rc = t % kRot;
-  const int seg = col >> 6;
   const unsigned long long keep = ~(1ull << (col & 63));
-  const uint32_t nw = ld_agent(&C->cnt[rc][1]), ng = ld_agent(&C->cnt[rc][2]);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nw + ng; i += stride) {
-    const int32_t u = i < nw ? ld_queue(&A.qwave[q][i]) : ld_queue(&A.qwg[q][i - nw].x);
-    atomicAnd(&A.mk[q][(size_t)u * A.nseg + seg], keep);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    atomicAnd(&C->colact[rc][seg], keep);
-    atomicAnd(&C->live[seg], keep);
-  }
+  atomicAnd(&C->colact[t % kRot][col >> 6], keep);
+  atomicAnd(&C->live[col >> 6], keep);
 }
 
 // ---------------------------------------------------------------------------
-// one step
+// compaction: masks of the step -> union-frontier queues
 // ---------------------------------------------------------------------------
-constexpr int kTileLdsQ = 1024;  // next union-frontier entries gathered per workgroup
-constexpr int kTileUnroll = 2;   // (edge, segment) units in flight per 16-lane group
-
-// Dynamic LDS of a tile launch: the distances of each wavefront's current row
-// (K words per wavefront) and of the workgroup's current chunk row (K words).
-__host__ __device__ inline size_t tile_dyn_lds(int K, int waves) {
-  return (size_t)(waves + 1) * (size_t)K * 4u;
+__device__ __forceinline__ void tile_prologue(TileCtl* C, uint32_t step, int K) {
+  // zero the counters of the next step and count this step for active columns
+  const int rz = (step + 1) % kRot, rc = step % kRot;
+  if (threadIdx.x < 4) st_agent(&C->cnt[rz][threadIdx.x], 0u);
+  if (threadIdx.x < kSegMax) st_agent64(&C->colact[rz][threadIdx.x], 0ull);
+  for (int j = threadIdx.x; j < K; j += blockDim.x)
+    if ((ld_agent64(&C->colact[rc][j >> 6]) >> (j & 63)) & 1ull)
+      st_agent_i(&C->colsteps[j], ld_agent_i(&C->colsteps[j]) + 1);
 }
 
-struct TileShared {
-  unsigned long long rowmask[kMaxWavesPerBlock][kSegMax];  // masks of each wave's row
-  unsigned long long blkmask[kSegMax];                     // masks of the workgroup's chunk
-  unsigned long long colact[kSegMax];                      // columns improved (this workgroup)
-  int32_t q[kTileLdsQ];
-  uint32_t nq, gbase;
-};
-
-__device__ __forceinline__ void tile_block_push(bool pred, int32_t v, TileShared& sh,
-                                                int32_t* gq, uint32_t* gcnt, uint32_t gcap,
-                                                uint32_t* overflow) {
-  const unsigned long long b = __ballot(pred);
-  if (b == 0) return;
-  const int leader = __ffsll((long long)b) - 1;
-  uint32_t base = 0;
-  if (lane_id() == leader) base = atomicAdd(&sh.nq, (uint32_t)__popcll(b));
-  base = __shfl(base, leader, kWave);
-  const uint32_t pos = base + lanes_below(b);
-  const bool spill = pred && pos >= (uint32_t)kTileLdsQ;
-  if (pred && !spill) sh.q[pos] = v;
-  wave_push(spill, v, gq, gcnt, gcap, overflow);
-}
-
-template <bool F32>
-__device__ __forceinline__ void tile_enqueue(const TileArgs& A, bool newv, int32_t v, int qn,
-                                             int rn, TileShared& sh) {
+// Counts, from step 1 on, the (vertex, source) pairs whose distance the
+// previous step lowered (a pair lowered twice in one step counts once).
+__device__ __forceinline__ void tile_compact(const TileArgs& A, uint32_t step, uint32_t gb,
+                                             uint32_t nb, Acc& acc) {
   TileCtl* C = A.ctl;
-  int32_t start = 0, deg = 0;
-  if (newv) {
-    start = A.rowptr[v];
-    deg = A.rowptr[v + 1] - start;
-  }
-  const bool tw = newv && deg > 0 && deg <= A.t_wave;
-  const bool tg = newv && deg > A.t_wave;
-  tile_block_push(tw, v, sh, A.qwave[qn], &C->cnt[rn][1], A.cap_v, &C->overflow);
-  if (tg) {
-    const uint32_t nch = (uint32_t)((deg + A.t_chunk - 1) / A.t_chunk);
-    const uint32_t base = atomicAdd(&C->cnt[rn][2], nch);
-    for (uint32_t c = 0; c < nch; c++) {
-      const int32_t off = (int32_t)c * A.t_chunk;
-      if (base + c < A.cap_wg)
-        A.qwg[qn][base + c] = make_int4(v, start + off, min(A.t_chunk, deg - off), c == 0);
-      else
-        atomicOr(&C->overflow, 1u);
+  const int q = step % 3, rc = step % kRot;
+  const int nseg = A.nseg;
+  const int64_t n = A.n;
+  for (int64_t v0 = (int64_t)gb * blockDim.x; v0 < n; v0 += (int64_t)nb * blockDim.x) {
+    const int64_t v = v0 + threadIdx.x;
+    unsigned long long* mp = A.mk[q] + v * nseg;
+    unsigned long long any = 0ull;
+    uint32_t pairs = 0u;
+    if (v < n)
+      for (int s = 0; s < nseg; s++) {
+        const unsigned long long x = mp[s];
+        any |= x;
+        pairs += (uint32_t)__popcll(x);
+      }
+    if (step > 0) acc.im += pairs;
+    int32_t start = 0, deg = 0;
+    if (any) {
+      start = A.rowptr[v];
+      deg = A.rowptr[v + 1] - start;
+      if (deg == 0)  // nothing to expand: the row never enters a queue
+        for (int s = 0; s < nseg; s++) mp[s] = 0ull;
+    }
+    const bool tg = any && deg > 0 && deg <= A.t_group;
+    const bool tw = any && deg > A.t_group && deg <= A.t_wave;
+    wave_push(tg, (int32_t)v, A.qgrp[q], &C->cnt[rc][0], A.cap_v, &C->overflow);
+    wave_push(tw, (int32_t)v, A.qwave[q], &C->cnt[rc][1], A.cap_v, &C->overflow);
+    if (any && deg > A.t_wave) {
+      const uint32_t nch = (uint32_t)((deg + A.t_chunk - 1) / A.t_chunk);
+      const uint32_t base = atomicAdd(&C->cnt[rc][2], nch);
+      for (uint32_t c = 0; c < nch; c++) {
+        const int32_t off = (int32_t)c * A.t_chunk;
+        if (base + c < A.cap_wg)
+          A.qwg[q][base + c] = make_int4((int32_t)v, start + off, min(A.t_chunk, deg - off), c == 0);
+        else
+          atomicOr(&C->overflow, 1u);
+      }
     }
   }
 }
 
+// ---------------------------------------------------------------------------
+// relaxation
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t elem4(const uint4& x, int i) {
   return i == 0 ? x.x : i == 1 ? x.y : i == 2 ? x.z : x.w;
 }
 
-// Process the (edge, active segment) units of edges [start, start+len) of row
-// u, whose masks are in `rowmask` (LDS).  `ngroups` groups of 16 lanes
-// cooperate (a wavefront: 4; a workgroup: blockDim/16); `gidx` is this lane's
-// group, j16 its lane in the group.  The loop count is uniform over the
-// cooperating lanes.  Each lane covers 4 consecutive sources of a segment.
+// Relax edges [start, start+len) of one frontier row for the 4 sources of
+// segment sg that this lane covers (`bits`; `du` = the row's distances of
+// those sources).  `ngroups` 16-lane groups share the row; this lane's group
+// is `gidx`.  The loop count is uniform within a group.
 template <bool F32>
-__device__ __forceinline__ void tile_units(const TileArgs& A, int32_t start, int32_t len,
-                                           const unsigned long long* rowmask,
-                                           const uint32_t* rowdu, uint32_t actseg, int nact,
-                                           int gidx, int ngroups, int qn, int rn, int nxt,
-                                           Acc& acc, TileShared& sh) {
-  constexpr int U = kTileUnroll;
+__device__ __forceinline__ void tile_seg_relax(const TileArgs& A, int32_t start, int32_t len,
+                                               int sg, uint32_t bits, const uint4& du, int gidx,
+                                               int ngroups, unsigned long long* mk_next,
+                                               unsigned long long* sh_colact, Acc& acc) {
+  constexpr int U = kTileU;
   const int j16 = threadIdx.x & 15;
-  const uint32_t units = (uint32_t)len * (uint32_t)nact;
-  for (uint32_t ub = 0; ub < units; ub += (uint32_t)(ngroups * U)) {
+  const int col = sg * 64 + 4 * j16;
+  const int K = A.K, nseg = A.nseg;
+  for (int32_t e0 = gidx * U; e0 < len; e0 += ngroups * U) {
     int32_t v[U];
-    int sg[U];
-    uint32_t w[U], bits[U];
+    uint32_t w[U];
 #pragma unroll
     for (int i = 0; i < U; i++) {
-      const uint32_t unit = ub + (uint32_t)(i * ngroups + gidx);
-      v[i] = 0;
-      sg[i] = 0;
+      const int32_t e = e0 + i;
+      v[i] = -1;
       w[i] = 0u;
-      bits[i] = 0u;
-      if (unit < units) {
-        const uint32_t eo = unit / (uint32_t)nact;
-        uint32_t si = unit - eo * (uint32_t)nact;
-        uint32_t am = actseg;
-        while (si--) am &= am - 1u;
-        sg[i] = __ffs(am) - 1;
-        const int32_t e = start + (int32_t)eo;
-        v[i] = A.colidx[e];
-        w[i] = A.w[e];
-        bits[i] = (uint32_t)(rowmask[sg[i]] >> (4 * j16)) & 0xFu;
+      if (e < len) {
+        v[i] = A.colidx[start + e];
+        w[i] = A.w[start + e];
       }
     }
-    uint4 du[U], dv[U];
+    uint4 dv[U];
 #pragma unroll
     for (int i = 0; i < U; i++) {
-      if (bits[i]) {
-        const int col = sg[i] * 64 + 4 * j16;
-        du[i] = *reinterpret_cast<const uint4*>(rowdu + col);
-        dv[i] = *reinterpret_cast<const uint4*>(A.D + (size_t)v[i] * A.K + col);
-      } else {
-        du[i] = make_uint4(0u, 0u, 0u, 0u);
-        dv[i] = du[i];
-      }
+      dv[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (v[i] >= 0 && bits) dv[i] = *reinterpret_cast<const uint4*>(A.D + (size_t)v[i] * K + col);
     }
-    uint32_t imp[U];
 #pragma unroll
     for (int i = 0; i < U; i++) {
-      imp[i] = 0u;
-      const size_t ov = (size_t)v[i] * A.K + sg[i] * 64 + 4 * j16;
+      uint32_t imp = 0u;
+      if (v[i] >= 0) {
+        uint32_t* dp = A.D + (size_t)v[i] * K + col;
 #pragma unroll
-      for (int t = 0; t < 4; t++) {
-        if ((bits[i] >> t) & 1u) {
-          const uint32_t c = relax_add<F32>(elem4(du[i], t), w[i]);
-          if (c < elem4(dv[i], t) && c < atomicMin(&A.D[ov + t], c)) imp[i] |= 1u << t;
+        for (int t = 0; t < 4; t++) {
+          if ((bits >> t) & 1u) {
+            const uint32_t c = relax_add<F32>(elem4(du, t), w[i]);
+            if (c < elem4(dv[i], t)) {
+              atomicMin(dp + t, c);  // result unused: a non-returning atomic
+              imp |= 1u << t;
+            }
+          }
         }
       }
-    }
-    bool newv[U];
-#pragma unroll
-    for (int i = 0; i < U; i++) {
-      unsigned long long x = (unsigned long long)imp[i] << (4 * j16);
-      x |= __shfl_xor(x, 1, kWave);
-      x |= __shfl_xor(x, 2, kWave);
-      x |= __shfl_xor(x, 4, kWave);
-      x |= __shfl_xor(x, 8, kWave);
-      newv[i] = false;
+      unsigned long long x = (unsigned long long)imp << (4 * j16);
+      x |= __shfl_xor(x, 1, 16);
+      x |= __shfl_xor(x, 2, 16);
+      x |= __shfl_xor(x, 4, 16);
+      x |= __shfl_xor(x, 8, 16);
       if (j16 == 0 && x != 0ull) {
-        atomicOr(&A.mk[qn][(size_t)v[i] * A.nseg + sg[i]], x);
-        atomicOr(&sh.colact[sg[i]], x);
-        acc.im += (unsigned long long)__popcll(x);
-        const uint32_t vb = 1u << (v[i] & 31);
-        newv[i] = (atomicOr(&A.ubm[nxt][v[i] >> 5], vb) & vb) == 0u;
+        atomicOr(mk_next + (size_t)v[i] * nseg + sg, x);
+        atomicOr(&sh_colact[sg], x);
       }
     }
-#pragma unroll
-    for (int i = 0; i < U; i++) tile_enqueue<F32>(A, newv[i], v[i], qn, rn, sh);
   }
 }
 
+// Active-source mask word `s` of row u for this step; with skipping, minus the
+// sources whose alpha[u] was already lowered again in this step (they are in
+// the next step's mask and are expanded then, with the lower value).  The next
+// mask was cleared before this step began (an earlier launch, or before a grid
+// barrier), so a plain load returns only bits set in this step, or misses some
+// of them -- which only means expanding a pair that could have waited.
+__device__ __forceinline__ unsigned long long tile_row_mask(const TileArgs& A, int q, int qn,
+                                                            int32_t u, int s) {
+  const size_t i = (size_t)u * A.nseg + s;
+  unsigned long long x = A.mk[q][i];
+  if (A.skip && x) x &= ~A.mk[qn][i];
+  return x;
+}
+
 template <bool F32>
-__device__ void tile_step(const TileArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
-                          TileShared& sh, uint32_t* dyn) {
+__device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
+                           unsigned long long* sh_colact) {
   const int q = step % 3, qn = (step + 1) % 3, qp = (step + 2) % 3;
-  const int cur = step & 1, nxt = cur ^ 1;
   const int rc = step % kRot, rn = (step + 1) % kRot, rp = (step + 3) % kRot;
   TileCtl* C = A.ctl;
   const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int j16 = lane & 15, gbase = lane & 48;
   const uint32_t gw = gb * W + wave, nwv = nb * W;
   const int nseg = A.nseg;
-  if (threadIdx.x < kSegMax) sh.colact[threadIdx.x] = 0ull;
-  if (threadIdx.x == 0) sh.nq = 0u;
+  unsigned long long* mkn = A.mk[qn];
+  if (threadIdx.x < kSegMax) sh_colact[threadIdx.x] = 0ull;
   __syncthreads();
 
   // (a) clear the masks of the previous step's frontier (read one step ago)
   {
-    const uint32_t pw = ld_agent(&C->cnt[rp][1]), pg = ld_agent(&C->cnt[rp][2]);
-    const uint32_t tot = pw + pg;
+    const uint32_t pg = min(ld_agent(&C->cnt[rp][0]), A.cap_v);
+    const uint32_t pw = min(ld_agent(&C->cnt[rp][1]), A.cap_v);
+    const uint32_t pc = min(ld_agent(&C->cnt[rp][2]), A.cap_wg);
+    const uint32_t tot = pg + pw + pc;
     for (uint32_t i = gb * blockDim.x + threadIdx.x; i < tot; i += nb * blockDim.x) {
-      const int32_t u = i < pw ? ld_queue(&A.qwave[qp][i]) : ld_queue(&A.qwg[qp][i - pw].x);
-      unsigned long long* mp = A.mk[qp] + (size_t)u * nseg;
-      for (int s = 0; s < nseg; s++) mp[s] = 0ull;
+      int32_t u;
+      bool first = true;
+      if (i < pg) {
+        u = ld_queue(&A.qgrp[qp][i]);
+      } else if (i < pg + pw) {
+        u = ld_queue(&A.qwave[qp][i - pg]);
+      } else {
+        const int4 r = ld_queue4(&A.qwg[qp][i - pg - pw]);
+        u = r.x;
+        first = r.w != 0;
+      }
+      if (first) {
+        unsigned long long* mp = A.mk[qp] + (size_t)u * nseg;
+        for (int s = 0; s < nseg; s++) mp[s] = 0ull;
+      }
     }
   }
 
-  // (b) workgroup tier: one chunk of a long row per workgroup
-  uint32_t* bdu = dyn + (size_t)W * A.K;
-  const uint32_t ng = ld_agent(&C->cnt[rc][2]);
-  for (uint32_t i = gb; i < ng; i += nb) {
+  // (b) workgroup tier: the 16-lane groups of the workgroup share a chunk
+  const uint32_t nc = min(ld_agent(&C->cnt[rc][2]), A.cap_wg);
+  for (uint32_t i = gb; i < nc; i += nb) {
     const int4 r = ld_queue4(&A.qwg[q][i]);
-    __syncthreads();  // the previous chunk is done with blkmask / bdu
-    if ((int)threadIdx.x < nseg) sh.blkmask[threadIdx.x] = A.mk[q][(size_t)r.x * nseg + threadIdx.x];
-    for (int c = threadIdx.x; c < A.K; c += blockDim.x) bdu[c] = A.D[(size_t)r.x * A.K + c];
-    __syncthreads();
-    uint32_t act = 0u;
-    int nsrc = 0;
-    for (int s = 0; s < nseg; s++) {
-      const unsigned long long x = sh.blkmask[s];
-      if (x) {
-        act |= 1u << s;
-        nsrc += __popcll(x);
-      }
-    }
+    const unsigned long long x = lane < nseg ? tile_row_mask(A, q, qn, r.x, lane) : 0ull;
+    const uint32_t act = (uint32_t)__ballot(x != 0ull);
+    if (act == 0u) continue;
+    int ns = __popcll(x);
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) ns += __shfl_xor(ns, off, kWave);
     if (threadIdx.x == 0) {
       acc.es += (unsigned long long)r.z;
-      acc.se += (unsigned long long)r.z * (unsigned long long)nsrc;
+      acc.se += (unsigned long long)r.z * (unsigned long long)ns;
       if (r.w) {
-        A.ubm[cur][r.x >> 5] = 0u;
         acc.fe += 1;
-        acc.sa += (unsigned long long)nsrc;
+        acc.sa += (unsigned long long)ns;
       }
     }
-    tile_units<F32>(A, r.y, r.z, sh.blkmask, bdu, act, __popc(act), threadIdx.x >> 4,
-                    blockDim.x >> 4, qn, rn, nxt, acc, sh);
+    for (uint32_t a = act; a; a &= a - 1u) {
+      const int sg = __ffs(a) - 1;
+      const unsigned long long xs = __shfl(x, sg);
+      const uint32_t bits = (uint32_t)(xs >> (4 * j16)) & 0xFu;
+      uint4 du = make_uint4(0u, 0u, 0u, 0u);
+      if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)r.x * A.K + sg * 64 + 4 * j16);
+      tile_seg_relax<F32>(A, r.y, r.z, sg, bits, du, threadIdx.x >> 4, blockDim.x >> 4, mkn,
+                          sh_colact, acc);
+    }
   }
 
-  // (c) wave tier: one wavefront per row
-  const uint32_t nw = ld_agent(&C->cnt[rc][1]);
-  unsigned long long* wmask = sh.rowmask[wave];
-  uint32_t* wdu = dyn + (size_t)wave * A.K;
+  // (c) wave tier: one wavefront per row, its 4 groups share the row
+  const uint32_t nw = min(ld_agent(&C->cnt[rc][1]), A.cap_v);
   for (uint32_t i = gw; i < nw; i += nwv) {
     const int32_t u = ld_queue(&A.qwave[q][i]);
     const int32_t start = A.rowptr[u], deg = A.rowptr[u + 1] - start;
-    unsigned long long x = 0ull;
-    if (lane < nseg) x = A.mk[q][(size_t)u * nseg + lane];
-    const unsigned long long actb = __ballot(x != 0ull);
-    const int cnt = __popcll(x);
-    int nsrc = cnt;
+    const unsigned long long x = lane < nseg ? tile_row_mask(A, q, qn, u, lane) : 0ull;
+    const uint32_t act = (uint32_t)__ballot(x != 0ull);
+    if (act == 0u) continue;
+    int ns = __popcll(x);
 #pragma unroll
-    for (int off = 4; off > 0; off >>= 1) nsrc += __shfl_xor(nsrc, off, kWave);
-    nsrc = __shfl(nsrc, 0, kWave);
-    if (lane < nseg) wmask[lane] = x;
-    const uint32_t act = (uint32_t)actb & 0xFFu;
-    for (int sgm = 0; sgm < nseg; sgm++)
-      if ((act >> sgm) & 1u) wdu[sgm * 64 + lane] = A.D[(size_t)u * A.K + sgm * 64 + lane];
-    wave_lds_sync();
+    for (int off = 4; off > 0; off >>= 1) ns += __shfl_xor(ns, off, kWave);
     if (lane == 0) {
-      A.ubm[cur][u >> 5] = 0u;
       acc.fe += 1;
       acc.es += (unsigned long long)deg;
-      acc.sa += (unsigned long long)nsrc;
-      acc.se += (unsigned long long)deg * (unsigned long long)nsrc;
+      acc.sa += (unsigned long long)ns;
+      acc.se += (unsigned long long)deg * (unsigned long long)ns;
     }
-    tile_units<F32>(A, start, deg, wmask, wdu, act, __popc(act), lane >> 4, kWave / 16, qn, rn,
-                    nxt, acc, sh);
-    wave_lds_sync();
+    for (uint32_t a = act; a; a &= a - 1u) {
+      const int sg = __ffs(a) - 1;
+      const unsigned long long xs = __shfl(x, sg);
+      const uint32_t bits = (uint32_t)(xs >> (4 * j16)) & 0xFu;
+      uint4 du = make_uint4(0u, 0u, 0u, 0u);
+      if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)u * A.K + sg * 64 + 4 * j16);
+      tile_seg_relax<F32>(A, start, deg, sg, bits, du, lane >> 4, 4, mkn, sh_colact, acc);
+    }
   }
 
-  // (d) publish the workgroup's next-frontier entries and column activity
-  __syncthreads();
-  const uint32_t n_q = min(sh.nq, (uint32_t)kTileLdsQ);
-  if (threadIdx.x == 0 && n_q) sh.gbase = atomicAdd(&C->cnt[rn][1], n_q);
-  if ((int)threadIdx.x < nseg && sh.colact[threadIdx.x])
-    atomicOr(&C->colact[rn][threadIdx.x], sh.colact[threadIdx.x]);
-  __syncthreads();
-  for (uint32_t j = threadIdx.x; j < n_q; j += blockDim.x) {
-    const uint32_t p = sh.gbase + j;
-    if (p < A.cap_v) A.qwave[qn][p] = sh.q[j];
-    else atomicOr(&C->overflow, 1u);
+  // (d) group tier: one 16-lane group per row
+  const uint32_t ng = min(ld_agent(&C->cnt[rc][0]), A.cap_v);
+  for (uint32_t i = gw * 4 + (lane >> 4); i < ng; i += nwv * 4) {
+    const int32_t u = ld_queue(&A.qgrp[q][i]);
+    const int32_t start = A.rowptr[u], deg = A.rowptr[u + 1] - start;
+    const unsigned long long x = j16 < nseg ? tile_row_mask(A, q, qn, u, j16) : 0ull;
+    const uint32_t act = (uint32_t)(__ballot(x != 0ull) >> gbase) & 0xFFu;
+    if (act == 0u) continue;
+    int ns = __popcll(x);
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) ns += __shfl_xor(ns, off, 16);
+    if (j16 == 0) {
+      acc.fe += 1;
+      acc.es += (unsigned long long)deg;
+      acc.sa += (unsigned long long)ns;
+      acc.se += (unsigned long long)deg * (unsigned long long)ns;
+    }
+    for (uint32_t a = act; a; a &= a - 1u) {
+      const int sg = __ffs(a) - 1;
+      const unsigned long long xs = __shfl(x, gbase + sg);
+      const uint32_t bits = (uint32_t)(xs >> (4 * j16)) & 0xFu;
+      uint4 du = make_uint4(0u, 0u, 0u, 0u);
+      if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)u * A.K + sg * 64 + 4 * j16);
+      tile_seg_relax<F32>(A, start, deg, sg, bits, du, 0, 1, mkn, sh_colact, acc);
+    }
   }
-}
 
-__device__ __forceinline__ void tile_step_prologue(TileCtl* C, uint32_t step, int K) {
-  // zero the counters two steps ahead and count this step for active columns
-  if (blockIdx.x == 0) {
-    const int rz = (step + 2) % kRot, rc = step % kRot;
-    if (threadIdx.x < 4) st_agent(&C->cnt[rz][threadIdx.x], 0u);
-    if (threadIdx.x < kSegMax) st_agent64(&C->colact[rz][threadIdx.x], 0ull);
-    for (int j = threadIdx.x; j < K; j += blockDim.x)
-      if ((ld_agent64(&C->colact[rc][j >> 6]) >> (j & 63)) & 1ull)
-        st_agent_i(&C->colsteps[j], ld_agent_i(&C->colsteps[j]) + 1);
-  }
+  // (e) publish the workgroup's column activity
+  __syncthreads();
+  if ((int)threadIdx.x < nseg && sh_colact[threadIdx.x])
+    atomicOr(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
 }
 
 __device__ __forceinline__ bool any_active(const TileCtl* C, int rn, int nseg) {
@@ -390,12 +377,11 @@ __device__ __forceinline__ bool any_active(const TileCtl* C, int rn, int nseg) {
 }
 
 // All steps (up to max_steps, and at most n when cap_n) in one launch with a
-// grid barrier between steps.
+// grid barrier after each compaction and each relaxation.
 template <bool F32>
 __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32_t max_steps,
                                                                int32_t cap_n) {
-  __shared__ TileShared sh;
-  extern __shared__ uint32_t tile_dyn[];
+  __shared__ unsigned long long sh_colact[kSegMax];
   TileCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
   Acc acc;
@@ -406,8 +392,14 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   int32_t status = 1;
   bool finished = false;
   for (;;) {
-    tile_step_prologue(C, step, A.K);
-    tile_step<F32>(A, step, blockIdx.x, gridDim.x, acc, sh, tile_dyn);
+    if (blockIdx.x == 0) tile_prologue(C, step, A.K);
+    tile_compact(A, step, blockIdx.x, gridDim.x, acc);
+    if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
+      status = -2;
+      finished = true;
+      break;
+    }
+    tile_relax<F32>(A, step, blockIdx.x, gridDim.x, acc, sh_colact);
     if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       finished = true;
@@ -430,17 +422,26 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   }
 }
 
-// One step per launch; the last block advances the step.
-template <bool F32>
-__global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap_n) {
-  __shared__ TileShared sh;
-  extern __shared__ uint32_t tile_dyn[];
+// Step launches: the compaction of a step, then its relaxation, whose last
+// workgroup advances the step and detects the end.
+__global__ void __launch_bounds__(1024) tile_compact_kernel(TileArgs A) {
   TileCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
   const uint32_t step = ld_agent(&C->step);
-  tile_step_prologue(C, step, A.K);
+  if (blockIdx.x == 0) tile_prologue(C, step, A.K);
   Acc acc;
-  tile_step<F32>(A, step, blockIdx.x, gridDim.x, acc, sh, tile_dyn);
+  tile_compact(A, step, blockIdx.x, gridDim.x, acc);
+  flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap_n) {
+  __shared__ unsigned long long sh_colact[kSegMax];
+  TileCtl* C = A.ctl;
+  if (ld_agent(&C->done)) return;
+  const uint32_t step = ld_agent(&C->step);
+  Acc acc;
+  tile_relax<F32>(A, step, blockIdx.x, gridDim.x, acc, sh_colact);
   flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
   if (last_block_done(&C->blocks_done)) {
     st_agent(&C->blocks_done, 0u);
@@ -536,14 +537,13 @@ TileLayout tile_layout(int64_t n, int64_t m, int32_t k) {
   // rows above the smallest allowed threshold (32), each in at most deg/64 + 1
   // chunks (smallest allowed chunk 64)
   L.cap_wg = (uint32_t)(m / 33 + m / 64 + 2);
-  L.nwords = (n + 31) / 32;
   L.ctl = c.take(sizeof(TileCtl));
   L.info = c.take(sizeof(dawn_run_info));
   L.D = c.take((size_t)n * L.K * 4);
   for (int i = 0; i < 3; i++) L.mk[i] = c.take((size_t)n * L.nseg * 8);
+  for (int i = 0; i < 3; i++) L.qgrp[i] = c.take((size_t)n * 4);
   for (int i = 0; i < 3; i++) L.qwave[i] = c.take((size_t)n * 4);
   for (int i = 0; i < 3; i++) L.qwg[i] = c.take((size_t)L.cap_wg * 16);
-  for (int i = 0; i < 2; i++) L.ubm[i] = c.take((size_t)L.nwords * 4);
   L.total = c.off;
   return L;
 }
@@ -563,12 +563,14 @@ TileArgs tile_args(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.nseg = L.nseg;
   A.t_wave = T.tile_t_wave;
   A.t_chunk = T.tile_t_chunk;
+  A.t_group = T.tile_t_group;
+  A.skip = T.tile_skip;
   for (int i = 0; i < 3; i++) {
     A.mk[i] = reinterpret_cast<unsigned long long*>(base + L.mk[i]);
+    A.qgrp[i] = reinterpret_cast<int32_t*>(base + L.qgrp[i]);
     A.qwave[i] = reinterpret_cast<int32_t*>(base + L.qwave[i]);
     A.qwg[i] = reinterpret_cast<int4*>(base + L.qwg[i]);
   }
-  for (int i = 0; i < 2; i++) A.ubm[i] = reinterpret_cast<uint32_t*>(base + L.ubm[i]);
   A.cap_v = L.cap_v;
   A.cap_wg = L.cap_wg;
   A.ctl = reinterpret_cast<TileCtl*>(base + L.ctl);
@@ -580,10 +582,9 @@ static int grid_for(int64_t work, int threads) {
 }
 
 dawn_status tile_reset(const TileArgs& a, bool f32, hipStream_t stream) {
-  const int64_t nwords = ((int64_t)a.n + 31) / 32;
   const int g = grid_for((int64_t)a.n * a.K / 4, 256);
-  if (f32) hipLaunchKernelGGL(tile_fill_kernel<true>, dim3(g), dim3(256), 0, stream, a, nwords);
-  else hipLaunchKernelGGL(tile_fill_kernel<false>, dim3(g), dim3(256), 0, stream, a, nwords);
+  if (f32) hipLaunchKernelGGL(tile_fill_kernel<true>, dim3(g), dim3(256), 0, stream, a);
+  else hipLaunchKernelGGL(tile_fill_kernel<false>, dim3(g), dim3(256), 0, stream, a);
   return hip_check(hipGetLastError(), "tile reset");
 }
 
@@ -611,8 +612,11 @@ dawn_status tile_admit(const TileArgs& a, bool f32, int32_t col, int32_t source,
   return hip_check(hipGetLastError(), "tile admit");
 }
 
-dawn_status tile_evict(const TileArgs& a, int32_t col, hipStream_t stream) {
-  hipLaunchKernelGGL(tile_evict_kernel, dim3(grid_for(a.n, 256)), dim3(256), 0, stream, a, col);
+dawn_status tile_evict(const TileArgs& a, bool f32, int32_t col, hipStream_t stream) {
+  const int g = grid_for(a.n, 256);
+  if (f32) hipLaunchKernelGGL(tile_col_fill_kernel<true>, dim3(g), dim3(256), 0, stream, a, col);
+  else hipLaunchKernelGGL(tile_col_fill_kernel<false>, dim3(g), dim3(256), 0, stream, a, col);
+  hipLaunchKernelGGL(tile_evict_kernel, dim3(1), dim3(64), 0, stream, a, col);
   return hip_check(hipGetLastError(), "tile evict");
 }
 
@@ -633,7 +637,7 @@ static int persistent_grid_t(K kernel, int threads, int* per_cu_out = nullptr, s
 void tile_persistent_occupancy(int threads, int* per_cu, int* grid) {
   if (threads <= 0) threads = 256;
   *grid = persistent_grid_t(tile_persistent_kernel<false>, threads, per_cu,
-                            tile_dyn_lds(256, threads / 64));
+                            0);
 }
 
 template <bool F32>
@@ -642,9 +646,8 @@ static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_
   const Tuning& T = tuning();
   const int threads = T.wg_threads > 0 ? T.wg_threads : 256;
   const int32_t cap_n = persistent ? 1 : 0;
-  const size_t dyn = tile_dyn_lds(a.K, threads / 64);
   if (persistent) {
-    int grid = persistent_grid_t(tile_persistent_kernel<F32>, threads, nullptr, dyn);
+    int grid = persistent_grid_t(tile_persistent_kernel<F32>, threads, nullptr, 0);
     if (T.grid > 0 && T.grid < grid) grid = T.grid;
     TileArgs aa = a;
     int32_t ms = max_steps, cn = cap_n;
@@ -653,20 +656,27 @@ static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_
     void* tk = ktimer_begin(stream);
     if (dev_info().coop && T.coop) {
       e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&tile_persistent_kernel<F32>),
-                                     dim3(grid), dim3(threads), args, (unsigned)dyn, stream);
+                                     dim3(grid), dim3(threads), args, 0, stream);
     } else {
-      hipLaunchKernelGGL(tile_persistent_kernel<F32>, dim3(grid), dim3(threads), dyn, stream, aa,
+      hipLaunchKernelGGL(tile_persistent_kernel<F32>, dim3(grid), dim3(threads), 0, stream, aa,
                          ms, cn);
       e = hipGetLastError();
     }
     ktimer_end(tk, stream, 1);
     return hip_check(e, "tile persistent launch");
   }
-  const int grid = T.grid > 0 ? T.grid : 16 * dev_info().cus;
-  void* tk = ktimer_begin(stream);
-  for (int s = 0; s < max_steps; s++)
-    hipLaunchKernelGGL(tile_step_kernel<F32>, dim3(grid), dim3(threads), dyn, stream, a, 0);
-  ktimer_end(tk, stream, max_steps);
+  // relaxation: 16 workgroups per CU, fewer for small graphs (about one
+  // workgroup per 64 vertices, at least one per CU)
+  const int cus = dev_info().cus;
+  const int grid = T.grid > 0 ? T.grid
+                              : (int)std::max<int64_t>(cus, std::min<int64_t>(16 * cus, ((int64_t)a.n + 63) / 64));
+  const int cgrid = std::min(16 * dev_info().cus, (int)std::max<int64_t>(1, ((int64_t)a.n + 255) / 256));
+  for (int s = 0; s < max_steps; s++) {
+    hipLaunchKernelGGL(tile_compact_kernel, dim3(cgrid), dim3(256), 0, stream, a);
+    void* tk = ktimer_begin(stream);
+    hipLaunchKernelGGL(tile_step_kernel<F32>, dim3(grid), dim3(threads), 0, stream, a, 0);
+    ktimer_end(tk, stream, 1);
+  }
   return hip_check(hipGetLastError(), "tile step launches");
 }
 

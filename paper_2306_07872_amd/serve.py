@@ -15,8 +15,12 @@ ticks:
    `steps_per_tick` GOVM steps enqueued on its own stream, followed by an
    asynchronous copy of its done bits and an event.
 
-A tile takes new columns only while no run of it is in flight, so the done
-bits a run reports always belong to columns admitted before that run.
+A tile takes new columns also while a run of it is in flight: the admission
+is enqueued on the tile's stream behind that run and joins the next run.  The
+done bits of a run are taken only for columns admitted before the run was
+launched (a column's previous query stays live on the device until the column
+is reused, so the bits of a run launched before a reuse speak for that
+previous query).
 
 Columns join and leave a running tile between step chunks; the arithmetic of
 a column does not depend on the other columns (different sources never update
@@ -51,6 +55,7 @@ class Query:
     _col: int | None = None
     _tile: object = None
     _read: object = None
+    _admit_run: int = 0           # runs of its tile launched before its admission
 
     @property
     def latency(self) -> float | None:
@@ -140,7 +145,7 @@ class _TileSlot:
         self.ex = ex
         self.free = list(range(ex.k))
         self.live: dict[int, Query] = {}
-        self.idle_ticks = 0
+        self.runs = 0                 # runs launched so far
 
 
 class Server:
@@ -206,9 +211,10 @@ class Server:
                 if not slot.ex.finished_run():
                     continue
                 for col in slot.ex.done_cols():
-                    q = slot.live.pop(col, None)
-                    if q is None:
-                        continue
+                    q = slot.live.get(col)
+                    if q is None or q._admit_run >= slot.runs:
+                        continue    # free, or admitted after this run was launched
+                    del slot.live[col]
                     q._read = slot.ex.read(col)
                     q.state = "reading"
                     slot.free.append(col)   # the read is enqueued before any later admit
@@ -227,10 +233,8 @@ class Server:
         self.reading = still
 
     def _slot_for(self, gid: int):
-        # Only tiles with no run in flight take new columns: the done bits of a
-        # run enqueued before an admission must not speak for the new column.
         for slot in self.tiles[gid]:
-            if slot.free and slot.ex.idle():
+            if slot.free:
                 return slot
         if len(self.tiles[gid]) >= self.max_tiles_per_graph:
             return None
@@ -273,7 +277,7 @@ class Server:
             col = slot.free.pop(0)
             slot.ex.admit(col, q.source)
             slot.live[col] = q
-            q._col, q._tile = col, slot
+            q._col, q._tile, q._admit_run = col, slot, slot.runs
             q.state, q.t_admit = "running", now
         self.waiting = keep
 
@@ -283,6 +287,7 @@ class Server:
             for slot in slots:
                 if slot.live and slot.ex.idle():
                     slot.ex.launch(self.steps_per_tick)
+                    slot.runs += 1
 
     def tick(self) -> int:
         """One scheduling round; returns how many queries finished in it."""

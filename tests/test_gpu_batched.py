@@ -44,6 +44,10 @@ TILE_TUNINGS = [
     dict(tile_k=128, tile_t_wave=65536, wg_threads=1024),
     dict(tile_k=512, tile_t_wave=40, tile_t_chunk=100, wg_threads=512, grid=5),
     dict(mode=1, host_check=3, tile_t_wave=32, tile_t_chunk=64),
+    dict(tile_t_group=0, tile_skip=0),
+    dict(tile_t_group=31, tile_t_wave=32, tile_t_chunk=64, wg_threads=512),
+    dict(mode=2, tile_skip=0),
+    dict(mode=2, tile_t_group=64, tile_t_wave=100, wg_threads=1024),
 ]
 
 

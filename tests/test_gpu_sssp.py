@@ -54,6 +54,8 @@ TUNINGS = [
     dict(t_lane=8, t_wave=64, t_chunk=256, wg_threads=512, grid=7),
     dict(mode=1, grid=3, host_check=1),
     dict(mode=1, t_lane=2, t_wave=64, t_chunk=256, host_check=5),
+    dict(small_m=1 << 30),                    # one workgroup for the whole graph
+    dict(small_m=1 << 30, wg_threads=256),
 ]
 
 
@@ -77,7 +79,9 @@ def test_grid_f32_small(dawn):
         assert info["steps"] > 96   # a high-step-count case
 
 
-def test_edge_cases(dawn):
+@pytest.mark.parametrize("small_m", [None, 0, 1 << 30])
+def test_edge_cases(dawn, small_m):
+    tune = {} if small_m is None else dict(small_m=small_m)
     cases = []
     cases.append(("n1", graphgen.from_edges(1, [], [], np.zeros(0, np.uint32), "u32"), 0))
     cases.append(("m0", graphgen.from_edges(7, [], [], np.zeros(0, np.uint32), "u32"), 3))
@@ -105,8 +109,8 @@ def test_edge_cases(dawn):
     # ragged tail: sizes not multiples of 64 / 32
     cases.append(("ragged", graphgen.er(1001, 7003, 4, weights="u32", wlo=0, whi=3), 1000))
     for name, g, s in cases:
-        announce("edge case", name, "n", g.n, "m", g.m, "source", s)
-        d, info = _run(dawn, g, s)
+        announce("edge case", name, "n", g.n, "m", g.m, "source", s, tune)
+        d, info = _run(dawn, g, s, **tune)
         assert_sssp_matches(g, s, d, tag=name)
         assert info["converged"] == 1
 

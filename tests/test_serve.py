@@ -2,9 +2,12 @@
 
 The fake stands in for a HIP tile session: a column admitted with source s
 finishes after a number of step launches and then reads back the oracle's
-distances.  The tests check admission by HBM budget, FIFO service, column
-reuse, cancellation, and that a tile never takes a new column while a run of
-it is in flight.
+distances.  Like the device, a run reports as done every column that is live
+and no longer active when the run ends, including a finished column whose
+query was already collected and which has not been reused yet.  The tests
+check admission by HBM budget, FIFO service, column reuse, cancellation, and
+that admissions while a run is in flight are never answered from that run's
+done bits.
 """
 import numpy as np
 import pytest
@@ -39,8 +42,9 @@ class FakeExecutor:
         FakeExecutor.created += 1
         self.csr, self.k, self.lag = csr, k, lag
         self.nbytes = 1
-        self.cols = {}          # col -> [source, steps left, steps taken]
+        self.cols = {}          # col -> [source, steps left, steps taken]; stays after done
         self.run_polls = None
+        self.run_done = []
         self.admit_while_running = 0
         self.closed = False
 
@@ -58,6 +62,8 @@ class FakeExecutor:
             take = min(steps, c[1])
             c[1] -= take
             c[2] += take
+        # done bits as the device computes them when the run ends: live and idle
+        self.run_done = [col for col, c in self.cols.items() if c[1] == 0]
         self.run_polls = 0
 
     def running(self):
@@ -77,10 +83,10 @@ class FakeExecutor:
 
     def done_cols(self):
         self.run_polls = None
-        return [col for col, c in self.cols.items() if c[1] == 0]
+        return list(self.run_done)
 
     def read(self, col):
-        src, _, taken = self.cols.pop(col)
+        src, left, taken = self.cols[col]
         d, _ = oracle.sssp(self.csr.g, src)
         return FakeRead(d, taken)
 
@@ -169,19 +175,30 @@ def test_cancel_waiting_and_running(graphs):
     assert b.state == "done" and a.result is None and c.result is None
 
 
-def test_no_admission_into_a_running_tile(graphs):
-    srv = make_server(budget=5, tile_k=8, max_tiles=1, lag=3)
+def test_admission_while_running_never_reads_an_early_answer(graphs):
+    """A finished column is collected and freed; the next run is launched while
+    it is still live on the device (so that run reports it done); a new query
+    then takes the column while the run is in flight.  The run's done bit
+    speaks for the old query and must not answer the new one."""
+    srv = make_server(budget=5, tile_k=2, max_tiles=1, steps=2, lag=2)
     _patch_cost(srv, 1)
     srv.add_graph(0, FakeCsr(graphs[0]))
-    srv.submit(0, 1)
-    srv.tick()                      # admits and launches
-    for i in range(10):             # arrivals while the run is in flight
-        srv.submit(0, 10 + i)
-        srv.tick()
+    q1 = srv.submit(0, 5)           # needs 1 step
+    q2 = srv.submit(0, 4)           # needs 5 steps
+    srv.tick()                      # admit q1 -> col 0, q2 -> col 1; run 1
+    while q1.state != "done":
+        srv.tick()                  # run 1 collected: q1 read, col 0 freed; run 2 launched
+    slot = srv.tiles[0][0]
+    assert not slot.ex.idle() and 0 in slot.ex.run_done
+    q3 = srv.submit(0, 3)           # needs 4 steps; reuses col 0 while run 2 is in flight
+    srv.tick()
+    assert q3.state == "running" and q3._col == 0 and slot.ex.admit_while_running == 1
     srv.run_until_idle()
-    ex = srv.tiles[0][0].ex
-    assert ex.admit_while_running == 0
-    assert all(q.state == "done" for q in srv.done) and len(srv.done) == 11
+    for q in (q1, q2, q3):
+        assert q.state == "done"
+        assert q.steps == 1 + (q.source % 5)    # read only once its own steps were done
+        ref, _ = oracle.sssp(graphs[0], q.source)
+        assert np.array_equal(q.result, ref)
 
 
 def test_poisson_arrivals_and_percentiles():
