@@ -37,8 +37,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "tile_step_kernel_rmat20_k256_traffic.md")
 KERNEL_SOURCES = ("paper_2306_07872_amd/csrc/govm_tile.hip",
-                  "paper_2306_07872_amd/csrc/govm_device.hpp",
-                  "paper_2306_07872_amd/csrc/govm_host.hpp")
+                  "paper_2306_07872_amd/csrc/govm_device.hpp")
 
 
 def kernel_sources_sha256() -> str:
@@ -49,9 +48,15 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
+# tuning fields that shape the tile's launches (the others only concern
+# single-source runs)
+TILE_TUNING_KEYS = ("wg_threads", "grid", "mode", "host_check", "tile_k", "tile_t_wave",
+                    "tile_t_chunk", "tile_t_group", "tile_skip")
+
+
 def measured_traffic(tuning: dict, workload: str):
     """HBM bytes per relaxation launch from the committed counter summary, or
-    None when it was taken with other kernel sources, tuning or workload."""
+    None when it was taken with other kernel sources, tile tuning or workload."""
     try:
         with open(TRAFFIC_SUMMARY) as f:
             text = f.read()
@@ -63,8 +68,10 @@ def measured_traffic(tuning: dict, workload: str):
             k, v = line[2:].split(": ", 1)
             fields[k.strip("`")] = v.strip().strip("`")
     try:
+        taken = json.loads(fields["tuning"])
         if (fields["kernel_sources_sha256"] != kernel_sources_sha256()
-                or json.loads(fields["tuning"]) != tuning or fields["workload"] != workload):
+                or any(taken.get(k) != tuning.get(k) for k in TILE_TUNING_KEYS)
+                or fields["workload"] != workload):
             return None
         return int(fields["traffic_bytes_per_launch"])
     except (KeyError, ValueError):

@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Measurements of the workloads other than bench.py's headline one.
 
-    python bench_suite.py [--only c1,c2,c3,c4b,c5] [--out results.jsonl]
+    python bench_suite.py [--only c1,c2,c3,c4b,c5,mu] [--out results.jsonl]
 
 c1   plain SSSP latency: directed ER n=1000 m=8000, uint32 weights [1,100],
      source 0; per-call latency percentiles (host-observed, with a device
@@ -17,6 +17,12 @@ c4b  64 uneven ER graphs (n = 10^U(4,6), m = 8n, fp32 lognormal), one source
 c5   serving: Poisson arrivals over 32 resident R-MAT graphs (scales 14 + i%9
      capped at --c5-max-scale, edge factors 8/16/32, half uint32 half fp32
      lognormal); p50/p99 latency and completed queries/s per offered rate.
+mu   the validation experiment of Section 4.2 on synthetic graphs: the same
+     topology with fp32 weights all 1.0 and uniform on [0,2]; per graph, the
+     share of distance updates beyond the first per reached vertex
+     (improvements / reached - 1; 0 at unit weights), mu_e (edges scanned /
+     edges reachable), mu_v (rows expanded / vertices reached with out-edges),
+     steps, and the time ratio of the two weightings.
 
 Every input is synthetic and seeded (graphgen.workloads).  Each section prints
 one JSON line; --out appends them to a file.
@@ -120,7 +126,9 @@ def c2(args, dawn, torch, np):
            "sources": len(srcs), "gteps_per_source_mean": float(np.mean(gteps)),
            "gteps_per_source_min": float(np.min(gteps)), "mu_e_mean": float(np.mean(mu)),
            "steps_mean": float(np.mean(steps)),
-           "roofline": {"bound": "hbm", "kernel": "ss_persistent_kernel<false>",
+           "roofline": {"bound": "hbm",
+                        "kernel": ("ss_step_kernel<false>" if g.m >= dawn.get_tuning()["step_min_m"]
+                                   else "ss_persistent_kernel<false>"),
                         "achieved": kb / (kms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
                         "frac": kb / (kms * 1e-3) / 1e9 / 8000.0}}
     rec.update(percentile_ms(per))
@@ -263,6 +271,50 @@ def c5(args, dawn, torch, np):
     return recs
 
 
+def mu(args, dawn, torch, np):
+    import graphgen
+    graphs = [("rmat18_ef16", lambda wk: graphgen.rmat(18, 16, 180, weights=wk)),
+              ("er_n262144_m16n", lambda wk: graphgen.er(1 << 18, 16 << 18, 181, weights=wk)),
+              ("grid512_1pct", lambda wk: graphgen.grid(512, 512, 0.01, 182, weights=wk))]
+    recs = []
+    for name, make in graphs:
+        row = {"config": f"mu_{name}"}
+        for wk in ("f32one", "f32range02"):
+            g = make(wk)
+            csr = dawn.Csr.from_graph(g)
+            out = torch.empty(g.n, dtype=torch.float32, device="cuda")
+            ws = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
+            info = dawn.info_tensor()
+            outdeg = torch.as_tensor(np.diff(g.rowptr.astype(np.int64)), device="cuda")
+            srcs = graphgen.pick_sources(g, args.mu_sources, 7)
+            dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info)
+            torch.cuda.synchronize()
+            tot = dict(t=0.0, reached=0, reached_rows=0, reach_edges=0, imp=0, rows=0, es=0, steps=0)
+            for s in srcs:
+                t0 = time.perf_counter()
+                dawn.sssp(csr, int(s), out=out, ws=ws, info=info)
+                torch.cuda.synchronize()
+                tot["t"] += time.perf_counter() - t0
+                i = dawn.read_info(info)
+                fin = torch.isfinite(out)
+                tot["reached"] += int(fin.sum().item()) - 1
+                tot["reached_rows"] += int((fin & (outdeg > 0)).sum().item())
+                tot["reach_edges"] += int((fin.to(torch.int64) * outdeg).sum().item())
+                tot["imp"] += i["improvements"]
+                tot["rows"] += i["frontier_entries"]
+                tot["es"] += i["edges_scanned"]
+                tot["steps"] += i["steps"]
+            k = len(srcs)
+            row[wk] = {"update_share": tot["imp"] / max(tot["reached"], 1) - 1.0,
+                       "mu_e": tot["es"] / max(tot["reach_edges"], 1),
+                       "mu_v": tot["rows"] / max(tot["reached_rows"], 1),
+                       "steps_mean": tot["steps"] / k, "ms_mean": tot["t"] * 1e3 / k}
+        row["time_ratio_range02_over_one"] = row["f32range02"]["ms_mean"] / row["f32one"]["ms_mean"]
+        log(f"mu {name}: {row}")
+        recs.append(row)
+    return recs
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--only", default="c1,c2,c3,c4b,c5")
@@ -280,6 +332,7 @@ def main() -> int:
     ap.add_argument("--c5-tile-k", type=int, default=64)
     ap.add_argument("--c5-steps-per-tick", type=int, default=4)
     ap.add_argument("--c5-rates", default="0.1,0.25,0.5,0.7,0.8,0.9,1.0,1.2")
+    ap.add_argument("--mu-sources", type=int, default=8)
     args = ap.parse_args()
     args.c5_rates = [float(x) for x in args.c5_rates.split(",")]
     import numpy as np
@@ -289,7 +342,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     dawn.load()
     for name in args.only.split(","):
-        fn = {"c1": c1, "c2": c2, "c3": c3, "c4b": c4b, "c5": c5}[name]
+        fn = {"c1": c1, "c2": c2, "c3": c3, "c4b": c4b, "c5": c5, "mu": mu}[name]
         log(f"== {name}")
         t = time.perf_counter()
         recs = fn(args, dawn, torch, np)

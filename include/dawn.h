@@ -103,14 +103,18 @@ typedef struct {
  *   wave tier      d <= t_wave   one wavefront per row (t_wave >= 64);
  *   workgroup tier d >  t_wave   the row is cut into chunks of t_chunk edges,
  *                                one workgroup per chunk.
- * mode: 0 auto (single source and batches of graphs: one workgroup when
- * m <= small_m, else 2; tiles: 1), 1 step
+ * mode: 0 auto: single source and batches of graphs run in one workgroup
+ * when m <= small_m; with m >= step_min_m edges as `host_check` step launches
+ * followed, if the run has not ended by then, by one persistent launch for
+ * the rest; otherwise (and when captured) as one persistent launch; tiles: 1.
+ * 1 step
  * launches (one kernel per step; the host checks termination every
  * `host_check` steps, so such a call waits for its stream), 2 one persistent
  * launch for all steps with a grid
  * barrier between steps (the barrier gives up after a few seconds, so a grid
  * that cannot be co-resident ends with converged = -2 instead of hanging).
- * wg_threads: 256, 512 or 1024, or 0 = auto (single source 1024, tiles 256).
+ * wg_threads: 256, 512 or 1024, or 0 = auto (single source: 512 for step launches,
+ * 1024 for persistent launches; tiles 256).
  * grid: workgroups per launch, 0 = auto (persistent: what the device holds at
  * once; tile step launches: 16 per compute unit; single-source step launches:
  * 4 per compute unit).
@@ -133,13 +137,15 @@ typedef struct {
                            device holds at once (half the occupancy query's figure) */
   int32_t tile_t_group; /* tile rows of out-degree <= this go one per 16-lane group,
                            0..64, default 8 (0: none) */
-  int32_t tile_skip;    /* 1 (default): in a tile step, a (row, source) pair whose distance
-                           was already lowered again in the same step is not expanded
-                           (it is expanded next step with the lower value); 0: every
+  int32_t tile_skip;    /* 1: in a tile step, a (row, source) pair whose distance was
+                           already lowered again in the same step is not expanded (it is
+                           expanded next step with the lower value); 0 (default): every
                            pair of the frontier is expanded, as Algorithm 2 states */
   int32_t small_m;      /* single-source and batch runs with mode 0 and m <= small_m run in
                            one workgroup, one launch (no grid barrier); default 131072,
                            0 = never */
+  int32_t step_min_m;   /* mode 0: graphs with at least this many edges start with step
+                           launches (see mode); default 1 << 25 */
 } dawn_tuning;
 
 #define DAWN_TILE_K_MAX 512

@@ -66,7 +66,7 @@ static bool tuning_ok(const Tuning& t) {
          t.tile_t_chunk >= 64 && t.tile_t_chunk <= 65536 && (t.validate == 0 || t.validate == 1) &&
          (t.coop == 0 || t.coop == 1) && t.tile_t_group >= 0 && t.tile_t_group <= 64 &&
          t.tile_t_group < t.tile_t_wave && (t.tile_skip == 0 || t.tile_skip == 1) &&
-         t.small_m >= 0;
+         t.small_m >= 0 && t.step_min_m >= 0;
 }
 
 static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
@@ -79,6 +79,26 @@ static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, con
   if (wt != DAWN_W_U32 && wt != DAWN_W_F32) return set_error(DAWN_E_INVALID, "unknown wtype");
   if (!tuning_ok(g_tuning)) return set_error(DAWN_E_INVALID, "tuning out of range");
   return DAWN_OK;
+}
+
+static std::mutex g_pin_mu;
+static std::vector<uint32_t*> g_pin_free;
+
+PinnedWord::PinnedWord() {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  if (!g_pin_free.empty()) {
+    p = g_pin_free.back();
+    g_pin_free.pop_back();
+    return;
+  }
+  void* q = nullptr;
+  if (hipHostMalloc(&q, 64, hipHostMallocDefault) == hipSuccess) p = static_cast<uint32_t*>(q);
+}
+
+PinnedWord::~PinnedWord() {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.push_back(p);
 }
 
 // Scratch owned for the duration of one call: hipMallocAsync / hipFreeAsync
@@ -220,6 +240,7 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->tile_t_group = t.tile_t_group;
   out->tile_skip = t.tile_skip;
   out->small_m = t.small_m;
+  out->step_min_m = t.step_min_m;
   return DAWN_OK;
 }
 
@@ -241,6 +262,7 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.tile_t_group = in->tile_t_group;
     t.tile_skip = in->tile_skip;
     t.small_m = in->small_m;
+    t.step_min_m = in->step_min_m;
   }
   if (!tuning_ok(t)) return set_error(DAWN_E_INVALID, "tuning out of range");
   g_tuning = t;
@@ -337,18 +359,16 @@ static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, cons
     if (mode == 2) {
       if ((st = tile_steps(A, f32, true, INT32_MAX, stream)) != DAWN_OK) return st;
     } else {
-      uint32_t* h_done = nullptr;
-      if (hipHostMalloc((void**)&h_done, 4, hipHostMallocDefault) != hipSuccess)
-        return set_error(DAWN_E_HIP, "hipHostMalloc failed");
-      *h_done = 0;
+      PinnedWord done;
+      if (!done.p) return set_error(DAWN_E_HIP, "hipHostMalloc failed");
+      *done.p = 0;
       for (int64_t launched = 0; launched <= n;) {
         const int chunk = g_tuning.host_check;
         if ((st = tile_steps(A, f32, false, chunk, stream)) != DAWN_OK) break;
         launched += chunk;
-        hipMemcpyAsync(h_done, &A.ctl->done, 4, hipMemcpyDeviceToHost, stream);
-        if (hipStreamSynchronize(stream) != hipSuccess || *h_done) break;
+        hipMemcpyAsync(done.p, &A.ctl->done, 4, hipMemcpyDeviceToHost, stream);
+        if (hipStreamSynchronize(stream) != hipSuccess || *done.p) break;
       }
-      hipHostFree(h_done);
       if (st != DAWN_OK) return st;
     }
     char* out = static_cast<char*>(dist_out) + (size_t)j0 * (size_t)n * 4;

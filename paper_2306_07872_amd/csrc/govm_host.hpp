@@ -24,8 +24,9 @@ struct Tuning {
   int32_t validate = 0;
   int32_t coop = 0;
   int32_t tile_t_group = 8;
-  int32_t tile_skip = 1;
+  int32_t tile_skip = 0;
   int32_t small_m = 131072;
+  int32_t step_min_m = 1 << 25;
 };
 
 Tuning& tuning();
@@ -107,6 +108,18 @@ void tile_persistent_occupancy(int threads, int* per_cu, int* grid);
 // Bracket a main launch with events when the kernel timer is on.
 void* ktimer_begin(hipStream_t stream);
 void ktimer_end(void* token, hipStream_t stream, int32_t launches);
+
+// ----- host polling -----------------------------------------------------------
+// A pinned host word for reading a device flag after a stream synchronisation.
+// Pinned allocations cost far more than a step, so words come from a
+// process-wide pool and go back to it (the pool lives until the process ends).
+struct PinnedWord {
+  uint32_t* p = nullptr;
+  PinnedWord();
+  ~PinnedWord();
+  PinnedWord(const PinnedWord&) = delete;
+  PinnedWord& operator=(const PinnedWord&) = delete;
+};
 
 // ----- misc ------------------------------------------------------------------
 dawn_status set_error(dawn_status s, const char* fmt, ...);

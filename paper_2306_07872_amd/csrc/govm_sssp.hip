@@ -608,6 +608,173 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
 }
 
 // ---------------------------------------------------------------------------
+// tiny graphs: the whole state in LDS
+//
+// With n <= kTinyN the distances, both beta bitmaps and both frontier queues
+// fit in one workgroup's LDS, so every step runs on LDS atomics (a few
+// hundred cycles) instead of device-scope atomics; only the CSR is read from
+// global memory.  The final distances are copied out once.
+// ---------------------------------------------------------------------------
+constexpr int kTinyN = 6144;
+
+struct SsTinyShared {
+  int stage[kMaxWavesPerBlock * 3 * kWave];
+  uint32_t dist[kTinyN];
+  uint16_t q[2][kTinyN];
+  uint32_t bm[2][kTinyN / 32];
+  uint32_t cnt_next, upd;
+};
+
+template <bool F32>
+__global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* sources,
+                                                       const int64_t* voff, int32_t count,
+                                                       int32_t single, int32_t check_valid,
+                                                       dawn_run_info* info) {
+  __shared__ SsTinyShared sh;
+  SsCtl* C = A.ctl;
+  const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int n = A.n, nwords = (n + 31) / 32;
+  uint32_t step = 0;
+  int32_t status = 1;
+  Acc acc;
+  if (check_valid && ld_agent(&C->done)) {
+    status = -1;
+  } else {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sh.dist[i] = inf_bits<F32>();
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
+      sh.bm[0][i] = 0u;
+      sh.bm[1][i] = 0u;
+    }
+    if (threadIdx.x == 0) {
+      sh.cnt_next = 0u;
+      sh.upd = 0u;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < count; j += blockDim.x) {
+      int64_t s = sources ? (int64_t)sources[j] : (int64_t)single;
+      if (voff) s += voff[j];
+      sh.dist[s] = 0u;
+      const uint32_t bit = 1u << (s & 31);
+      if (atomicOr(&sh.bm[0][s >> 5], bit) & bit) continue;
+      sh.q[0][atomicAdd(&sh.cnt_next, 1u)] = (uint16_t)s;
+    }
+    __syncthreads();
+    uint32_t cnt = sh.cnt_next;
+    __syncthreads();
+    if (threadIdx.x == 0) sh.cnt_next = 0u;
+    __syncthreads();
+    int* l_incl = sh.stage + wave * 3 * kWave;
+    int* l_base = l_incl + kWave;
+    int* l_du = l_base + kWave;
+    for (;;) {
+      const int cur = step & 1, nxt = cur ^ 1;
+      for (uint32_t bi = wave; (uint64_t)bi * kWave < cnt; bi += W) {
+        const uint32_t i = bi * kWave + lane;
+        int32_t u = 0, start = 0, deg = 0;
+        uint32_t du = 0;
+        if (i < cnt) {
+          u = sh.q[cur][i];
+          start = A.rowptr[u];
+          deg = A.rowptr[u + 1] - start;
+          du = sh.dist[u];
+          sh.bm[cur][u >> 5] = 0u;
+          if (deg > 0) {
+            acc.fe += 1;
+            acc.es += (unsigned long long)deg;
+          }
+        }
+        const int incl = wave_incl_scan(deg);
+        const int total = __shfl(incl, kWave - 1, kWave);
+        l_incl[lane] = incl;
+        l_base[lane] = start - (incl - deg);
+        l_du[lane] = (int)du;
+        wave_lds_sync();
+        for (int base = 0; base < total; base += kWave * kUnrollLane) {
+          int32_t v[kUnrollLane];
+          uint32_t cand[kUnrollLane];
+          bool ok[kUnrollLane];
+#pragma unroll
+          for (int j = 0; j < kUnrollLane; j++) {
+            const int k = base + j * kWave + lane;
+            int owner = 0;  // first lane whose inclusive prefix exceeds k
+#pragma unroll
+            for (int s = 32; s >= 1; s >>= 1)
+              if (l_incl[owner + s - 1] <= k) owner += s;
+            ok[j] = k < total;
+            v[j] = 0;
+            cand[j] = 0u;
+            if (ok[j]) {
+              const int32_t e = l_base[owner] + k;
+              v[j] = A.colidx[e];
+              cand[j] = relax_add<F32>((uint32_t)l_du[owner], A.w[e]);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < kUnrollLane; j++) {
+            bool newv = false;
+            if (ok[j] && v[j] != A.src && cand[j] < sh.dist[v[j]] &&
+                cand[j] < atomicMin(&sh.dist[v[j]], cand[j])) {
+              acc.im += 1;
+              sh.upd = 1u;
+              const uint32_t bit = 1u << (v[j] & 31);
+              newv = (atomicOr(&sh.bm[nxt][v[j] >> 5], bit) & bit) == 0u;
+            }
+            const unsigned long long b = __ballot(newv);
+            if (b != 0ull) {
+              const int leader = __ffsll((long long)b) - 1;
+              uint32_t pos = 0;
+              if (lane == leader) pos = atomicAdd(&sh.cnt_next, (uint32_t)__popcll(b));
+              pos = __shfl(pos, leader, kWave) + lanes_below(b);
+              if (newv) sh.q[nxt][pos] = (uint16_t)v[j];
+            }
+          }
+        }
+        wave_lds_sync();
+      }
+      __syncthreads();
+      const uint32_t upd = sh.upd, cn = sh.cnt_next;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        sh.upd = 0u;
+        sh.cnt_next = 0u;
+      }
+      __syncthreads();
+      step++;
+      cnt = cn;
+      if (!upd) { status = 1; break; }
+      if (step >= (uint32_t)A.n) { status = 0; break; }
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) A.dist[i] = sh.dist[i];
+  }
+  if (threadIdx.x == 0) {
+    st_agent64(&C->fe, 0ull);
+    st_agent64(&C->es, 0ull);
+    st_agent64(&C->im, 0ull);
+  }
+  __syncthreads();
+  flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (status != -1) {
+      st_agent(&C->step, step);
+      st_agent_i(&C->converged, status);
+      st_agent(&C->done, 1u);
+    }
+    if (info) {
+      info->steps = (int32_t)ld_agent(&C->step);
+      info->converged = ld_agent_i(&C->converged);
+      info->frontier_entries = (int64_t)ld_agent64(&C->fe);
+      info->edges_scanned = (int64_t)ld_agent64(&C->es);
+      info->improvements = (int64_t)ld_agent64(&C->im);
+      info->union_rows = info->frontier_entries;
+      info->union_edges = info->edges_scanned;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 SsLayout ss_layout(int64_t n, int64_t m) {
@@ -653,7 +820,11 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
                             hipStream_t stream, bool capture) {
   const Tuning& T = tuning();
   const DevInfo& di = dev_info();
-  const int threads = T.wg_threads > 0 ? T.wg_threads : 1024;
+  const int auto_threads = (T.mode == 0 && !capture && (int64_t)A.m >= (int64_t)T.step_min_m) ||
+                                   T.mode == 1
+                               ? 512
+                               : 1024;
+  const int threads = T.wg_threads > 0 ? T.wg_threads : auto_threads;
   const int fill_blocks = (int)std::min<int64_t>(4096, (A.n + 255) / 256 + 1);
   if (T.mode == 0 && (int64_t)A.m <= (int64_t)T.small_m) {
     // one workgroup, one launch (after the optional device validation)
@@ -665,9 +836,14 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
                          A.n, A.m, (int32_t)F32, &A.ctl->done, &A.ctl->converged);
     }
     void* tk = capture ? nullptr : ktimer_begin(stream);
-    hipLaunchKernelGGL(ss_small_kernel<F32>, dim3(1), dim3(threads), 0, stream, A,
-                       seeds.sources_dev, seeds.voff_dev, seeds.count, seeds.source,
-                       (int32_t)(T.validate != 0), info);
+    if (A.n <= kTinyN)
+      hipLaunchKernelGGL(ss_tiny_kernel<F32>, dim3(1), dim3(threads), 0, stream, A,
+                         seeds.sources_dev, seeds.voff_dev, seeds.count, seeds.source,
+                         (int32_t)(T.validate != 0), info);
+    else
+      hipLaunchKernelGGL(ss_small_kernel<F32>, dim3(1), dim3(threads), 0, stream, A,
+                         seeds.sources_dev, seeds.voff_dev, seeds.count, seeds.source,
+                         (int32_t)(T.validate != 0), info);
     ktimer_end(tk, stream, 1);
     return hip_check(hipGetLastError(), "small-graph launch");
   }
@@ -683,9 +859,41 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
   dawn_status st = hip_check(hipGetLastError(), "init launch");
   if (st != DAWN_OK) return st;
 
+  // mode 0 on graphs of at least step_min_m edges: step launches for the
+  // first `host_check` steps (such runs, with few large steps, mostly finish
+  // there), then -- if the run goes on -- one persistent launch for the rest;
+  // smaller graphs, and captured runs (which cannot wait on the host), use the
+  // persistent launch at once.  Measured on MI355X: on R-MAT scale 22 (67M
+  // edges) step launches of 512-thread workgroups take a third of the time of
+  // the persistent launch; on 16.7M-edge graphs (R-MAT scale 20, the 2048^2
+  // grid) the persistent launch of 1024-thread workgroups is faster.
   int mode = T.mode;
-  if (mode == 0) mode = 2;
-  if (mode == 2) {
+  if (mode == 0) mode = (capture || (int64_t)A.m < (int64_t)T.step_min_m) ? 2 : 3;
+  bool finished = false;
+  if (mode == 1 || mode == 3) {
+    if (capture) return set_error(DAWN_E_UNSUPPORTED, "step launches cannot be captured");
+    const int grid = T.grid > 0 ? T.grid : 4 * di.cus;
+    PinnedWord done;
+    if (!done.p) return set_error(DAWN_E_HIP, "hipHostMalloc failed");
+    *done.p = 0;
+    int64_t launched = 0;
+    const int64_t cap = (int64_t)A.n + 1;
+    while (launched < cap) {
+      const int chunk = (int)std::min<int64_t>(T.host_check, cap - launched);
+      void* tk = ktimer_begin(stream);
+      for (int s = 0; s < chunk; s++)
+        hipLaunchKernelGGL(ss_step_kernel<F32>, dim3(grid), dim3(threads), 0, stream, A);
+      ktimer_end(tk, stream, chunk);
+      launched += chunk;
+      hipMemcpyAsync(done.p, &A.ctl->done, 4, hipMemcpyDeviceToHost, stream);
+      if (hipStreamSynchronize(stream) != hipSuccess) break;
+      if (*done.p) { finished = true; break; }
+      if (mode == 3) break;
+    }
+    st = hip_check(hipGetLastError(), "step launches");
+    if (st != DAWN_OK) return st;
+  }
+  if (mode == 2 || (mode == 3 && !finished)) {
     int grid = persistent_grid(ss_persistent_kernel<F32>, threads);
     if (T.grid > 0 && T.grid < grid) grid = T.grid;
     SsArgs a = A;
@@ -701,29 +909,6 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
     }
     ktimer_end(tk, stream, 1);
     st = hip_check(e, "persistent launch");
-    if (st != DAWN_OK) return st;
-  } else {
-    if (capture) return set_error(DAWN_E_UNSUPPORTED, "step launches cannot be captured");
-    const int grid = T.grid > 0 ? T.grid : 4 * di.cus;
-    uint32_t* h_done = nullptr;
-    if (hipHostMalloc((void**)&h_done, 4, hipHostMallocDefault) != hipSuccess)
-      return set_error(DAWN_E_HIP, "hipHostMalloc failed");
-    *h_done = 0;
-    int64_t launched = 0;
-    const int64_t cap = (int64_t)A.n + 1;
-    while (launched < cap) {
-      const int chunk = (int)std::min<int64_t>(T.host_check, cap - launched);
-      void* tk = ktimer_begin(stream);
-      for (int s = 0; s < chunk; s++)
-        hipLaunchKernelGGL(ss_step_kernel<F32>, dim3(grid), dim3(threads), 0, stream, A);
-      ktimer_end(tk, stream, chunk);
-      launched += chunk;
-      hipMemcpyAsync(h_done, &A.ctl->done, 4, hipMemcpyDeviceToHost, stream);
-      if (hipStreamSynchronize(stream) != hipSuccess) break;
-      if (*h_done) break;
-    }
-    hipHostFree(h_done);
-    st = hip_check(hipGetLastError(), "step launches");
     if (st != DAWN_OK) return st;
   }
   if (info) {

@@ -115,20 +115,71 @@ __device__ __forceinline__ void tile_prologue(TileCtl* C, uint32_t step, int K) 
       st_agent_i(&C->colsteps[j], ld_agent_i(&C->colsteps[j]) + 1);
 }
 
+// Queued vertices are gathered per workgroup in LDS (per tier) and written to
+// the global queues with one atomicAdd per tier per flush; each workgroup
+// scans a contiguous range of vertices, so the queues come out nearly sorted.
+constexpr int kCompactLds = 2048;
+
+struct CompactShared {
+  int32_t q[2][kCompactLds];
+  uint32_t cnt[2];
+  uint32_t base[2];
+  uint32_t nch, chbase;  // workgroup-chunk records of the current batch of vertices
+};
+
+__device__ __forceinline__ void compact_push(bool pred, int32_t v, int t, CompactShared& sh) {
+  const unsigned long long b = __ballot(pred);
+  if (b == 0ull) return;
+  const int leader = __ffsll((long long)b) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(&sh.cnt[t], (uint32_t)__popcll(b));
+  base = __shfl(base, leader, kWave);
+  if (pred) sh.q[t][base + lanes_below(b)] = v;
+}
+
+// Write the gathered entries of both tiers to the global queues of slot q.
+// Reached by the whole workgroup.
+__device__ __forceinline__ void compact_flush(const TileArgs& A, int q, int rc,
+                                              CompactShared& sh) {
+  TileCtl* C = A.ctl;
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const uint32_t c = sh.cnt[threadIdx.x];
+    sh.base[threadIdx.x] = c ? atomicAdd(&C->cnt[rc][threadIdx.x], c) : 0u;
+  }
+  __syncthreads();
+  for (int t = 0; t < 2; t++) {
+    int32_t* gq = t == 0 ? A.qgrp[q] : A.qwave[q];
+    const uint32_t c = sh.cnt[t], b = sh.base[t];
+    for (uint32_t j = threadIdx.x; j < c; j += blockDim.x) {
+      if (b + j < A.cap_v) gq[b + j] = sh.q[t][j];
+      else atomicOr(&C->overflow, 1u);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) sh.cnt[threadIdx.x] = 0u;
+  __syncthreads();
+}
+
 // Counts, from step 1 on, the (vertex, source) pairs whose distance the
 // previous step lowered (a pair lowered twice in one step counts once).
 __device__ __forceinline__ void tile_compact(const TileArgs& A, uint32_t step, uint32_t gb,
-                                             uint32_t nb, Acc& acc) {
+                                             uint32_t nb, Acc& acc, CompactShared& sh) {
   TileCtl* C = A.ctl;
   const int q = step % 3, rc = step % kRot;
   const int nseg = A.nseg;
-  const int64_t n = A.n;
-  for (int64_t v0 = (int64_t)gb * blockDim.x; v0 < n; v0 += (int64_t)nb * blockDim.x) {
+  const int64_t n = A.n, bd = blockDim.x;
+  const int64_t per = ((n + nb - 1) / nb + bd - 1) / bd * bd;
+  const int64_t lo = (int64_t)gb * per, hi = min(n, lo + per);
+  if (threadIdx.x < 2) sh.cnt[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) sh.nch = 0u;
+  __syncthreads();
+  for (int64_t v0 = lo; v0 < hi; v0 += bd) {
     const int64_t v = v0 + threadIdx.x;
     unsigned long long* mp = A.mk[q] + v * nseg;
     unsigned long long any = 0ull;
     uint32_t pairs = 0u;
-    if (v < n)
+    if (v < hi)
       for (int s = 0; s < nseg; s++) {
         const unsigned long long x = mp[s];
         any |= x;
@@ -142,22 +193,37 @@ __device__ __forceinline__ void tile_compact(const TileArgs& A, uint32_t step, u
       if (deg == 0)  // nothing to expand: the row never enters a queue
         for (int s = 0; s < nseg; s++) mp[s] = 0ull;
     }
-    const bool tg = any && deg > 0 && deg <= A.t_group;
-    const bool tw = any && deg > A.t_group && deg <= A.t_wave;
-    wave_push(tg, (int32_t)v, A.qgrp[q], &C->cnt[rc][0], A.cap_v, &C->overflow);
-    wave_push(tw, (int32_t)v, A.qwave[q], &C->cnt[rc][1], A.cap_v, &C->overflow);
-    if (any && deg > A.t_wave) {
-      const uint32_t nch = (uint32_t)((deg + A.t_chunk - 1) / A.t_chunk);
-      const uint32_t base = atomicAdd(&C->cnt[rc][2], nch);
-      for (uint32_t c = 0; c < nch; c++) {
-        const int32_t off = (int32_t)c * A.t_chunk;
-        if (base + c < A.cap_wg)
-          A.qwg[q][base + c] = make_int4((int32_t)v, start + off, min(A.t_chunk, deg - off), c == 0);
-        else
-          atomicOr(&C->overflow, 1u);
-      }
+    compact_push(any && deg > 0 && deg <= A.t_group, (int32_t)v, 0, sh);
+    compact_push(any && deg > A.t_group && deg <= A.t_wave, (int32_t)v, 1, sh);
+    // workgroup-chunk records: reserve within the workgroup, then one global
+    // reservation per batch
+    const bool hub = any && deg > A.t_wave;
+    const uint32_t nch = hub ? (uint32_t)((deg + A.t_chunk - 1) / A.t_chunk) : 0u;
+    uint32_t loc = 0u;
+    if (hub) loc = atomicAdd(&sh.nch, nch);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      sh.chbase = sh.nch ? atomicAdd(&C->cnt[rc][2], sh.nch) : 0u;
+      sh.nch = 0u;
     }
+    __syncthreads();
+    // every wavefront reads the same counts: no push happens until the
+    // barrier below
+    const bool flush =
+        sh.cnt[0] > (uint32_t)(kCompactLds - bd) || sh.cnt[1] > (uint32_t)(kCompactLds - bd);
+    const uint32_t chbase = sh.chbase;
+    for (uint32_t c = 0; c < nch; c++) {
+      const int32_t off = (int32_t)c * A.t_chunk;
+      const uint32_t p = chbase + loc + c;
+      if (p < A.cap_wg)
+        A.qwg[q][p] = make_int4((int32_t)v, start + off, min(A.t_chunk, deg - off), c == 0);
+      else
+        atomicOr(&C->overflow, 1u);
+    }
+    __syncthreads();
+    if (flush) compact_flush(A, q, rc, sh);
   }
+  compact_flush(A, q, rc, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -382,6 +448,7 @@ template <bool F32>
 __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32_t max_steps,
                                                                int32_t cap_n) {
   __shared__ unsigned long long sh_colact[kSegMax];
+  __shared__ CompactShared csh;
   TileCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
   Acc acc;
@@ -393,7 +460,7 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   bool finished = false;
   for (;;) {
     if (blockIdx.x == 0) tile_prologue(C, step, A.K);
-    tile_compact(A, step, blockIdx.x, gridDim.x, acc);
+    tile_compact(A, step, blockIdx.x, gridDim.x, acc, csh);
     if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       finished = true;
@@ -425,12 +492,13 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
 // Step launches: the compaction of a step, then its relaxation, whose last
 // workgroup advances the step and detects the end.
 __global__ void __launch_bounds__(1024) tile_compact_kernel(TileArgs A) {
+  __shared__ CompactShared csh;
   TileCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
   const uint32_t step = ld_agent(&C->step);
   if (blockIdx.x == 0) tile_prologue(C, step, A.K);
   Acc acc;
-  tile_compact(A, step, blockIdx.x, gridDim.x, acc);
+  tile_compact(A, step, blockIdx.x, gridDim.x, acc, csh);
   flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
 }
 
@@ -670,9 +738,10 @@ static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_
   const int cus = dev_info().cus;
   const int grid = T.grid > 0 ? T.grid
                               : (int)std::max<int64_t>(cus, std::min<int64_t>(16 * cus, ((int64_t)a.n + 63) / 64));
-  const int cgrid = std::min(16 * dev_info().cus, (int)std::max<int64_t>(1, ((int64_t)a.n + 255) / 256));
+  // compaction: one 1024-thread workgroup per CU (fewer for small graphs)
+  const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, ((int64_t)a.n + 1023) / 1024));
   for (int s = 0; s < max_steps; s++) {
-    hipLaunchKernelGGL(tile_compact_kernel, dim3(cgrid), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(tile_compact_kernel, dim3(cgrid), dim3(1024), 0, stream, a);
     void* tk = ktimer_begin(stream);
     hipLaunchKernelGGL(tile_step_kernel<F32>, dim3(grid), dim3(threads), 0, stream, a, 0);
     ktimer_end(tk, stream, 1);

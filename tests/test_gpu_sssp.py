@@ -33,7 +33,7 @@ def test_er_small_bitexact(dawn):
         assert info["converged"] == 1
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("wk", ["u32", "f32lognormal", "f32range02", "f32unit"])
 def test_rmat_weight_kinds(dawn, wk, mode):
     g = graphgen.rmat(14, 16, 5, weights=wk)
@@ -56,6 +56,9 @@ TUNINGS = [
     dict(mode=1, t_lane=2, t_wave=64, t_chunk=256, host_check=5),
     dict(small_m=1 << 30),                    # one workgroup for the whole graph
     dict(small_m=1 << 30, wg_threads=256),
+    dict(step_min_m=0, host_check=2),         # step launches, then a persistent launch
+    dict(step_min_m=0, host_check=1, wg_threads=1024, t_lane=2, t_wave=64, t_chunk=256),
+    dict(step_min_m=0),
 ]
 
 
@@ -77,6 +80,18 @@ def test_grid_f32_small(dawn):
         d, info = _run(dawn, g, s)
         assert_sssp_matches(g, s, d, tag="grid")
         assert info["steps"] > 96   # a high-step-count case
+
+
+def test_grid_f32_tiny_and_small_paths(dawn):
+    """n <= 6144 runs with its whole state in LDS, larger small graphs in one
+    workgroup over global memory; both many-step fp32 cases match the oracle."""
+    for rows, cols in ((60, 60), (90, 90)):
+        g = graphgen.grid(rows, cols, 0.02, 5, weights="f32unit")
+        for s in graphgen.pick_sources(g, 2, 3):
+            announce("grid", rows, cols, "f32 source", s)
+            d, info = _run(dawn, g, s)
+            assert_sssp_matches(g, s, d, tag=f"grid{rows}")
+            assert info["steps"] > rows
 
 
 @pytest.mark.parametrize("small_m", [None, 0, 1 << 30])
