@@ -51,7 +51,7 @@ def kernel_sources_sha256() -> str:
 # tuning fields that shape the tile's launches (the others only concern
 # single-source runs)
 TILE_TUNING_KEYS = ("wg_threads", "grid", "mode", "host_check", "tile_k", "tile_t_wave",
-                    "tile_t_chunk", "tile_t_group", "tile_skip")
+                    "tile_t_chunk", "tile_t_group", "tile_skip", "tile_sparse")
 
 
 def measured_traffic(tuning: dict, workload: str):

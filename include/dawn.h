@@ -146,6 +146,9 @@ typedef struct {
                            0 = never */
   int32_t step_min_m;   /* mode 0: graphs with at least this many edges start with step
                            launches (see mode); default 1 << 25 */
+  int32_t tile_sparse;  /* tile rows (and workgroup chunks) with at most this many active
+                           sources are relaxed one edge per lane, 4 bytes per source,
+                           instead of 16 lanes per 64-source segment; 0..512, default 8 */
 } dawn_tuning;
 
 #define DAWN_TILE_K_MAX 512

@@ -46,7 +46,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
                 ("t_lane", "t_wave", "t_chunk", "wg_threads", "grid", "mode", "host_check",
                  "tile_k", "tile_t_wave", "tile_t_chunk", "validate", "coop", "tile_t_group",
-                 "tile_skip", "small_m", "step_min_m")]
+                 "tile_skip", "small_m", "step_min_m", "tile_sparse")]
 
 
 INFO_BYTES = ctypes.sizeof(RunInfo)

@@ -66,7 +66,7 @@ static bool tuning_ok(const Tuning& t) {
          t.tile_t_chunk >= 64 && t.tile_t_chunk <= 65536 && (t.validate == 0 || t.validate == 1) &&
          (t.coop == 0 || t.coop == 1) && t.tile_t_group >= 0 && t.tile_t_group <= 64 &&
          t.tile_t_group < t.tile_t_wave && (t.tile_skip == 0 || t.tile_skip == 1) &&
-         t.small_m >= 0 && t.step_min_m >= 0;
+         t.small_m >= 0 && t.step_min_m >= 0 && t.tile_sparse >= 0 && t.tile_sparse <= 512;
 }
 
 static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
@@ -241,6 +241,7 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->tile_skip = t.tile_skip;
   out->small_m = t.small_m;
   out->step_min_m = t.step_min_m;
+  out->tile_sparse = t.tile_sparse;
   return DAWN_OK;
 }
 
@@ -263,6 +264,7 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.tile_skip = in->tile_skip;
     t.small_m = in->small_m;
     t.step_min_m = in->step_min_m;
+    t.tile_sparse = in->tile_sparse;
   }
   if (!tuning_ok(t)) return set_error(DAWN_E_INVALID, "tuning out of range");
   g_tuning = t;

@@ -266,6 +266,7 @@ struct TileArgs {
   int32_t n, m, K, nseg;
   int32_t t_group, t_wave, t_chunk;
   int32_t skip;               // skip (row, source) pairs already lowered again this step
+  int32_t sparse;             // rows with at most this many active sources: one edge per lane
   unsigned long long* mk[3];  // per-vertex active-source masks [step % 3][n][nseg]
   int32_t* qgrp[3];           // union frontier, 16-lane-group tier [step % 3]
   int32_t* qwave[3];          // union frontier, wave tier

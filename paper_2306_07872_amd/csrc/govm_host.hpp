@@ -27,6 +27,7 @@ struct Tuning {
   int32_t tile_skip = 0;
   int32_t small_m = 131072;
   int32_t step_min_m = 1 << 25;
+  int32_t tile_sparse = 8;
 };
 
 Tuning& tuning();

@@ -233,10 +233,59 @@ __device__ __forceinline__ uint32_t elem4(const uint4& x, int i) {
   return i == 0 ? x.x : i == 1 ? x.y : i == 2 ? x.z : x.w;
 }
 
+// OR over the 16 lanes of a row of the wavefront (lanes 16r..16r+15); every
+// lane of the row gets the result.  DPP row rotations stay in the VALU (a
+// cross-lane shuffle would go through the LDS crossbar).
+// Value of a 64-bit register in lane `src` (wave-uniform), as a scalar.
+__device__ __forceinline__ unsigned long long lane64(unsigned long long x, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t row16_or(uint32_t x) {
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x121, 0xF, 0xF, false);  // row_ror:1
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x122, 0xF, 0xF, false);  // row_ror:2
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xF, 0xF, false);  // row_ror:4
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false);  // row_ror:8
+  return x;
+}
+
+// Value of lane n (0..15) of this lane's 16-lane row (DPP row_share, VALU
+// only).  n must fold to a constant.
+__device__ __forceinline__ int row_share(int x, int n) {
+  switch (n) {
+    case 0: return __builtin_amdgcn_update_dpp(0, x, 0x150, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x151, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, x, 0x152, 0xF, 0xF, false);
+    case 3: return __builtin_amdgcn_update_dpp(0, x, 0x153, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_update_dpp(0, x, 0x154, 0xF, 0xF, false);
+    case 5: return __builtin_amdgcn_update_dpp(0, x, 0x155, 0xF, 0xF, false);
+    case 6: return __builtin_amdgcn_update_dpp(0, x, 0x156, 0xF, 0xF, false);
+    case 7: return __builtin_amdgcn_update_dpp(0, x, 0x157, 0xF, 0xF, false);
+    case 8: return __builtin_amdgcn_update_dpp(0, x, 0x158, 0xF, 0xF, false);
+    case 9: return __builtin_amdgcn_update_dpp(0, x, 0x159, 0xF, 0xF, false);
+    case 10: return __builtin_amdgcn_update_dpp(0, x, 0x15A, 0xF, 0xF, false);
+    case 11: return __builtin_amdgcn_update_dpp(0, x, 0x15B, 0xF, 0xF, false);
+    case 12: return __builtin_amdgcn_update_dpp(0, x, 0x15C, 0xF, 0xF, false);
+    case 13: return __builtin_amdgcn_update_dpp(0, x, 0x15D, 0xF, 0xF, false);
+    case 14: return __builtin_amdgcn_update_dpp(0, x, 0x15E, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_update_dpp(0, x, 0x15F, 0xF, 0xF, false);
+  }
+}
+
 // Relax edges [start, start+len) of one frontier row for the 4 sources of
 // segment sg that this lane covers (`bits`; `du` = the row's distances of
 // those sources).  `ngroups` 16-lane groups share the row; this lane's group
-// is `gidx`.  The loop count is uniform within a group.
+// is `gidx`.  Loop counts are uniform within a group.
+//
+// A group takes 16 edges at a time: lane j loads edge j's id and weight (one
+// coalesced load each), and the 16 edges are walked kTileU at a time with the
+// id and weight broadcast along the row (DPP); the next 16 are requested
+// before the current ones are relaxed.  Within a batch all candidates are
+// compared before any atomic is issued and the atomics go out back to back
+// (gfx9's vector-memory counter also counts non-returning atomics, in order,
+// so an atomic between two compares would make the second wait for it).
 template <bool F32>
 __device__ __forceinline__ void tile_seg_relax(const TileArgs& A, int32_t start, int32_t len,
                                                int sg, uint32_t bits, const uint4& du, int gidx,
@@ -246,49 +295,72 @@ __device__ __forceinline__ void tile_seg_relax(const TileArgs& A, int32_t start,
   const int j16 = threadIdx.x & 15;
   const int col = sg * 64 + 4 * j16;
   const int K = A.K, nseg = A.nseg;
-  for (int32_t e0 = gidx * U; e0 < len; e0 += ngroups * U) {
-    int32_t v[U];
-    uint32_t w[U];
-#pragma unroll
-    for (int i = 0; i < U; i++) {
-      const int32_t e = e0 + i;
-      v[i] = -1;
-      w[i] = 0u;
-      if (e < len) {
-        v[i] = A.colidx[start + e];
-        w[i] = A.w[start + e];
+  const int32_t stride = ngroups * 16;
+  int32_t eb = gidx * 16;
+  if (eb >= len) return;
+  int32_t cvn = -1;
+  uint32_t cwn = 0u;
+  if (eb + j16 < len) {
+    cvn = A.colidx[start + eb + j16];
+    cwn = A.w[start + eb + j16];
+  }
+  for (; eb < len; eb += stride) {
+    const int32_t cv = cvn;
+    const uint32_t cw = cwn;
+    const int cnt = min(16, len - eb);
+    if (eb + stride < len) {
+      cvn = -1;
+      cwn = 0u;
+      if (eb + stride + j16 < len) {
+        cvn = A.colidx[start + eb + stride + j16];
+        cwn = A.w[start + eb + stride + j16];
       }
     }
-    uint4 dv[U];
 #pragma unroll
-    for (int i = 0; i < U; i++) {
-      dv[i] = make_uint4(0u, 0u, 0u, 0u);
-      if (v[i] >= 0 && bits) dv[i] = *reinterpret_cast<const uint4*>(A.D + (size_t)v[i] * K + col);
-    }
+    for (int i0 = 0; i0 < 16; i0 += U) {
+      if (i0 >= cnt) break;
+      int32_t v[U];
+      uint32_t w[U];
 #pragma unroll
-    for (int i = 0; i < U; i++) {
-      uint32_t imp = 0u;
-      if (v[i] >= 0) {
-        uint32_t* dp = A.D + (size_t)v[i] * K + col;
+      for (int i = 0; i < U; i++) {
+        v[i] = i0 + i < cnt ? row_share(cv, i0 + i) : -1;
+        w[i] = (uint32_t)row_share((int)cw, i0 + i);
+      }
+      uint4 dv[U];
+#pragma unroll
+      for (int i = 0; i < U; i++) {
+        dv[i] = make_uint4(0u, 0u, 0u, 0u);
+        if (v[i] >= 0 && bits) dv[i] = *reinterpret_cast<const uint4*>(A.D + (size_t)v[i] * K + col);
+      }
+      uint32_t imp[U];
+#pragma unroll
+      for (int i = 0; i < U; i++) {
+        imp[i] = 0u;
 #pragma unroll
         for (int t = 0; t < 4; t++) {
-          if ((bits >> t) & 1u) {
-            const uint32_t c = relax_add<F32>(elem4(du, t), w[i]);
-            if (c < elem4(dv[i], t)) {
-              atomicMin(dp + t, c);  // result unused: a non-returning atomic
-              imp |= 1u << t;
-            }
-          }
+          const uint32_t c = relax_add<F32>(elem4(du, t), w[i]);
+          if (v[i] >= 0 && ((bits >> t) & 1u) && c < elem4(dv[i], t)) imp[i] |= 1u << t;
         }
       }
-      unsigned long long x = (unsigned long long)imp << (4 * j16);
-      x |= __shfl_xor(x, 1, 16);
-      x |= __shfl_xor(x, 2, 16);
-      x |= __shfl_xor(x, 4, 16);
-      x |= __shfl_xor(x, 8, 16);
-      if (j16 == 0 && x != 0ull) {
-        atomicOr(mk_next + (size_t)v[i] * nseg + sg, x);
-        atomicOr(&sh_colact[sg], x);
+#pragma unroll
+      for (int i = 0; i < U; i++) {
+        if (imp[i]) {
+          uint32_t* dp = A.D + (size_t)v[i] * K + col;
+#pragma unroll
+          for (int t = 0; t < 4; t++)
+            if ((imp[i] >> t) & 1u) atomicMin(dp + t, relax_add<F32>(elem4(du, t), w[i]));
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < U; i++) {
+        // the group's 64 improvement bits of segment sg: lane j16 holds bits 4*j16..4*j16+3
+        const uint32_t lo = row16_or(j16 < 8 ? imp[i] << (4 * j16) : 0u);
+        const uint32_t hi = row16_or(j16 >= 8 ? imp[i] << (4 * (j16 - 8)) : 0u);
+        const unsigned long long x = ((unsigned long long)hi << 32) | lo;
+        if (j16 == 0 && x != 0ull) {
+          atomicOr(mk_next + (size_t)v[i] * nseg + sg, x);
+          atomicOr(&sh_colact[sg], x);
+        }
       }
     }
   }
@@ -306,6 +378,91 @@ __device__ __forceinline__ unsigned long long tile_row_mask(const TileArgs& A, i
   unsigned long long x = A.mk[q][i];
   if (A.skip && x) x &= ~A.mk[qn][i];
   return x;
+}
+
+// Relax edges [start, start+len) of row u for its few active sources, one
+// edge per lane: lane t of a team of nt lanes takes edges t, t+nt, ...  For
+// each active source (column j) the team streams the row once, each lane
+// loading 4 bytes of its target's distances.  Used for rows with at most
+// tile_sparse active sources, where the segment mapping (16 lanes per 64
+// sources) would leave most lanes idle: early steps reach hub rows of
+// thousands of edges for one or two sources.
+template <bool F32>
+__device__ __forceinline__ void tile_sparse_relax(const TileArgs& A, int32_t u, int32_t start,
+                                                  int32_t len, int q, int qn, int t, int nt,
+                                                  unsigned long long* mk_next,
+                                                  unsigned long long* sh_colact) {
+  const int K = A.K, nseg = A.nseg;
+  for (int sg = 0; sg < nseg; sg++) {
+    unsigned long long x = tile_row_mask(A, q, qn, u, sg);
+    while (x) {
+      const int b = __ffsll((long long)x) - 1;
+      x &= x - 1ull;
+      const int j = sg * 64 + b;
+      const unsigned long long bit = 1ull << b;
+      const uint32_t duj = A.D[(size_t)u * K + j];
+      bool any = false;
+      for (int32_t e0 = t; e0 < len; e0 += 2 * nt) {
+        const int32_t e1 = e0 + nt;
+        const int32_t v0 = A.colidx[start + e0];
+        const uint32_t w0 = A.w[start + e0];
+        int32_t v1 = -1;
+        uint32_t w1 = 0u;
+        if (e1 < len) {
+          v1 = A.colidx[start + e1];
+          w1 = A.w[start + e1];
+        }
+        const uint32_t d0 = A.D[(size_t)v0 * K + j];
+        const uint32_t d1 = v1 >= 0 ? A.D[(size_t)v1 * K + j] : 0u;
+        const uint32_t c0 = relax_add<F32>(duj, w0), c1 = relax_add<F32>(duj, w1);
+        const bool i0 = c0 < d0, i1 = v1 >= 0 && c1 < d1;
+        if (i0) {
+          atomicMin(A.D + (size_t)v0 * K + j, c0);
+          atomicOr(mk_next + (size_t)v0 * nseg + sg, bit);
+        }
+        if (i1) {
+          atomicMin(A.D + (size_t)v1 * K + j, c1);
+          atomicOr(mk_next + (size_t)v1 * nseg + sg, bit);
+        }
+        any |= i0 | i1;
+      }
+      if (any) atomicOr(&sh_colact[sg], bit);
+    }
+  }
+}
+
+// Lane l sets up row b0 + l of queue `qq` (count n): its vertex, row bounds
+// and active segments (bit s: mask word s non-zero), and counts the row.
+// Rows past the count get act = 0.
+__device__ __forceinline__ void tile_row_setup(const TileArgs& A, const int32_t* qq, uint32_t n,
+                                               uint32_t b0, int q, int qn, int32_t& u,
+                                               int32_t& start, int32_t& deg, uint32_t& act,
+                                               uint32_t& nsrc, Acc& acc) {
+  const uint32_t i = b0 + (uint32_t)lane_id();
+  u = 0;
+  start = 0;
+  deg = 0;
+  act = 0u;
+  nsrc = 0u;
+  if (i >= n) return;
+  u = ld_queue(qq + i);
+  start = A.rowptr[u];
+  deg = A.rowptr[u + 1] - start;
+  unsigned long long ns = 0ull;
+  for (int s = 0; s < A.nseg; s++) {
+    const unsigned long long x = tile_row_mask(A, q, qn, u, s);
+    if (x) {
+      act |= 1u << s;
+      ns += (unsigned long long)__popcll(x);
+    }
+  }
+  nsrc = (uint32_t)ns;
+  if (act) {
+    acc.fe += 1;
+    acc.es += (unsigned long long)deg;
+    acc.sa += ns;
+    acc.se += (unsigned long long)deg * ns;
+  }
 }
 
 template <bool F32>
@@ -365,9 +522,20 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
         acc.sa += (unsigned long long)ns;
       }
     }
+    // The path must be the same for every wavefront of the workgroup (each
+    // covers only its share of the chunk), so it is chosen from this step's
+    // mask, which no lane changes during the step.
+    int nsc = lane < nseg ? __popcll(A.mk[q][(size_t)r.x * nseg + lane]) : 0;
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) nsc += __shfl_xor(nsc, off, kWave);
+    nsc = __builtin_amdgcn_readlane(nsc, 0);  // lanes 0..7 hold the sum; make it uniform
+    if (nsc <= A.sparse) {
+      tile_sparse_relax<F32>(A, r.x, r.y, r.z, q, qn, threadIdx.x, blockDim.x, mkn, sh_colact);
+      continue;
+    }
     for (uint32_t a = act; a; a &= a - 1u) {
       const int sg = __ffs(a) - 1;
-      const unsigned long long xs = __shfl(x, sg);
+      const unsigned long long xs = lane64(x, sg);
       const uint32_t bits = (uint32_t)(xs >> (4 * j16)) & 0xFu;
       uint4 du = make_uint4(0u, 0u, 0u, 0u);
       if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)r.x * A.K + sg * 64 + 4 * j16);
@@ -376,57 +544,61 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
     }
   }
 
-  // (c) wave tier: one wavefront per row, its 4 groups share the row
+  // (c) wave tier: one wavefront per row, its 4 groups share the row;
+  // (d) group tier: one 16-lane group per row.
+  // Rows are set up 64 at a time, one per lane (queue entry, row bounds,
+  // active segments, counters), so the setup round trips of a batch overlap;
+  // the rows are then walked from registers.
+  // Each wavefront takes an even, contiguous share of a queue.
   const uint32_t nw = min(ld_agent(&C->cnt[rc][1]), A.cap_v);
-  for (uint32_t i = gw; i < nw; i += nwv) {
-    const int32_t u = ld_queue(&A.qwave[q][i]);
-    const int32_t start = A.rowptr[u], deg = A.rowptr[u + 1] - start;
-    const unsigned long long x = lane < nseg ? tile_row_mask(A, q, qn, u, lane) : 0ull;
-    const uint32_t act = (uint32_t)__ballot(x != 0ull);
-    if (act == 0u) continue;
-    int ns = __popcll(x);
-#pragma unroll
-    for (int off = 4; off > 0; off >>= 1) ns += __shfl_xor(ns, off, kWave);
-    if (lane == 0) {
-      acc.fe += 1;
-      acc.es += (unsigned long long)deg;
-      acc.sa += (unsigned long long)ns;
-      acc.se += (unsigned long long)deg * (unsigned long long)ns;
-    }
-    for (uint32_t a = act; a; a &= a - 1u) {
-      const int sg = __ffs(a) - 1;
-      const unsigned long long xs = __shfl(x, sg);
-      const uint32_t bits = (uint32_t)(xs >> (4 * j16)) & 0xFu;
-      uint4 du = make_uint4(0u, 0u, 0u, 0u);
-      if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)u * A.K + sg * 64 + 4 * j16);
-      tile_seg_relax<F32>(A, start, deg, sg, bits, du, lane >> 4, 4, mkn, sh_colact, acc);
+  const uint32_t pw = (nw + nwv - 1) / nwv, hw = min(nw, gw * pw + pw);
+  for (uint32_t b0 = gw * pw; b0 < hw; b0 += kWave) {
+    int32_t u, start, deg;
+    uint32_t act, nsrc;
+    tile_row_setup(A, A.qwave[q], hw, b0, q, qn, u, start, deg, act, nsrc, acc);
+    const int rows = (int)min((uint32_t)kWave, hw - b0);
+    for (int r = 0; r < rows; r++) {
+      const uint32_t ar = (uint32_t)__builtin_amdgcn_readlane((int)act, r);
+      if (ar == 0u) continue;
+      const int32_t ur = __builtin_amdgcn_readlane(u, r);
+      const int32_t sr = __builtin_amdgcn_readlane(start, r);
+      const int32_t dr = __builtin_amdgcn_readlane(deg, r);
+      if ((int)__builtin_amdgcn_readlane((int)nsrc, r) <= A.sparse) {
+        tile_sparse_relax<F32>(A, ur, sr, dr, q, qn, lane, kWave, mkn, sh_colact);
+        continue;
+      }
+      for (uint32_t a = ar; a; a &= a - 1u) {
+        const int sg = __ffs(a) - 1;
+        const uint32_t bits = (uint32_t)(tile_row_mask(A, q, qn, ur, sg) >> (4 * j16)) & 0xFu;
+        uint4 du = make_uint4(0u, 0u, 0u, 0u);
+        if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)ur * A.K + sg * 64 + 4 * j16);
+        tile_seg_relax<F32>(A, sr, dr, sg, bits, du, lane >> 4, 4, mkn, sh_colact, acc);
+      }
     }
   }
 
-  // (d) group tier: one 16-lane group per row
   const uint32_t ng = min(ld_agent(&C->cnt[rc][0]), A.cap_v);
-  for (uint32_t i = gw * 4 + (lane >> 4); i < ng; i += nwv * 4) {
-    const int32_t u = ld_queue(&A.qgrp[q][i]);
-    const int32_t start = A.rowptr[u], deg = A.rowptr[u + 1] - start;
-    const unsigned long long x = j16 < nseg ? tile_row_mask(A, q, qn, u, j16) : 0ull;
-    const uint32_t act = (uint32_t)(__ballot(x != 0ull) >> gbase) & 0xFFu;
-    if (act == 0u) continue;
-    int ns = __popcll(x);
-#pragma unroll
-    for (int off = 4; off > 0; off >>= 1) ns += __shfl_xor(ns, off, 16);
-    if (j16 == 0) {
-      acc.fe += 1;
-      acc.es += (unsigned long long)deg;
-      acc.sa += (unsigned long long)ns;
-      acc.se += (unsigned long long)deg * (unsigned long long)ns;
-    }
-    for (uint32_t a = act; a; a &= a - 1u) {
-      const int sg = __ffs(a) - 1;
-      const unsigned long long xs = __shfl(x, gbase + sg);
-      const uint32_t bits = (uint32_t)(xs >> (4 * j16)) & 0xFu;
-      uint4 du = make_uint4(0u, 0u, 0u, 0u);
-      if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)u * A.K + sg * 64 + 4 * j16);
-      tile_seg_relax<F32>(A, start, deg, sg, bits, du, 0, 1, mkn, sh_colact, acc);
+  const uint32_t pg = (ng + nwv - 1) / nwv, hg = min(ng, gw * pg + pg);
+  const int grp = lane >> 4;
+  for (uint32_t b0 = gw * pg; b0 < hg; b0 += kWave) {
+    int32_t u, start, deg;
+    uint32_t act, nsrc;
+    tile_row_setup(A, A.qgrp[q], hg, b0, q, qn, u, start, deg, act, nsrc, acc);
+    const int rows = (int)min((uint32_t)kWave, hg - b0);
+    // group g walks rows b0 + 4 r + g, held by lane 4 r + g
+    for (int r = 0; 4 * r < rows; r++) {
+      const int src = 4 * r + grp;
+      const uint32_t ar = (uint32_t)__shfl((int)act, src, kWave);
+      const int32_t ur = __shfl(u, src, kWave);
+      const int32_t sr = __shfl(start, src, kWave);
+      const int32_t dr = __shfl(deg, src, kWave);
+      for (uint32_t a = ar; a; a &= a - 1u) {
+        const int sg = __ffs(a) - 1;
+        const uint32_t bits = (uint32_t)(tile_row_mask(A, q, qn, ur, sg) >> (4 * j16)) & 0xFu;
+        uint4 du = make_uint4(0u, 0u, 0u, 0u);
+        if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)ur * A.K + sg * 64 + 4 * j16);
+        tile_seg_relax<F32>(A, sr, dr, sg, bits, du, 0, 1, mkn, sh_colact, acc);
+      }
     }
   }
 
@@ -633,6 +805,7 @@ TileArgs tile_args(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.t_chunk = T.tile_t_chunk;
   A.t_group = T.tile_t_group;
   A.skip = T.tile_skip;
+  A.sparse = T.tile_sparse;
   for (int i = 0; i < 3; i++) {
     A.mk[i] = reinterpret_cast<unsigned long long*>(base + L.mk[i]);
     A.qgrp[i] = reinterpret_cast<int32_t*>(base + L.qgrp[i]);

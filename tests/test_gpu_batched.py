@@ -48,6 +48,9 @@ TILE_TUNINGS = [
     dict(tile_t_group=31, tile_t_wave=32, tile_t_chunk=64, wg_threads=512),
     dict(mode=2, tile_skip=0),
     dict(mode=2, tile_t_group=64, tile_t_wave=100, wg_threads=1024),
+    dict(tile_sparse=0),                    # segment mapping everywhere
+    dict(tile_sparse=512, tile_skip=1),     # one edge per lane everywhere
+    dict(tile_sparse=3, tile_t_wave=32, tile_t_chunk=64, tile_skip=1, wg_threads=512),
 ]
 
 
