@@ -117,6 +117,8 @@ def main() -> int:
     ap.add_argument("--plain", type=int, default=256, help="sources timed one per launch")
     ap.add_argument("--cpu-sample", type=int, default=256, help="sources timed on the oracle")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-pull", action="store_true",
+                    help="no reverse graph: every tile step pushes")
     ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
                     help="library tuning field (see dawn_tuning), repeatable")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -151,6 +153,16 @@ def main() -> int:
     g, srcs = workloads.rmat20_tile(k=args.k, scale=args.scale)
     log(f"graph {g.name}: n={g.n} m={g.m} k={len(srcs)} ({time.perf_counter() - t_gen:.1f}s)")
     csr = dawn.Csr.from_graph(g)
+    # the reverse graph for pull steps: built once per graph, like the CSR
+    tg = None
+    t_tg = 0.0
+    if not args.no_pull:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tg = dawn.tgraph(csr)
+        torch.cuda.synchronize()
+        t_tg = time.perf_counter() - t0
+        log(f"reverse graph built in {t_tg * 1e3:.1f} ms")
     src_t = torch.as_tensor(srcs, dtype=torch.int32, device="cuda")
     k = int(src_t.numel())
     out = torch.empty((k, g.n), dtype=torch.uint32, device="cuda")
@@ -160,13 +172,13 @@ def main() -> int:
 
     # ---- batched: warmup, then K timed steps --------------------------------
     for _ in range(args.warmup):
-        dawn.msssp(csr, src_t, out=out, ws=ws, info=info)
+        dawn.msssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg)
     torch.cuda.synchronize()
     dawn.kernel_timer(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        dawn.msssp(csr, src_t, out=out, ws=ws, info=info)
+        dawn.msssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dawn.kernel_timer(False)
@@ -210,7 +222,12 @@ def main() -> int:
     avg_kms = k_ms / max(k_launches, 1)
     per_launch_bytes = kbytes_call * args.steps / max(k_launches, 1)
     achieved = per_launch_bytes / (avg_kms * 1e-3) / 1e9
-    kname = "tile_step_kernel<false>" if tune["mode"] in (0, 1) else "tile_persistent_kernel<false>"
+    if tune["mode"] == 2:
+        kname = "tile_persistent_kernel<false>"
+    elif tg is not None:
+        kname = "tile relaxation: tile_step_kernel<false> (push steps) + tile_pull_kernel<false> (pull steps)"
+    else:
+        kname = "tile_step_kernel<false>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(tune, f"rmat{args.scale}_ef16_u32_k{k}"),
@@ -249,7 +266,9 @@ def main() -> int:
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"rmat{args.scale}_ef16_u32_k{k}", "n": g.n, "m": g.m, "k": k,
-                   "weights": "uint32 uniform [1,255]", "sources": "uniform among out-degree>=1"},
+                   "weights": "uint32 uniform [1,255]", "sources": "uniform among out-degree>=1",
+                   "reverse_graph": tg is not None,
+                   "reverse_graph_build_ms": round(t_tg * 1e3, 2) if tg is not None else None},
         "sources_per_s": round(srcs_per_s, 1),
         "plain_sources_per_s": round(1.0 / plain_s, 1) if nplain else None,
         "plain_gteps": round(plain_gteps, 3) if nplain else None,

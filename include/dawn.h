@@ -149,6 +149,10 @@ typedef struct {
   int32_t tile_sparse;  /* tile rows (and workgroup chunks) with at most this many active
                            sources are relaxed one edge per lane, 4 bytes per source,
                            instead of 16 lanes per 64-source segment; 0..512, default 8 */
+  int32_t tile_pull;    /* with a reverse graph (dawn_msssp_tg_ws), a tile step whose
+                           frontier rows hold at least tile_pull / 1000 of the m edges is
+                           run as a pull step over the in-edges of every vertex; 0 = every
+                           step, 1001 = never; default 400 */
 } dawn_tuning;
 
 #define DAWN_TILE_K_MAX 512
@@ -203,6 +207,37 @@ dawn_status dawn_msssp_ws(const int32_t* rowptr_dev, const int32_t* colidx_dev,
 dawn_status dawn_apsp(const int32_t* rowptr_dev, const int32_t* colidx_dev,
                       const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
                       void* dist_out_dev, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Reverse graph and pull steps (direction-optimising tile steps).
+ *
+ * Algorithm 2 expands the rows of the frontier (push).  When the frontier's
+ * rows hold a large share of the edges, the same relaxations -- every edge
+ * (u, v) with u active for a source -- can be done per target v over its
+ * in-edges (pull): each v is then written by one wavefront with plain stores,
+ * with no atomics.  A pull step needs the reverse graph, built once per graph
+ * into an opaque device buffer owned by the caller (layout private to the
+ * library; valid while the CSR it was built from is unchanged).  Results are
+ * identical with and without pull steps.
+ * ------------------------------------------------------------------------- */
+size_t dawn_tgraph_bytes(int32_t n, int32_t m);
+/* Scratch (device, caller-owned, 256-byte aligned) for one build. */
+size_t dawn_tgraph_build_bytes(int32_t n, int32_t m);
+/* Build the reverse graph of a valid CSR (rowptr non-decreasing, column ids in
+ * [0,n)) into tgraph_dev (256-byte aligned, >= dawn_tgraph_bytes).  Weights
+ * are copied as 32-bit patterns, so one reverse graph serves u32 and f32.
+ * Stream-ordered; nothing is kept after the call. */
+dawn_status dawn_tgraph_build(const int32_t* rowptr_dev, const int32_t* colidx_dev,
+                              const void* weights_dev, int32_t n, int32_t m, void* tgraph_dev,
+                              size_t tgraph_bytes, void* scratch_dev, size_t scratch_bytes,
+                              hipStream_t stream);
+/* dawn_msssp_ws with the reverse graph of the same CSR: tile steps whose
+ * frontier is dense (see tuning field tile_pull) run as pull steps. */
+dawn_status dawn_msssp_tg_ws(const int32_t* rowptr_dev, const int32_t* colidx_dev,
+                             const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
+                             const void* tgraph_dev, const int32_t* sources_dev, int32_t k,
+                             void* dist_out_dev, void* ws_dev, size_t ws_bytes,
+                             dawn_run_info* info_dev, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Many graphs in one launch.  A batch concatenates `count` CSR graphs of one

@@ -46,7 +46,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
                 ("t_lane", "t_wave", "t_chunk", "wg_threads", "grid", "mode", "host_check",
                  "tile_k", "tile_t_wave", "tile_t_chunk", "validate", "coop", "tile_t_group",
-                 "tile_skip", "small_m", "step_min_m", "tile_sparse")]
+                 "tile_skip", "small_m", "step_min_m", "tile_sparse", "tile_pull")]
 
 
 INFO_BYTES = ctypes.sizeof(RunInfo)
@@ -81,6 +81,11 @@ def load():
         "dawn_msssp_ws": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _sz, _vp, _vp],
                           _i32),
         "dawn_apsp": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp], _i32),
+        "dawn_tgraph_bytes": ([_i32, _i32], _sz),
+        "dawn_tgraph_build_bytes": ([_i32, _i32], _sz),
+        "dawn_tgraph_build": ([_vp, _vp, _vp, _i32, _i32, _vp, _sz, _vp, _sz, _vp], _i32),
+        "dawn_msssp_tg_ws": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp,
+                              _vp], _i32),
         "dawn_batch_create": ([ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp),
                                ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32, _vp], _i32),
@@ -117,6 +122,7 @@ def exported_symbols() -> list[str]:
         "dawn_status_str", "dawn_last_error", "dawn_build_info", "dawn_get_tuning",
         "dawn_set_tuning", "dawn_sssp", "dawn_sssp_workspace_bytes", "dawn_sssp_ws",
         "dawn_msssp", "dawn_msssp_workspace_bytes", "dawn_msssp_ws", "dawn_apsp",
+        "dawn_tgraph_bytes", "dawn_tgraph_build_bytes", "dawn_tgraph_build", "dawn_msssp_tg_ws",
         "dawn_batch_create", "dawn_batch_sizes", "dawn_batch_vertex_offset", "dawn_batch_run",
         "dawn_batch_capture", "dawn_batch_replay", "dawn_batch_destroy", "dawn_tile_bytes",
         "dawn_tile_create", "dawn_tile_admit", "dawn_tile_run", "dawn_tile_read",
@@ -282,8 +288,28 @@ def msssp_workspace_bytes(n: int, m: int, k: int) -> int:
     return int(load().dawn_msssp_workspace_bytes(n, m, k))
 
 
-def msssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None):
-    """Distances from each source: [k, n] tensor, row j = sources[j]."""
+def tgraph(csr: Csr, stream=None):
+    """The reverse graph of `csr` for pull steps (``dawn_tgraph_build``), as a
+    device byte buffer; built once and kept on the Csr object."""
+    cached = getattr(csr, "_tgraph", None)
+    if cached is not None:
+        return cached
+    dev = csr.rowptr.device
+    L = load()
+    buf = workspace(int(L.dawn_tgraph_bytes(csr.n, csr.m)), dev)
+    scratch = workspace(int(L.dawn_tgraph_build_bytes(csr.n, csr.m)), dev)
+    bp, bn = _aligned(buf)
+    sp, sn = _aligned(scratch)
+    _check(L.dawn_tgraph_build(_ptr(csr.rowptr), _ptr(csr.colidx), _ptr(csr.w), csr.n, csr.m,
+                               bp, bn, sp, sn, _stream(stream)))
+    _torch().cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    csr._tgraph = buf
+    return buf
+
+
+def msssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None, tgraph=None):
+    """Distances from each source: [k, n] tensor, row j = sources[j].  With
+    `tgraph` (from ``tgraph(csr)``) dense steps run as pull steps."""
     torch = _torch()
     dev = csr.rowptr.device
     if not torch.is_tensor(sources):
@@ -293,6 +319,14 @@ def msssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None):
     if out is None:
         out = torch.empty((k, csr.n), dtype=dist_dtype(csr.wtype), device=dev)
     L = load()
+    if tgraph is not None:
+        if ws is None:
+            ws = workspace(msssp_workspace_bytes(csr.n, csr.m, k), dev)
+        p, nb = _aligned(ws)
+        tp, _ = _aligned(tgraph)
+        _check(L.dawn_msssp_tg_ws(*_csr_args(csr), tp, _ptr(sources), k, _ptr(out), p, nb,
+                                  _ptr(info), _stream(stream)))
+        return out
     if ws is None and info is None:
         _check(L.dawn_msssp(*_csr_args(csr), _ptr(sources), k, _ptr(out), _stream(stream)))
         return out

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdawn.so")
-SOURCES = ["govm_sssp.hip", "govm_tile.hip", "dawn_api.hip"]
+SOURCES = ["govm_sssp.hip", "govm_tile.hip", "govm_transpose.hip", "dawn_api.hip"]
 HEADERS = ["govm_device.hpp", "govm_host.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -66,7 +66,8 @@ static bool tuning_ok(const Tuning& t) {
          t.tile_t_chunk >= 64 && t.tile_t_chunk <= 65536 && (t.validate == 0 || t.validate == 1) &&
          (t.coop == 0 || t.coop == 1) && t.tile_t_group >= 0 && t.tile_t_group <= 64 &&
          t.tile_t_group < t.tile_t_wave && (t.tile_skip == 0 || t.tile_skip == 1) &&
-         t.small_m >= 0 && t.step_min_m >= 0 && t.tile_sparse >= 0 && t.tile_sparse <= 512;
+         t.small_m >= 0 && t.step_min_m >= 0 && t.tile_sparse >= 0 && t.tile_sparse <= 512 &&
+         t.tile_pull >= 0 && t.tile_pull <= 1001;
 }
 
 static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
@@ -242,6 +243,7 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->small_m = t.small_m;
   out->step_min_m = t.step_min_m;
   out->tile_sparse = t.tile_sparse;
+  out->tile_pull = t.tile_pull;
   return DAWN_OK;
 }
 
@@ -265,6 +267,7 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.small_m = in->small_m;
     t.step_min_m = in->step_min_m;
     t.tile_sparse = in->tile_sparse;
+    t.tile_pull = in->tile_pull;
   }
   if (!tuning_ok(t)) return set_error(DAWN_E_INVALID, "tuning out of range");
   g_tuning = t;
@@ -342,11 +345,15 @@ __global__ void dawn_info_add_kernel(dawn_run_info* acc, const dawn_run_info* pa
 static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, const void* weights,
                               dawn_wtype wt, int32_t n, int32_t m, const int32_t* sources,
                               int32_t k, void* dist_out, void* ws, dawn_run_info* info,
-                              hipStream_t stream) {
+                              hipStream_t stream, const void* tgraph = nullptr) {
   const bool f32 = wt == DAWN_W_F32;
   const int32_t kt = std::min(k, g_tuning.tile_k);
   const TileLayout L = tile_layout(n, m, kt);
-  const TileArgs A = tile_args(rowptr, colidx, weights, n, m, L, ws);
+  TileArgs A = tile_args(rowptr, colidx, weights, n, m, L, ws);
+  if (tgraph && g_tuning.tile_pull <= 1000) {
+    A.T = tgraph_view(tgraph, n, m);
+    A.pull_min = (long long)m * g_tuning.tile_pull / 1000;
+  }
   // per-tile summary, inside the workspace (no allocation on this path)
   dawn_run_info* part = reinterpret_cast<dawn_run_info*>(static_cast<char*>(ws) + L.info);
   dawn_status st;
@@ -398,6 +405,53 @@ extern "C" dawn_status dawn_msssp_ws(const int32_t* rowptr, const int32_t* colid
   const size_t need = tile_layout(n, m, std::min(k, g_tuning.tile_k)).total;
   if (ws_bytes < need) return set_error(DAWN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
   return msssp_impl(rowptr, colidx, weights, wt, n, m, sources, k, dist_out, ws, info, stream);
+}
+
+extern "C" size_t dawn_tgraph_bytes(int32_t n, int32_t m) {
+  if (n < 1 || m < 0) return 0;
+  return tgraph_bytes(n, m);
+}
+
+extern "C" size_t dawn_tgraph_build_bytes(int32_t n, int32_t m) {
+  if (n < 1 || m < 0) return 0;
+  return tgraph_build_bytes(n, m);
+}
+
+extern "C" dawn_status dawn_tgraph_build(const int32_t* rowptr, const int32_t* colidx,
+                                         const void* weights, int32_t n, int32_t m,
+                                         void* tgraph, size_t tgraph_bytes_, void* scratch,
+                                         size_t scratch_bytes, hipStream_t stream) {
+  dawn_status st = check_graph(rowptr, colidx, weights, DAWN_W_U32, n, m);
+  if (st != DAWN_OK) return st;
+  if (!tgraph || !scratch) return set_error(DAWN_E_INVALID, "null buffer");
+  if (((reinterpret_cast<uintptr_t>(tgraph) | reinterpret_cast<uintptr_t>(scratch)) & 255u) != 0)
+    return set_error(DAWN_E_INVALID, "buffers must be 256-byte aligned");
+  if (tgraph_bytes_ < tgraph_bytes(n, m))
+    return set_error(DAWN_E_WORKSPACE, "reverse-graph buffer too small (%zu < %zu)", tgraph_bytes_,
+                     tgraph_bytes(n, m));
+  if (scratch_bytes < tgraph_build_bytes(n, m))
+    return set_error(DAWN_E_WORKSPACE, "scratch too small (%zu < %zu)", scratch_bytes,
+                     tgraph_build_bytes(n, m));
+  return tgraph_build(rowptr, colidx, weights, n, m, tgraph, scratch, stream);
+}
+
+extern "C" dawn_status dawn_msssp_tg_ws(const int32_t* rowptr, const int32_t* colidx,
+                                        const void* weights, dawn_wtype wt, int32_t n, int32_t m,
+                                        const void* tgraph, const int32_t* sources, int32_t k,
+                                        void* dist_out, void* ws, size_t ws_bytes,
+                                        dawn_run_info* info, hipStream_t stream) {
+  dawn_status st = check_graph(rowptr, colidx, weights, wt, n, m);
+  if (st != DAWN_OK) return st;
+  if (!tgraph) return set_error(DAWN_E_INVALID, "null reverse graph");
+  if (!sources || !dist_out || !ws) return set_error(DAWN_E_INVALID, "null pointer");
+  if (k < 1) return set_error(DAWN_E_INVALID, "k must be >= 1 (got %d)", k);
+  if (((reinterpret_cast<uintptr_t>(ws) | reinterpret_cast<uintptr_t>(tgraph)) & 255u) != 0)
+    return set_error(DAWN_E_INVALID, "workspace and reverse graph must be 256-byte aligned");
+  const size_t need = tile_layout(n, m, std::min(k, g_tuning.tile_k)).total;
+  if (ws_bytes < need)
+    return set_error(DAWN_E_WORKSPACE, "workspace too small (%zu < %zu)", ws_bytes, need);
+  return msssp_impl(rowptr, colidx, weights, wt, n, m, sources, k, dist_out, ws, info, stream,
+                    tgraph);
 }
 
 extern "C" dawn_status dawn_msssp(const int32_t* rowptr, const int32_t* colidx,

@@ -49,6 +49,7 @@ struct alignas(256) TileCtl {
   uint32_t bar, abort, blocks_done, overflow, bar_base;
   unsigned long long fe, es, im, sa, se;  // union rows, union edges, improvements,
                                           // per-source rows, per-source edges
+  unsigned long long fedges[kRot];      // [step % 4]: out-edges of the step's frontier rows
   int32_t colsteps[kSegMax * 64];
 };
 
@@ -257,6 +258,21 @@ struct SsArgs {
   SsCtl* ctl;
 };
 
+// The reverse graph for pull steps (built by tgraph_build): in-edge lists per
+// target, cut into chunks of at most kPullChunk in-edges.
+constexpr int kPullChunk = 1024;
+struct TGraphHeader {
+  uint32_t nchunks, pad;
+};
+struct TGraph {
+  const TGraphHeader* hdr;
+  const int32_t* rowptr;   // [n+1]
+  const int32_t* colidx;   // [m] source vertex of each in-edge
+  const uint32_t* w;       // [m]
+  const int4* chunks;      // {target, first in-edge, count, split (target has several chunks)}
+  int64_t cap_chunks;
+};
+
 // Kernel arguments of a batched [n x K] distance-tile run (K = 64 * nseg).
 struct TileArgs {
   const int32_t* rowptr;
@@ -271,8 +287,11 @@ struct TileArgs {
   int32_t* qgrp[3];           // union frontier, 16-lane-group tier [step % 3]
   int32_t* qwave[3];          // union frontier, wave tier
   int4* qwg[3];               // union frontier, workgroup-chunk records
+  uint32_t* fbm[2];           // union frontier as a bitmap [step % 2] (for pull steps)
   uint32_t cap_v, cap_wg;
   TileCtl* ctl;
+  TGraph T;                   // reverse graph, or hdr == nullptr
+  long long pull_min;         // pull steps when the frontier has >= this many out-edges; < 0: never
 };
 
 }  // namespace dawn

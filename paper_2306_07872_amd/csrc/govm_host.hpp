@@ -28,6 +28,7 @@ struct Tuning {
   int32_t small_m = 131072;
   int32_t step_min_m = 1 << 25;
   int32_t tile_sparse = 8;
+  int32_t tile_pull = 400;
 };
 
 Tuning& tuning();
@@ -74,7 +75,7 @@ dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, 
 
 // ----- distance tile ---------------------------------------------------------
 struct TileLayout {
-  size_t ctl, info, D, mk[3], qgrp[3], qwave[3], qwg[3], total;
+  size_t ctl, info, D, mk[3], qgrp[3], qwave[3], qwg[3], fbm[2], total;
   uint32_t cap_v, cap_wg;
   int32_t K, nseg;
 };
@@ -109,6 +110,13 @@ void tile_persistent_occupancy(int threads, int* per_cu, int* grid);
 // Bracket a main launch with events when the kernel timer is on.
 void* ktimer_begin(hipStream_t stream);
 void ktimer_end(void* token, hipStream_t stream, int32_t launches);
+
+// ----- reverse graph for pull steps ------------------------------------------
+size_t tgraph_bytes(int64_t n, int64_t m);
+size_t tgraph_build_bytes(int64_t n, int64_t m);
+dawn_status tgraph_build(const int32_t* rowptr, const int32_t* colidx, const void* w, int64_t n,
+                         int64_t m, void* buf, void* scratch, hipStream_t stream);
+TGraph tgraph_view(const void* buf, int64_t n, int64_t m);
 
 // ----- host polling -----------------------------------------------------------
 // A pinned host word for reading a device flag after a stream synchronisation.

@@ -109,6 +109,7 @@ __device__ __forceinline__ void tile_prologue(TileCtl* C, uint32_t step, int K) 
   // zero the counters of the next step and count this step for active columns
   const int rz = (step + 1) % kRot, rc = step % kRot;
   if (threadIdx.x < 4) st_agent(&C->cnt[rz][threadIdx.x], 0u);
+  if (threadIdx.x == 4) st_agent64(&C->fedges[rz], 0ull);
   if (threadIdx.x < kSegMax) st_agent64(&C->colact[rz][threadIdx.x], 0ull);
   for (int j = threadIdx.x; j < K; j += blockDim.x)
     if ((ld_agent64(&C->colact[rc][j >> 6]) >> (j & 63)) & 1ull)
@@ -192,6 +193,20 @@ __device__ __forceinline__ void tile_compact(const TileArgs& A, uint32_t step, u
       deg = A.rowptr[v + 1] - start;
       if (deg == 0)  // nothing to expand: the row never enters a queue
         for (int s = 0; s < nseg; s++) mp[s] = 0ull;
+      else {
+        acc.fe += 1;        // frontier rows
+        acc.sa += pairs;    // frontier (row, source) pairs
+        acc.es += (unsigned long long)deg;  // out-edges of the frontier (direction choice)
+      }
+    }
+    {
+      // frontier bitmap of the step: each wavefront owns 64 consecutive
+      // vertices (ranges start at multiples of the workgroup size), so it
+      // writes its two words whole and nothing needs clearing
+      const unsigned long long fb = __ballot(any && deg > 0);
+      const int64_t wbase = (v0 + (threadIdx.x & ~(kWave - 1))) >> 5;
+      if (lane_id() == 0 && (wbase << 5) < n) A.fbm[step & 1][wbase] = (uint32_t)fb;
+      if (lane_id() == 1 && ((wbase + 1) << 5) < n) A.fbm[step & 1][wbase + 1] = (uint32_t)(fb >> 32);
     }
     compact_push(any && deg > 0 && deg <= A.t_group, (int32_t)v, 0, sh);
     compact_push(any && deg > A.t_group && deg <= A.t_wave, (int32_t)v, 1, sh);
@@ -458,28 +473,18 @@ __device__ __forceinline__ void tile_row_setup(const TileArgs& A, const int32_t*
   }
   nsrc = (uint32_t)ns;
   if (act) {
-    acc.fe += 1;
     acc.es += (unsigned long long)deg;
-    acc.sa += ns;
     acc.se += (unsigned long long)deg * ns;
   }
 }
 
-template <bool F32>
-__device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
-                           unsigned long long* sh_colact) {
-  const int q = step % 3, qn = (step + 1) % 3, qp = (step + 2) % 3;
-  const int rc = step % kRot, rn = (step + 1) % kRot, rp = (step + 3) % kRot;
+// Clear the mask words of the previous step's frontier rows (slot read one
+// step ago; it is written again from the next step on).
+__device__ __forceinline__ void tile_clear_prev(const TileArgs& A, uint32_t step, uint32_t gb,
+                                                uint32_t nb) {
   TileCtl* C = A.ctl;
-  const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
-  const int j16 = lane & 15, gbase = lane & 48;
-  const uint32_t gw = gb * W + wave, nwv = nb * W;
+  const int qp = (step + 2) % 3, rp = (step + 3) % kRot;
   const int nseg = A.nseg;
-  unsigned long long* mkn = A.mk[qn];
-  if (threadIdx.x < kSegMax) sh_colact[threadIdx.x] = 0ull;
-  __syncthreads();
-
-  // (a) clear the masks of the previous step's frontier (read one step ago)
   {
     const uint32_t pg = min(ld_agent(&C->cnt[rp][0]), A.cap_v);
     const uint32_t pw = min(ld_agent(&C->cnt[rp][1]), A.cap_v);
@@ -504,6 +509,24 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
     }
   }
 
+}
+
+template <bool F32>
+__device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
+                           unsigned long long* sh_colact) {
+  const int q = step % 3, qn = (step + 1) % 3, qp = (step + 2) % 3;
+  const int rc = step % kRot, rn = (step + 1) % kRot, rp = (step + 3) % kRot;
+  TileCtl* C = A.ctl;
+  const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  const int j16 = lane & 15, gbase = lane & 48;
+  const uint32_t gw = gb * W + wave, nwv = nb * W;
+  const int nseg = A.nseg;
+  unsigned long long* mkn = A.mk[qn];
+  if (threadIdx.x < kSegMax) sh_colact[threadIdx.x] = 0ull;
+  __syncthreads();
+
+  tile_clear_prev(A, step, gb, nb);
+
   // (b) workgroup tier: the 16-lane groups of the workgroup share a chunk
   const uint32_t nc = min(ld_agent(&C->cnt[rc][2]), A.cap_wg);
   for (uint32_t i = gb; i < nc; i += nb) {
@@ -517,10 +540,6 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
     if (threadIdx.x == 0) {
       acc.es += (unsigned long long)r.z;
       acc.se += (unsigned long long)r.z * (unsigned long long)ns;
-      if (r.w) {
-        acc.fe += 1;
-        acc.sa += (unsigned long long)ns;
-      }
     }
     // The path must be the same for every wavefront of the workgroup (each
     // covers only its share of the chunk), so it is chosen from this step's
@@ -623,7 +642,7 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   __shared__ CompactShared csh;
   TileCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
-  Acc acc;
+  Acc acc, cacc;  // relaxation / compaction counters
   uint32_t epoch = 0;
   const uint32_t bar_base = ld_agent(&C->bar_base);
   uint32_t step = ld_agent(&C->step);
@@ -632,7 +651,7 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   bool finished = false;
   for (;;) {
     if (blockIdx.x == 0) tile_prologue(C, step, A.K);
-    tile_compact(A, step, blockIdx.x, gridDim.x, acc, csh);
+    tile_compact(A, step, blockIdx.x, gridDim.x, cacc, csh);
     if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       finished = true;
@@ -651,6 +670,7 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
     if (step == stop) break;
   }
   flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
+  flush_acc(cacc, &C->fe, &C->fedges[0], &C->im, &C->sa, nullptr);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st_agent(&C->step, step);
     st_agent(&C->bar_base, bar_base + epoch * gridDim.x);
@@ -671,18 +691,21 @@ __global__ void __launch_bounds__(1024) tile_compact_kernel(TileArgs A) {
   if (blockIdx.x == 0) tile_prologue(C, step, A.K);
   Acc acc;
   tile_compact(A, step, blockIdx.x, gridDim.x, acc, csh);
-  flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
+  // frontier rows and pairs, improvements, and the frontier's out-edges
+  flush_acc(acc, &C->fe, &C->fedges[step % kRot], &C->im, &C->sa, nullptr);
 }
 
-template <bool F32>
-__global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap_n) {
-  __shared__ unsigned long long sh_colact[kSegMax];
+// A step is a pull step when the reverse graph is there and the frontier has
+// at least pull_min out-edges (counted by the compaction before both relaxation
+// kernels of the step run, so both take the same decision).
+__device__ __forceinline__ bool tile_is_pull_step(const TileArgs& A, uint32_t step) {
+  return A.T.hdr != nullptr && A.pull_min >= 0 &&
+         ld_agent64(&A.ctl->fedges[step % kRot]) >= (unsigned long long)A.pull_min;
+}
+
+// End of a step launch: the last workgroup advances the step and detects the end.
+__device__ __forceinline__ void tile_end_step(const TileArgs& A, uint32_t step, int32_t cap_n) {
   TileCtl* C = A.ctl;
-  if (ld_agent(&C->done)) return;
-  const uint32_t step = ld_agent(&C->step);
-  Acc acc;
-  tile_relax<F32>(A, step, blockIdx.x, gridDim.x, acc, sh_colact);
-  flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
   if (last_block_done(&C->blocks_done)) {
     st_agent(&C->blocks_done, 0u);
     const bool act = any_active(C, (step + 1) % kRot, A.nseg);
@@ -696,6 +719,171 @@ __global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap
       st_agent(&C->done, 1u);
     }
   }
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap_n) {
+  __shared__ unsigned long long sh_colact[kSegMax];
+  TileCtl* C = A.ctl;
+  if (ld_agent(&C->done)) return;
+  const uint32_t step = ld_agent(&C->step);
+  if (tile_is_pull_step(A, step)) return;  // the pull kernel runs this step
+  Acc acc;
+  tile_relax<F32>(A, step, blockIdx.x, gridDim.x, acc, sh_colact);
+  flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
+  tile_end_step(A, step, cap_n);
+}
+
+// ---------------------------------------------------------------------------
+// pull steps
+//
+// When the frontier's rows carry a large share of the edges, the step walks
+// the in-edges of every target instead (the reverse graph): a wavefront takes
+// one in-edge chunk of a target v and a quad of 64-source segments (lane =
+// 4 sources of one segment), keeps the best candidate of each of its sources
+// in registers over all in-edges (u, v) whose u is active for that source,
+// and finally writes the improved distances of v and v's next-step mask word
+// with plain stores: no other lane writes them in this step.  Only targets
+// whose in-edges span several chunks combine their chunks with atomics.  The
+// (edge, source) pairs relaxed are exactly those a push step relaxes.
+// ---------------------------------------------------------------------------
+constexpr int kPullThreads = 256;
+constexpr int kPullU = 4;  // in-edges gathered at a time per wavefront
+
+template <bool F32>
+__device__ __forceinline__ void tile_pull_chunk(const TileArgs& A, const int4 ch, int p, int q,
+                                                int qn, const uint32_t* fbm,
+                                                unsigned long long (*lm)[kSegMax],
+                                                unsigned long long* sh_colact, Acc& acc) {
+  const int lane = lane_id(), j16 = lane & 15;
+  const int32_t v = ch.x, start = ch.y, len = ch.z;
+  const bool split = ch.w != 0;
+  const int nseg = A.nseg, K = A.K;
+  const int s = 4 * p + (lane >> 4);
+  const bool sok = s < nseg;
+  const int col = s * 64 + 4 * j16;
+  const uint32_t inf = inf_bits<F32>();
+  uint32_t best[4] = {inf, inf, inf, inf};
+  for (int32_t b = 0; b < len; b += kWave) {
+    const int cnt = min(kWave, len - b);
+    // lane l: in-edge b + l -- its source, weight and the source's mask words
+    int32_t ul = 0;
+    uint32_t wl = 0u, actq = 0u;
+    bool anyl = false;
+    uint32_t pc = 0u;
+    if (lane < cnt) {
+      ul = A.T.colidx[start + b + lane];
+      wl = A.T.w[start + b + lane];
+    }
+    const bool fr = lane < cnt && ((fbm[ul >> 5] >> (ul & 31)) & 1u);
+    if (fr) {
+      for (int s2 = 0; s2 < nseg; s2++) {
+        const unsigned long long x = A.mk[q][(size_t)ul * nseg + s2];
+        lm[lane][s2] = x;
+        if (x) {
+          anyl = true;
+          pc += (uint32_t)__popcll(x);
+          if ((s2 >> 2) == p) actq |= 1u << (s2 & 3);
+        }
+      }
+    }
+    const unsigned long long anyb = __ballot(anyl);
+    if (p == 0) {  // count each in-edge once, in the first segment quad
+      acc.se += pc;
+      if (lane == 0) acc.es += (unsigned long long)__popcll(anyb);
+    }
+    wave_lds_sync();
+    // in-edges with an active source in this quad, kPullU at a time
+    unsigned long long todo = __ballot(actq != 0u);
+    while (todo) {
+      int32_t ui[kPullU];
+      uint32_t wi[kPullU], bits[kPullU];
+      uint4 du[kPullU];
+#pragma unroll
+      for (int k = 0; k < kPullU; k++) {
+        bits[k] = 0u;
+        ui[k] = 0;
+        wi[k] = 0u;
+        du[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (todo) {
+          const int i = __ffsll((long long)todo) - 1;
+          todo &= todo - 1ull;
+          ui[k] = __builtin_amdgcn_readlane(ul, i);
+          wi[k] = (uint32_t)__builtin_amdgcn_readlane((int)wl, i);
+          const unsigned long long x = sok ? lm[i][s] : 0ull;
+          bits[k] = (uint32_t)(x >> (4 * j16)) & 0xFu;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kPullU; k++)
+        if (bits[k]) du[k] = *reinterpret_cast<const uint4*>(A.D + (size_t)ui[k] * K + col);
+#pragma unroll
+      for (int k = 0; k < kPullU; k++) {
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+          if ((bits[k] >> t) & 1u) best[t] = min(best[t], relax_add<F32>(elem4(du[k], t), wi[k]));
+      }
+    }
+    wave_lds_sync();
+  }
+  // write back the improved distances of v (this lane's 4 sources)
+  uint32_t imp = 0u;
+  if (sok && (best[0] != inf || best[1] != inf || best[2] != inf || best[3] != inf)) {
+    uint32_t* dp = A.D + (size_t)v * K + col;
+    const uint4 dv = *reinterpret_cast<const uint4*>(dp);
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+      if (best[t] < elem4(dv, t)) imp |= 1u << t;
+    if (imp) {
+      if (split) {
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+          if ((imp >> t) & 1u) atomicMin(dp + t, best[t]);
+      } else {
+        *reinterpret_cast<uint4*>(dp) = make_uint4(min(dv.x, best[0]), min(dv.y, best[1]),
+                                                   min(dv.z, best[2]), min(dv.w, best[3]));
+      }
+    }
+  }
+  const uint32_t lo = row16_or(j16 < 8 ? imp << (4 * j16) : 0u);
+  const uint32_t hi = row16_or(j16 >= 8 ? imp << (4 * (j16 - 8)) : 0u);
+  const unsigned long long x = ((unsigned long long)hi << 32) | lo;
+  if (j16 == 0 && sok && x != 0ull) {
+    unsigned long long* mp = A.mk[qn] + (size_t)v * nseg + s;
+    if (split) atomicOr(mp, x);
+    else *mp = x;
+    atomicOr(&sh_colact[s], x);
+  }
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(kPullThreads) tile_pull_kernel(TileArgs A, int32_t cap_n) {
+  __shared__ unsigned long long sh_colact[kSegMax];
+  __shared__ unsigned long long lmask[kPullThreads / kWave][kWave][kSegMax];
+  TileCtl* C = A.ctl;
+  if (ld_agent(&C->done)) return;
+  const uint32_t step = ld_agent(&C->step);
+  if (!tile_is_pull_step(A, step)) return;  // the push kernel runs this step
+  const int q = step % 3, qn = (step + 1) % 3, rn = (step + 1) % kRot;
+  tile_clear_prev(A, step, blockIdx.x, gridDim.x);
+  if (threadIdx.x < kSegMax) sh_colact[threadIdx.x] = 0ull;
+  __syncthreads();
+  Acc acc;
+  const int wave = threadIdx.x >> 6;
+  const uint32_t gw = blockIdx.x * (kPullThreads / kWave) + wave;
+  const uint32_t nwv = gridDim.x * (kPullThreads / kWave);
+  const uint32_t nq = (uint32_t)((A.nseg + 3) / 4);
+  const uint32_t nch = (uint32_t)min((long long)A.T.hdr->nchunks, (long long)A.T.cap_chunks);
+  for (uint32_t task = gw; task < nch * nq; task += nwv) {
+    const uint32_t c = task / nq;
+    const int p = (int)(task - c * nq);
+    tile_pull_chunk<F32>(A, A.T.chunks[c], p, q, qn, A.fbm[step & 1], lmask[wave], sh_colact, acc);
+  }
+  flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
+  __syncthreads();
+  if ((int)threadIdx.x < A.nseg && sh_colact[threadIdx.x])
+    atomicOr(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
+  tile_end_step(A, step, cap_n);
 }
 
 // ---------------------------------------------------------------------------
@@ -784,6 +972,7 @@ TileLayout tile_layout(int64_t n, int64_t m, int32_t k) {
   for (int i = 0; i < 3; i++) L.qgrp[i] = c.take((size_t)n * 4);
   for (int i = 0; i < 3; i++) L.qwave[i] = c.take((size_t)n * 4);
   for (int i = 0; i < 3; i++) L.qwg[i] = c.take((size_t)L.cap_wg * 16);
+  for (int i = 0; i < 2; i++) L.fbm[i] = c.take((size_t)((n + 63) / 64) * 8);
   L.total = c.off;
   return L;
 }
@@ -806,12 +995,15 @@ TileArgs tile_args(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.t_group = T.tile_t_group;
   A.skip = T.tile_skip;
   A.sparse = T.tile_sparse;
+  A.T = TGraph{};
+  A.pull_min = -1;
   for (int i = 0; i < 3; i++) {
     A.mk[i] = reinterpret_cast<unsigned long long*>(base + L.mk[i]);
     A.qgrp[i] = reinterpret_cast<int32_t*>(base + L.qgrp[i]);
     A.qwave[i] = reinterpret_cast<int32_t*>(base + L.qwave[i]);
     A.qwg[i] = reinterpret_cast<int4*>(base + L.qwg[i]);
   }
+  for (int i = 0; i < 2; i++) A.fbm[i] = reinterpret_cast<uint32_t*>(base + L.fbm[i]);
   A.cap_v = L.cap_v;
   A.cap_wg = L.cap_wg;
   A.ctl = reinterpret_cast<TileCtl*>(base + L.ctl);
@@ -891,6 +1083,7 @@ static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_
     int grid = persistent_grid_t(tile_persistent_kernel<F32>, threads, nullptr, 0);
     if (T.grid > 0 && T.grid < grid) grid = T.grid;
     TileArgs aa = a;
+    aa.pull_min = -1;  // pull steps need the step-launch path
     int32_t ms = max_steps, cn = cap_n;
     void* args[] = {&aa, &ms, &cn};
     hipError_t e;
@@ -913,10 +1106,14 @@ static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_
                               : (int)std::max<int64_t>(cus, std::min<int64_t>(16 * cus, ((int64_t)a.n + 63) / 64));
   // compaction: one 1024-thread workgroup per CU (fewer for small graphs)
   const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, ((int64_t)a.n + 1023) / 1024));
+  const bool pull = a.T.hdr != nullptr && a.pull_min >= 0;
+  const int pgrid = 16 * cus;
   for (int s = 0; s < max_steps; s++) {
     hipLaunchKernelGGL(tile_compact_kernel, dim3(cgrid), dim3(1024), 0, stream, a);
     void* tk = ktimer_begin(stream);
     hipLaunchKernelGGL(tile_step_kernel<F32>, dim3(grid), dim3(threads), 0, stream, a, 0);
+    if (pull)
+      hipLaunchKernelGGL(tile_pull_kernel<F32>, dim3(pgrid), dim3(kPullThreads), 0, stream, a, 0);
     ktimer_end(tk, stream, 1);
   }
   return hip_check(hipGetLastError(), "tile step launches");

@@ -276,3 +276,78 @@ def test_full_size_tile_rmat20_sampled(dawn):
     for j in (17, 128):
         rc, v = oracle.check(g, int(srcs[j]), to_np(D[j]))
         assert rc == 0, f"col {j}: invariant V{rc} at {v}"
+
+
+# ---------------------------------------------------------------------------
+# pull steps (reverse graph): same relaxations, so results are identical
+# ---------------------------------------------------------------------------
+PULL_TUNINGS = [
+    dict(tile_pull=0),                      # every step a pull step
+    dict(tile_pull=1001),                   # never
+    dict(),                                 # by frontier density
+    dict(tile_pull=0, tile_k=512),          # two 4-segment quads per target
+    dict(tile_pull=50, tile_t_wave=32, tile_t_chunk=64, tile_sparse=0, tile_t_group=0),
+]
+
+
+def _msssp_tg(dawn, csr, sources, tg, **tune):
+    import torch
+    prev = dawn.set_tuning(**tune) if tune else None
+    try:
+        info = dawn.info_tensor()
+        out = dawn.msssp(csr, sources, info=info, tgraph=tg)
+        torch.cuda.synchronize()
+        return to_np(out), dawn.read_info(info)
+    finally:
+        if prev is not None:
+            dawn.set_tuning(**prev)
+
+
+@pytest.mark.parametrize("ti", range(len(PULL_TUNINGS)))
+@pytest.mark.parametrize("wk", ["u32", "f32lognormal"])
+def test_msssp_pull_steps_match_push_and_oracle(dawn, wk, ti):
+    g = graphgen.rmat(13, 16, 21, weights=wk)   # hubs: targets with several in-edge chunks
+    csr = dawn.Csr.from_graph(g)
+    tg = dawn.tgraph(csr)
+    srcs = graphgen.pick_sources(g, 150, 4 + ti)
+    srcs = np.concatenate([srcs, srcs[:2]])      # duplicate sources
+    announce("msssp pull", wk, PULL_TUNINGS[ti])
+    D, info = _msssp_tg(dawn, csr, srcs, tg, **PULL_TUNINGS[ti])
+    P, pinfo = _msssp(dawn, g, srcs)             # push steps only
+    assert np.array_equal(D.view(np.uint32), P.view(np.uint32))
+    for j in (0, 75, 149, 151):
+        assert_sssp_matches(g, int(srcs[j]), D[j], tag=f"pull col {j}")
+    assert info["converged"] == 1
+    # both directions relax the same (edge, source) pairs; only the order of
+    # updates within a step (and so the step count) may differ
+    assert info["union_edges"] > 0 and info["edges_scanned"] > 0
+
+
+def test_msssp_pull_hub_target_with_many_chunks(dawn):
+    """A star whose centre has 100000 in-edges (about a hundred in-edge chunks,
+    combined with atomics) and out-edges to every leaf."""
+    n = 100001
+    leaves = np.arange(1, n)
+    src = np.concatenate([leaves, np.zeros(n - 1, np.int64), leaves[:-1]])
+    dst = np.concatenate([np.zeros(n - 1, np.int64), leaves, leaves[1:]])
+    rng = np.random.default_rng(11)
+    w = rng.integers(1, 1000, size=src.size).astype(np.uint32)
+    g = graphgen.from_edges(n, src, dst, w, "u32")
+    csr = dawn.Csr.from_graph(g)
+    tg = dawn.tgraph(csr)
+    srcs = np.array([0, 5, 77777, 100000, 3], dtype=np.int32)
+    announce("msssp pull star")
+    D, info = _msssp_tg(dawn, csr, srcs, tg, tile_pull=0)
+    for j, s in enumerate(srcs):
+        assert_sssp_matches(g, int(s), D[j], tag=f"star pull source {s}")
+
+
+def test_msssp_pull_grid_f32_many_steps(dawn):
+    g = graphgen.grid(64, 48, 0.01, 3, weights="f32unit")
+    csr = dawn.Csr.from_graph(g)
+    tg = dawn.tgraph(csr)
+    srcs = graphgen.pick_sources(g, 70, 1)
+    announce("msssp pull grid f32")
+    D, info = _msssp_tg(dawn, csr, srcs, tg, tile_pull=0)
+    for j in (0, 33, 69):
+        assert_sssp_matches(g, int(srcs[j]), D[j], tag=f"pull grid col {j}")
