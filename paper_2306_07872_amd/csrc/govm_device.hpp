@@ -40,6 +40,16 @@ struct alignas(256) SsCtl {
   unsigned long long fe, es, im;  // frontier rows, edges scanned, improvements
 };
 
+// Counters of a tile run, striped: workgroup b adds to stripe b % kCtrStripes,
+// each on its own 256-byte line, so that the adds of many workgroups do not
+// queue on one address; a reader sums the stripes.
+constexpr int kCtrStripes = 32;
+struct alignas(256) CtrStripe {
+  unsigned long long fe, es, im, sa, se;  // union rows, union edges, improvements,
+                                          // per-source rows, per-source edges
+  unsigned long long fedges[kRot];        // [step % 4]: out-edges of the step's frontier rows
+};
+
 struct alignas(256) TileCtl {
   uint32_t cnt[kRot][4];               // [step % 4][tier]: group, wave, workgroup-chunk
   unsigned long long colact[kRot][kSegMax];  // [step % 4]: columns improved in step-1
@@ -47,9 +57,7 @@ struct alignas(256) TileCtl {
   uint32_t step, done;
   int32_t converged;
   uint32_t bar, abort, blocks_done, overflow, bar_base;
-  unsigned long long fe, es, im, sa, se;  // union rows, union edges, improvements,
-                                          // per-source rows, per-source edges
-  unsigned long long fedges[kRot];      // [step % 4]: out-edges of the step's frontier rows
+  CtrStripe ctr[kCtrStripes];           // statistics, summed over the stripes
   int32_t colsteps[kSegMax * 64];
 };
 
@@ -222,19 +230,46 @@ __device__ __forceinline__ bool last_block_done(uint32_t* blocks_done) {
   return s_last != 0 && threadIdx.x == 0;
 }
 
-// Sum per-thread counters over the block and add them to the control block.
+// Sum per-thread counters over the workgroup (wavefront sums, then LDS) and
+// add each total to its counter with one atomic (null pointer: not counted).
+// One add per workgroup rather than per wavefront: device-scope atomics on one
+// address are serialised where they execute.  Every thread must call it.
 __device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* fe,
                                           unsigned long long* es, unsigned long long* im,
                                           unsigned long long* sa, unsigned long long* se) {
+  __shared__ unsigned long long part[1024 / kWave][5];
   const unsigned long long v0 = wave_sum64(a.fe), v1 = wave_sum64(a.es), v2 = wave_sum64(a.im);
-  const unsigned long long v3 = sa ? wave_sum64(a.sa) : 0ull, v4 = se ? wave_sum64(a.se) : 0ull;
+  const unsigned long long v3 = wave_sum64(a.sa), v4 = wave_sum64(a.se);
+  const int w = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+  __syncthreads();  // an earlier call's readers of `part` are done
   if (lane_id() == 0) {
-    if (v0) atomicAdd(fe, v0);
-    if (v1) atomicAdd(es, v1);
-    if (v2) atomicAdd(im, v2);
-    if (sa && v3) atomicAdd(sa, v3);
-    if (se && v4) atomicAdd(se, v4);
+    part[w][0] = v0;
+    part[w][1] = v1;
+    part[w][2] = v2;
+    part[w][3] = v3;
+    part[w][4] = v4;
   }
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    unsigned long long s = 0;
+    for (int i = 0; i < nw; ++i) s += part[i][threadIdx.x];
+    unsigned long long* dst = threadIdx.x == 0 ? fe
+                              : threadIdx.x == 1 ? es
+                              : threadIdx.x == 2 ? im
+                              : threadIdx.x == 3 ? sa
+                                                 : se;
+    if (dst && s) atomicAdd(dst, s);
+  }
+}
+
+// Sum of one counter over the stripes, in every lane (all lanes must be active).
+__device__ __forceinline__ unsigned long long ctr_sum(const CtrStripe* ctr, size_t offset) {
+  const int lane = lane_id();
+  unsigned long long x = 0;
+  if (lane < kCtrStripes)
+    x = ld_agent64(reinterpret_cast<const unsigned long long*>(
+        reinterpret_cast<const char*>(ctr + lane) + offset));
+  return wave_sum64(x);
 }
 
 }  // namespace dawn

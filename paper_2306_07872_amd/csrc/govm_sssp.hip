@@ -579,12 +579,10 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
     }
   }
   // counters, state and run info
-  if (threadIdx.x == 0) {
-    st_agent64(&C->fe, 0ull);
-    st_agent64(&C->es, 0ull);
-    st_agent64(&C->im, 0ull);
-  }
-  __syncthreads();
+  // thread i zeroes the counter that it then adds to (flush_acc: fe, es, im)
+  if (threadIdx.x == 0) st_agent64(&C->fe, 0ull);
+  if (threadIdx.x == 1) st_agent64(&C->es, 0ull);
+  if (threadIdx.x == 2) st_agent64(&C->im, 0ull);
   flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
@@ -746,12 +744,10 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) A.dist[i] = sh.dist[i];
   }
-  if (threadIdx.x == 0) {
-    st_agent64(&C->fe, 0ull);
-    st_agent64(&C->es, 0ull);
-    st_agent64(&C->im, 0ull);
-  }
-  __syncthreads();
+  // thread i zeroes the counter that it then adds to (flush_acc: fe, es, im)
+  if (threadIdx.x == 0) st_agent64(&C->fe, 0ull);
+  if (threadIdx.x == 1) st_agent64(&C->es, 0ull);
+  if (threadIdx.x == 2) st_agent64(&C->im, 0ull);
   flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();

@@ -109,7 +109,7 @@ __device__ __forceinline__ void tile_prologue(TileCtl* C, uint32_t step, int K) 
   // zero the counters of the next step and count this step for active columns
   const int rz = (step + 1) % kRot, rc = step % kRot;
   if (threadIdx.x < 4) st_agent(&C->cnt[rz][threadIdx.x], 0u);
-  if (threadIdx.x == 4) st_agent64(&C->fedges[rz], 0ull);
+  if (threadIdx.x < kCtrStripes) st_agent64(&C->ctr[threadIdx.x].fedges[rz], 0ull);
   if (threadIdx.x < kSegMax) st_agent64(&C->colact[rz][threadIdx.x], 0ull);
   for (int j = threadIdx.x; j < K; j += blockDim.x)
     if ((ld_agent64(&C->colact[rc][j >> 6]) >> (j & 63)) & 1ull)
@@ -669,8 +669,10 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
     if (cap_n && step >= (uint32_t)A.n) { status = 0; finished = true; break; }
     if (step == stop) break;
   }
-  flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
-  flush_acc(cacc, &C->fe, &C->fedges[0], &C->im, &C->sa, nullptr);
+  // the frontier's out-edges decide pull steps of step launches only: not counted here
+  CtrStripe& S = C->ctr[blockIdx.x % kCtrStripes];
+  flush_acc(acc, &S.fe, &S.es, &S.im, &S.sa, &S.se);
+  flush_acc(cacc, &S.fe, nullptr, &S.im, &S.sa, nullptr);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st_agent(&C->step, step);
     st_agent(&C->bar_base, bar_base + epoch * gridDim.x);
@@ -692,15 +694,17 @@ __global__ void __launch_bounds__(1024) tile_compact_kernel(TileArgs A) {
   Acc acc;
   tile_compact(A, step, blockIdx.x, gridDim.x, acc, csh);
   // frontier rows and pairs, improvements, and the frontier's out-edges
-  flush_acc(acc, &C->fe, &C->fedges[step % kRot], &C->im, &C->sa, nullptr);
+  CtrStripe& S = C->ctr[blockIdx.x % kCtrStripes];
+  flush_acc(acc, &S.fe, &S.fedges[step % kRot], &S.im, &S.sa, nullptr);
 }
 
 // A step is a pull step when the reverse graph is there and the frontier has
 // at least pull_min out-edges (counted by the compaction before both relaxation
 // kernels of the step run, so both take the same decision).
 __device__ __forceinline__ bool tile_is_pull_step(const TileArgs& A, uint32_t step) {
-  return A.T.hdr != nullptr && A.pull_min >= 0 &&
-         ld_agent64(&A.ctl->fedges[step % kRot]) >= (unsigned long long)A.pull_min;
+  if (A.T.hdr == nullptr || A.pull_min < 0) return false;
+  const size_t off = offsetof(CtrStripe, fedges) + (step % kRot) * sizeof(unsigned long long);
+  return ctr_sum(A.ctl->ctr, off) >= (unsigned long long)A.pull_min;
 }
 
 // End of a step launch: the last workgroup advances the step and detects the end.
@@ -730,7 +734,8 @@ __global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap
   if (tile_is_pull_step(A, step)) return;  // the pull kernel runs this step
   Acc acc;
   tile_relax<F32>(A, step, blockIdx.x, gridDim.x, acc, sh_colact);
-  flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
+  CtrStripe& S = C->ctr[blockIdx.x % kCtrStripes];
+  flush_acc(acc, &S.fe, &S.es, &S.im, &S.sa, &S.se);
   tile_end_step(A, step, cap_n);
 }
 
@@ -879,7 +884,8 @@ __global__ void __launch_bounds__(kPullThreads) tile_pull_kernel(TileArgs A, int
     const int p = (int)(task - c * nq);
     tile_pull_chunk<F32>(A, A.T.chunks[c], p, q, qn, A.fbm[step & 1], lmask[wave], sh_colact, acc);
   }
-  flush_acc(acc, &C->fe, &C->es, &C->im, &C->sa, &C->se);
+  CtrStripe& S = C->ctr[blockIdx.x % kCtrStripes];
+  flush_acc(acc, &S.fe, &S.es, &S.im, &S.sa, &S.se);
   __syncthreads();
   if ((int)threadIdx.x < A.nseg && sh_colact[threadIdx.x])
     atomicOr(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
@@ -942,11 +948,19 @@ __global__ void tile_info_kernel(const TileCtl* C, int32_t K, dawn_run_info* inf
   if (ld_agent(&C->abort)) conv = -2;
   info->steps = s_max;
   info->converged = conv;
-  info->frontier_entries = (int64_t)ld_agent64(&C->sa);
-  info->edges_scanned = (int64_t)ld_agent64(&C->se);
-  info->improvements = (int64_t)ld_agent64(&C->im);
-  info->union_rows = (int64_t)ld_agent64(&C->fe);
-  info->union_edges = (int64_t)ld_agent64(&C->es);
+  unsigned long long fe = 0, es = 0, im = 0, sa = 0, se = 0;
+  for (int i = 0; i < kCtrStripes; ++i) {
+    fe += ld_agent64(&C->ctr[i].fe);
+    es += ld_agent64(&C->ctr[i].es);
+    im += ld_agent64(&C->ctr[i].im);
+    sa += ld_agent64(&C->ctr[i].sa);
+    se += ld_agent64(&C->ctr[i].se);
+  }
+  info->frontier_entries = (int64_t)sa;
+  info->edges_scanned = (int64_t)se;
+  info->improvements = (int64_t)im;
+  info->union_rows = (int64_t)fe;
+  info->union_edges = (int64_t)es;
 }
 
 __global__ void tile_col_steps_kernel(const TileCtl* C, int32_t k, int32_t* out) {
