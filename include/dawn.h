@@ -82,9 +82,11 @@ typedef enum { DAWN_W_U32 = 0, DAWN_W_F32 = 1 } dawn_wtype;
  * the largest per-source step count; union_rows / union_edges count the rows
  * and edges the tile actually read (each serving every source active there);
  * improvements counts, per step, the (vertex, source) pairs whose distance
- * the step lowered (two decreases of one pair in one step count once); with
- * tile_skip = 1 a (row, source) pair lowered again within the step it was to
- * be expanded in is expanded only in the next step, and is counted there.
+ * the step lowered (two decreases of one pair in one step count once).  The
+ * row and edge counters are taken from the frontier of each step (the same
+ * for push and pull steps); with tile_skip = 1 a (row, source) pair lowered
+ * again within the step it was to be expanded in is expanded only in the next
+ * step, but counted in both.
  * For single-source calls union_rows / union_edges equal frontier_entries /
  * edges_scanned. */
 typedef struct {

@@ -231,12 +231,14 @@ __device__ __forceinline__ bool last_block_done(uint32_t* blocks_done) {
 }
 
 // Sum per-thread counters over the workgroup (wavefront sums, then LDS) and
-// add each total to its counter with one atomic (null pointer: not counted).
+// add each total to its counter with one atomic (null pointer: not counted;
+// es2: a second counter that also takes the es total).
 // One add per workgroup rather than per wavefront: device-scope atomics on one
 // address are serialised where they execute.  Every thread must call it.
 __device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* fe,
                                           unsigned long long* es, unsigned long long* im,
-                                          unsigned long long* sa, unsigned long long* se) {
+                                          unsigned long long* sa, unsigned long long* se,
+                                          unsigned long long* es2 = nullptr) {
   __shared__ unsigned long long part[1024 / kWave][5];
   const unsigned long long v0 = wave_sum64(a.fe), v1 = wave_sum64(a.es), v2 = wave_sum64(a.im);
   const unsigned long long v3 = wave_sum64(a.sa), v4 = wave_sum64(a.se);
@@ -250,14 +252,16 @@ __device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* fe,
     part[w][4] = v4;
   }
   __syncthreads();
-  if (threadIdx.x < 5) {
+  if (threadIdx.x < 6) {
+    const int c = threadIdx.x == 5 ? 1 : threadIdx.x;
     unsigned long long s = 0;
-    for (int i = 0; i < nw; ++i) s += part[i][threadIdx.x];
+    for (int i = 0; i < nw; ++i) s += part[i][c];
     unsigned long long* dst = threadIdx.x == 0 ? fe
                               : threadIdx.x == 1 ? es
                               : threadIdx.x == 2 ? im
                               : threadIdx.x == 3 ? sa
-                                                 : se;
+                              : threadIdx.x == 4 ? se
+                                                 : es2;
     if (dst && s) atomicAdd(dst, s);
   }
 }

@@ -196,7 +196,8 @@ __device__ __forceinline__ void tile_compact(const TileArgs& A, uint32_t step, u
       else {
         acc.fe += 1;        // frontier rows
         acc.sa += pairs;    // frontier (row, source) pairs
-        acc.es += (unsigned long long)deg;  // out-edges of the frontier (direction choice)
+        acc.es += (unsigned long long)deg;  // out-edges of the frontier rows
+        acc.se += (unsigned long long)deg * pairs;  // out-edges of the (row, source) pairs
       }
     }
     {
@@ -305,7 +306,7 @@ template <bool F32>
 __device__ __forceinline__ void tile_seg_relax(const TileArgs& A, int32_t start, int32_t len,
                                                int sg, uint32_t bits, const uint4& du, int gidx,
                                                int ngroups, unsigned long long* mk_next,
-                                               unsigned long long* sh_colact, Acc& acc) {
+                                               unsigned long long* sh_colact) {
   constexpr int U = kTileU;
   const int j16 = threadIdx.x & 15;
   const int col = sg * 64 + 4 * j16;
@@ -452,7 +453,7 @@ __device__ __forceinline__ void tile_sparse_relax(const TileArgs& A, int32_t u, 
 __device__ __forceinline__ void tile_row_setup(const TileArgs& A, const int32_t* qq, uint32_t n,
                                                uint32_t b0, int q, int qn, int32_t& u,
                                                int32_t& start, int32_t& deg, uint32_t& act,
-                                               uint32_t& nsrc, Acc& acc) {
+                                               uint32_t& nsrc) {
   const uint32_t i = b0 + (uint32_t)lane_id();
   u = 0;
   start = 0;
@@ -472,10 +473,6 @@ __device__ __forceinline__ void tile_row_setup(const TileArgs& A, const int32_t*
     }
   }
   nsrc = (uint32_t)ns;
-  if (act) {
-    acc.es += (unsigned long long)deg;
-    acc.se += (unsigned long long)deg * ns;
-  }
 }
 
 // Clear the mask words of the previous step's frontier rows (slot read one
@@ -512,7 +509,7 @@ __device__ __forceinline__ void tile_clear_prev(const TileArgs& A, uint32_t step
 }
 
 template <bool F32>
-__device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
+__device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32_t nb,
                            unsigned long long* sh_colact) {
   const int q = step % 3, qn = (step + 1) % 3, qp = (step + 2) % 3;
   const int rc = step % kRot, rn = (step + 1) % kRot, rp = (step + 3) % kRot;
@@ -534,13 +531,6 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
     const unsigned long long x = lane < nseg ? tile_row_mask(A, q, qn, r.x, lane) : 0ull;
     const uint32_t act = (uint32_t)__ballot(x != 0ull);
     if (act == 0u) continue;
-    int ns = __popcll(x);
-#pragma unroll
-    for (int off = 4; off > 0; off >>= 1) ns += __shfl_xor(ns, off, kWave);
-    if (threadIdx.x == 0) {
-      acc.es += (unsigned long long)r.z;
-      acc.se += (unsigned long long)r.z * (unsigned long long)ns;
-    }
     // The path must be the same for every wavefront of the workgroup (each
     // covers only its share of the chunk), so it is chosen from this step's
     // mask, which no lane changes during the step.
@@ -559,7 +549,7 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
       uint4 du = make_uint4(0u, 0u, 0u, 0u);
       if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)r.x * A.K + sg * 64 + 4 * j16);
       tile_seg_relax<F32>(A, r.y, r.z, sg, bits, du, threadIdx.x >> 4, blockDim.x >> 4, mkn,
-                          sh_colact, acc);
+                          sh_colact);
     }
   }
 
@@ -574,7 +564,7 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
   for (uint32_t b0 = gw * pw; b0 < hw; b0 += kWave) {
     int32_t u, start, deg;
     uint32_t act, nsrc;
-    tile_row_setup(A, A.qwave[q], hw, b0, q, qn, u, start, deg, act, nsrc, acc);
+    tile_row_setup(A, A.qwave[q], hw, b0, q, qn, u, start, deg, act, nsrc);
     const int rows = (int)min((uint32_t)kWave, hw - b0);
     for (int r = 0; r < rows; r++) {
       const uint32_t ar = (uint32_t)__builtin_amdgcn_readlane((int)act, r);
@@ -591,7 +581,7 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
         const uint32_t bits = (uint32_t)(tile_row_mask(A, q, qn, ur, sg) >> (4 * j16)) & 0xFu;
         uint4 du = make_uint4(0u, 0u, 0u, 0u);
         if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)ur * A.K + sg * 64 + 4 * j16);
-        tile_seg_relax<F32>(A, sr, dr, sg, bits, du, lane >> 4, 4, mkn, sh_colact, acc);
+        tile_seg_relax<F32>(A, sr, dr, sg, bits, du, lane >> 4, 4, mkn, sh_colact);
       }
     }
   }
@@ -602,7 +592,7 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
   for (uint32_t b0 = gw * pg; b0 < hg; b0 += kWave) {
     int32_t u, start, deg;
     uint32_t act, nsrc;
-    tile_row_setup(A, A.qgrp[q], hg, b0, q, qn, u, start, deg, act, nsrc, acc);
+    tile_row_setup(A, A.qgrp[q], hg, b0, q, qn, u, start, deg, act, nsrc);
     const int rows = (int)min((uint32_t)kWave, hg - b0);
     // group g walks rows b0 + 4 r + g, held by lane 4 r + g
     for (int r = 0; 4 * r < rows; r++) {
@@ -616,7 +606,7 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
         const uint32_t bits = (uint32_t)(tile_row_mask(A, q, qn, ur, sg) >> (4 * j16)) & 0xFu;
         uint4 du = make_uint4(0u, 0u, 0u, 0u);
         if (bits) du = *reinterpret_cast<const uint4*>(A.D + (size_t)ur * A.K + sg * 64 + 4 * j16);
-        tile_seg_relax<F32>(A, sr, dr, sg, bits, du, 0, 1, mkn, sh_colact, acc);
+        tile_seg_relax<F32>(A, sr, dr, sg, bits, du, 0, 1, mkn, sh_colact);
       }
     }
   }
@@ -642,7 +632,7 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   __shared__ CompactShared csh;
   TileCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
-  Acc acc, cacc;  // relaxation / compaction counters
+  Acc acc;  // every counter is taken by the compaction
   uint32_t epoch = 0;
   const uint32_t bar_base = ld_agent(&C->bar_base);
   uint32_t step = ld_agent(&C->step);
@@ -651,13 +641,13 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   bool finished = false;
   for (;;) {
     if (blockIdx.x == 0) tile_prologue(C, step, A.K);
-    tile_compact(A, step, blockIdx.x, gridDim.x, cacc, csh);
+    tile_compact(A, step, blockIdx.x, gridDim.x, acc, csh);
     if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       finished = true;
       break;
     }
-    tile_relax<F32>(A, step, blockIdx.x, gridDim.x, acc, sh_colact);
+    tile_relax<F32>(A, step, blockIdx.x, gridDim.x, sh_colact);
     if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       finished = true;
@@ -669,10 +659,9 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
     if (cap_n && step >= (uint32_t)A.n) { status = 0; finished = true; break; }
     if (step == stop) break;
   }
-  // the frontier's out-edges decide pull steps of step launches only: not counted here
+  // (the frontier's out-edges per step decide pull steps of step launches only)
   CtrStripe& S = C->ctr[blockIdx.x % kCtrStripes];
   flush_acc(acc, &S.fe, &S.es, &S.im, &S.sa, &S.se);
-  flush_acc(cacc, &S.fe, nullptr, &S.im, &S.sa, nullptr);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st_agent(&C->step, step);
     st_agent(&C->bar_base, bar_base + epoch * gridDim.x);
@@ -695,7 +684,7 @@ __global__ void __launch_bounds__(1024) tile_compact_kernel(TileArgs A) {
   tile_compact(A, step, blockIdx.x, gridDim.x, acc, csh);
   // frontier rows and pairs, improvements, and the frontier's out-edges
   CtrStripe& S = C->ctr[blockIdx.x % kCtrStripes];
-  flush_acc(acc, &S.fe, &S.fedges[step % kRot], &S.im, &S.sa, nullptr);
+  flush_acc(acc, &S.fe, &S.es, &S.im, &S.sa, &S.se, &S.fedges[step % kRot]);
 }
 
 // A step is a pull step when the reverse graph is there and the frontier has
@@ -732,10 +721,7 @@ __global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap
   if (ld_agent(&C->done)) return;
   const uint32_t step = ld_agent(&C->step);
   if (tile_is_pull_step(A, step)) return;  // the pull kernel runs this step
-  Acc acc;
-  tile_relax<F32>(A, step, blockIdx.x, gridDim.x, acc, sh_colact);
-  CtrStripe& S = C->ctr[blockIdx.x % kCtrStripes];
-  flush_acc(acc, &S.fe, &S.es, &S.im, &S.sa, &S.se);
+  tile_relax<F32>(A, step, blockIdx.x, gridDim.x, sh_colact);
   tile_end_step(A, step, cap_n);
 }
 
@@ -743,99 +729,112 @@ __global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap
 // pull steps
 //
 // When the frontier's rows carry a large share of the edges, the step walks
-// the in-edges of every target instead (the reverse graph): a wavefront takes
-// one in-edge chunk of a target v and a quad of 64-source segments (lane =
-// 4 sources of one segment), keeps the best candidate of each of its sources
-// in registers over all in-edges (u, v) whose u is active for that source,
-// and finally writes the improved distances of v and v's next-step mask word
-// with plain stores: no other lane writes them in this step.  Only targets
-// whose in-edges span several chunks combine their chunks with atomics.  The
-// (edge, source) pairs relaxed are exactly those a push step relaxes.
+// the in-edges of every target instead (the reverse graph).  A wavefront takes
+// one in-edge chunk of a target v and a quad of 64-source segments; each
+// 16-lane group covers one segment (lane = 4 sources) and, when the quad has
+// fewer than four segments, the groups that cover the same segment take
+// different in-edges and combine at the end.  The best candidate of each
+// source is kept in registers over all in-edges (u, v) whose u is in the
+// step's frontier; v's improved distances and next-step mask word are then
+// written with plain stores: no other lane writes them in this step.  Only
+// targets whose in-edges span several chunks combine their chunks with atomics.
+//
+// Every source of a frontier row u is relaxed, not only those active at u:
+// for a source c not active at u, u's distance for c has not changed since the
+// step that last relaxed (u, v) for c (or is still INF), so that step left
+// D[v][c] <= D[u][c] (+) w and the candidate cannot improve v.  The improved
+// pairs -- hence the next frontier and the distances -- are exactly those of
+// the push step.  Reading u's whole row costs no more memory traffic than
+// reading its active sources (at 16 sources per 64-byte sector, a sector with
+// no active source is rare in the steps dense enough to pull) and saves the
+// gather of u's mask words.
 // ---------------------------------------------------------------------------
 constexpr int kPullThreads = 256;
-constexpr int kPullU = 4;  // in-edges gathered at a time per wavefront
+constexpr int kPullU = 4;  // in-edges gathered at a time per 16-lane group
 
-template <bool F32>
-__device__ __forceinline__ void tile_pull_chunk(const TileArgs& A, const int4 ch, int p, int q,
-                                                int qn, const uint32_t* fbm,
-                                                unsigned long long (*lm)[kSegMax],
-                                                unsigned long long* sh_colact, Acc& acc) {
-  const int lane = lane_id(), j16 = lane & 15;
+// E: in-edges taken at a time by the groups of one segment (4 / segments in
+// the quad; 1 for quads of 3 or 4 segments)
+template <bool F32, int E>
+__device__ __forceinline__ void tile_pull_chunk(const TileArgs& A, const int4 ch, int p, int qn,
+                                                const uint32_t* fbm,
+                                                unsigned long long* sh_colact) {
+  const int lane = lane_id(), j16 = lane & 15, g = lane >> 4;
   const int32_t v = ch.x, start = ch.y, len = ch.z;
   const bool split = ch.w != 0;
   const int nseg = A.nseg, K = A.K;
-  const int s = 4 * p + (lane >> 4);
-  const bool sok = s < nseg;
+  const int nsq = min(4, nseg - 4 * p);  // segments in this quad
+  const int e = g / nsq;                 // in-edge slot of this group
+  const bool gok = e < E;                // false only for the idle group of a 3-segment quad
+  const bool own = gok && e == 0;        // the group that writes v's segment
+  const int s = 4 * p + g % nsq;
   const int col = s * 64 + 4 * j16;
   const uint32_t inf = inf_bits<F32>();
+  uint32_t* dp = A.D + (size_t)v * K + col;
+  // v's distances: read early when this chunk is v's only writer, else after
+  // the loop (other chunks of v may lower them meanwhile)
+  uint4 dv = make_uint4(0u, 0u, 0u, 0u);
+  if (own && !split) dv = *reinterpret_cast<const uint4*>(dp);
   uint32_t best[4] = {inf, inf, inf, inf};
   for (int32_t b = 0; b < len; b += kWave) {
     const int cnt = min(kWave, len - b);
-    // lane l: in-edge b + l -- its source, weight and the source's mask words
+    // lane l: in-edge b + l -- its source and weight, kept if the source is in the frontier
     int32_t ul = 0;
-    uint32_t wl = 0u, actq = 0u;
-    bool anyl = false;
-    uint32_t pc = 0u;
+    uint32_t wl = 0u;
     if (lane < cnt) {
       ul = A.T.colidx[start + b + lane];
       wl = A.T.w[start + b + lane];
     }
     const bool fr = lane < cnt && ((fbm[ul >> 5] >> (ul & 31)) & 1u);
-    if (fr) {
-      for (int s2 = 0; s2 < nseg; s2++) {
-        const unsigned long long x = A.mk[q][(size_t)ul * nseg + s2];
-        lm[lane][s2] = x;
-        if (x) {
-          anyl = true;
-          pc += (uint32_t)__popcll(x);
-          if ((s2 >> 2) == p) actq |= 1u << (s2 & 3);
-        }
-      }
-    }
-    const unsigned long long anyb = __ballot(anyl);
-    if (p == 0) {  // count each in-edge once, in the first segment quad
-      acc.se += pc;
-      if (lane == 0) acc.es += (unsigned long long)__popcll(anyb);
-    }
-    wave_lds_sync();
-    // in-edges with an active source in this quad, kPullU at a time
-    unsigned long long todo = __ballot(actq != 0u);
+    unsigned long long todo = __ballot(fr);
     while (todo) {
       int32_t ui[kPullU];
-      uint32_t wi[kPullU], bits[kPullU];
+      uint32_t wi[kPullU];
+      bool ok[kPullU];
       uint4 du[kPullU];
 #pragma unroll
       for (int k = 0; k < kPullU; k++) {
-        bits[k] = 0u;
+        // the next E in-edges of the list go to slots 0 .. E-1
         ui[k] = 0;
         wi[k] = 0u;
-        du[k] = make_uint4(0u, 0u, 0u, 0u);
-        if (todo) {
-          const int i = __ffsll((long long)todo) - 1;
-          todo &= todo - 1ull;
-          ui[k] = __builtin_amdgcn_readlane(ul, i);
-          wi[k] = (uint32_t)__builtin_amdgcn_readlane((int)wl, i);
-          const unsigned long long x = sok ? lm[i][s] : 0ull;
-          bits[k] = (uint32_t)(x >> (4 * j16)) & 0xFu;
+        ok[k] = false;
+#pragma unroll
+        for (int t = 0; t < E; t++) {
+          if (todo) {
+            const int i = __ffsll((long long)todo) - 1;
+            todo &= todo - 1ull;
+            const int32_t ut = __builtin_amdgcn_readlane(ul, i);
+            const uint32_t wt = (uint32_t)__builtin_amdgcn_readlane((int)wl, i);
+            if (t == e) {
+              ui[k] = ut;
+              wi[k] = wt;
+              ok[k] = gok;
+            }
+          }
         }
+        du[k] = make_uint4(0u, 0u, 0u, 0u);
       }
 #pragma unroll
       for (int k = 0; k < kPullU; k++)
-        if (bits[k]) du[k] = *reinterpret_cast<const uint4*>(A.D + (size_t)ui[k] * K + col);
+        if (ok[k]) du[k] = *reinterpret_cast<const uint4*>(A.D + (size_t)ui[k] * K + col);
 #pragma unroll
       for (int k = 0; k < kPullU; k++) {
+        if (ok[k]) {
 #pragma unroll
-        for (int t = 0; t < 4; t++)
-          if ((bits[k] >> t) & 1u) best[t] = min(best[t], relax_add<F32>(elem4(du[k], t), wi[k]));
+          for (int t = 0; t < 4; t++) best[t] = min(best[t], relax_add<F32>(elem4(du[k], t), wi[k]));
+        }
       }
     }
-    wave_lds_sync();
+  }
+  // groups of one segment combine their candidates
+#pragma unroll
+  for (int off = 16 * (4 / E); off < kWave; off <<= 1) {
+#pragma unroll
+    for (int t = 0; t < 4; t++) best[t] = min(best[t], (uint32_t)__shfl_xor((int)best[t], off, kWave));
   }
   // write back the improved distances of v (this lane's 4 sources)
+  if (own && split) dv = *reinterpret_cast<const uint4*>(dp);
   uint32_t imp = 0u;
-  if (sok && (best[0] != inf || best[1] != inf || best[2] != inf || best[3] != inf)) {
-    uint32_t* dp = A.D + (size_t)v * K + col;
-    const uint4 dv = *reinterpret_cast<const uint4*>(dp);
+  if (own && (best[0] != inf || best[1] != inf || best[2] != inf || best[3] != inf)) {
 #pragma unroll
     for (int t = 0; t < 4; t++)
       if (best[t] < elem4(dv, t)) imp |= 1u << t;
@@ -853,7 +852,7 @@ __device__ __forceinline__ void tile_pull_chunk(const TileArgs& A, const int4 ch
   const uint32_t lo = row16_or(j16 < 8 ? imp << (4 * j16) : 0u);
   const uint32_t hi = row16_or(j16 >= 8 ? imp << (4 * (j16 - 8)) : 0u);
   const unsigned long long x = ((unsigned long long)hi << 32) | lo;
-  if (j16 == 0 && sok && x != 0ull) {
+  if (j16 == 0 && own && x != 0ull) {
     unsigned long long* mp = A.mk[qn] + (size_t)v * nseg + s;
     if (split) atomicOr(mp, x);
     else *mp = x;
@@ -864,28 +863,29 @@ __device__ __forceinline__ void tile_pull_chunk(const TileArgs& A, const int4 ch
 template <bool F32>
 __global__ void __launch_bounds__(kPullThreads) tile_pull_kernel(TileArgs A, int32_t cap_n) {
   __shared__ unsigned long long sh_colact[kSegMax];
-  __shared__ unsigned long long lmask[kPullThreads / kWave][kWave][kSegMax];
   TileCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
   const uint32_t step = ld_agent(&C->step);
   if (!tile_is_pull_step(A, step)) return;  // the push kernel runs this step
-  const int q = step % 3, qn = (step + 1) % 3, rn = (step + 1) % kRot;
+  const int qn = (step + 1) % 3, rn = (step + 1) % kRot;
   tile_clear_prev(A, step, blockIdx.x, gridDim.x);
   if (threadIdx.x < kSegMax) sh_colact[threadIdx.x] = 0ull;
   __syncthreads();
-  Acc acc;
   const int wave = threadIdx.x >> 6;
   const uint32_t gw = blockIdx.x * (kPullThreads / kWave) + wave;
   const uint32_t nwv = gridDim.x * (kPullThreads / kWave);
   const uint32_t nq = (uint32_t)((A.nseg + 3) / 4);
   const uint32_t nch = (uint32_t)min((long long)A.T.hdr->nchunks, (long long)A.T.cap_chunks);
+  const uint32_t* fbm = A.fbm[step & 1];
   for (uint32_t task = gw; task < nch * nq; task += nwv) {
     const uint32_t c = task / nq;
     const int p = (int)(task - c * nq);
-    tile_pull_chunk<F32>(A, A.T.chunks[c], p, q, qn, A.fbm[step & 1], lmask[wave], sh_colact, acc);
+    const int nsq = min(4, A.nseg - 4 * p);
+    const int4 ch = A.T.chunks[c];
+    if (nsq >= 3) tile_pull_chunk<F32, 1>(A, ch, p, qn, fbm, sh_colact);
+    else if (nsq == 2) tile_pull_chunk<F32, 2>(A, ch, p, qn, fbm, sh_colact);
+    else tile_pull_chunk<F32, 4>(A, ch, p, qn, fbm, sh_colact);
   }
-  CtrStripe& S = C->ctr[blockIdx.x % kCtrStripes];
-  flush_acc(acc, &S.fe, &S.es, &S.im, &S.sa, &S.se);
   __syncthreads();
   if ((int)threadIdx.x < A.nseg && sh_colact[threadIdx.x])
     atomicOr(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);

@@ -287,6 +287,9 @@ PULL_TUNINGS = [
     dict(),                                 # by frontier density
     dict(tile_pull=0, tile_k=512),          # two 4-segment quads per target
     dict(tile_pull=50, tile_t_wave=32, tile_t_chunk=64, tile_sparse=0, tile_t_group=0),
+    dict(tile_pull=0, tile_k=64),           # one segment: four in-edges at a time per wave
+    dict(tile_pull=0, tile_k=128),          # two segments: two in-edges at a time
+    dict(tile_pull=0, tile_k=192),          # three segments: one 16-lane group idle
 ]
 
 
@@ -321,6 +324,23 @@ def test_msssp_pull_steps_match_push_and_oracle(dawn, wk, ti):
     # both directions relax the same (edge, source) pairs; only the order of
     # updates within a step (and so the step count) may differ
     assert info["union_edges"] > 0 and info["edges_scanned"] > 0
+
+
+@pytest.mark.parametrize("wk", ["u32", "f32lognormal"])
+def test_msssp_pull_quads_of_four_and_one_segment(dawn, wk):
+    """k = 300 sources in one 320-column tile: a pull task covers four
+    segments (one in-edge at a time) or the fifth alone (four at a time)."""
+    g = graphgen.rmat(11, 16, 23, weights=wk)
+    csr = dawn.Csr.from_graph(g)
+    tg = dawn.tgraph(csr)
+    srcs = graphgen.pick_sources(g, 300, 9)
+    announce("msssp pull k=300", wk)
+    D, info = _msssp_tg(dawn, csr, srcs, tg, tile_pull=0, tile_k=320)
+    P, _ = _msssp(dawn, g, srcs, tile_k=320)
+    assert np.array_equal(D.view(np.uint32), P.view(np.uint32))
+    for j in (0, 255, 256, 299):
+        assert_sssp_matches(g, int(srcs[j]), D[j], tag=f"pull col {j}")
+    assert info["converged"] == 1
 
 
 def test_msssp_pull_hub_target_with_many_chunks(dawn):
