@@ -118,7 +118,8 @@ typedef struct {
  * wg_threads: 256, 512 or 1024, or 0 = auto (single source: 512 for step launches,
  * 1024 for persistent launches; tiles 256).
  * grid: workgroups per launch, 0 = auto (persistent: what the device holds at
- * once; tile step launches: 16 per compute unit; single-source step launches:
+ * once; tile step launches: 4 per compute unit for the push relaxation (the
+ * pull relaxation always takes 16); single-source step launches:
  * 4 per compute unit).
  * tile_k: sources per tile for dawn_msssp / dawn_apsp, a multiple of 64,
  * at most DAWN_TILE_K_MAX. */

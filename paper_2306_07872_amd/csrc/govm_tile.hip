@@ -750,7 +750,7 @@ __global__ void __launch_bounds__(1024) tile_step_kernel(TileArgs A, int32_t cap
 // gather of u's mask words.
 // ---------------------------------------------------------------------------
 constexpr int kPullThreads = 256;
-constexpr int kPullU = 4;  // in-edges gathered at a time per 16-lane group
+constexpr int kPullU = 8;  // in-edges gathered at a time per 16-lane group
 
 // E: in-edges taken at a time by the groups of one segment (4 / segments in
 // the quad; 1 for quads of 3 or 4 segments)
@@ -1113,11 +1113,14 @@ static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_
     ktimer_end(tk, stream, 1);
     return hip_check(e, "tile persistent launch");
   }
-  // relaxation: 16 workgroups per CU, fewer for small graphs (about one
-  // workgroup per 64 vertices, at least one per CU)
+  // push relaxation: 4 workgroups per CU, fewer for small graphs (about one
+  // workgroup per 64 vertices, at least one per CU).  Each workgroup ends the
+  // step with an agent-scope release (an L2 write-back) and an arrival on one
+  // counter, about 50 ns of serial time apiece: on R-MAT scale 20, 16 per CU
+  // made a push step with a near-empty frontier cost ~200 us instead of ~20.
   const int cus = dev_info().cus;
   const int grid = T.grid > 0 ? T.grid
-                              : (int)std::max<int64_t>(cus, std::min<int64_t>(16 * cus, ((int64_t)a.n + 63) / 64));
+                              : (int)std::max<int64_t>(cus, std::min<int64_t>(4 * cus, ((int64_t)a.n + 63) / 64));
   // compaction: one 1024-thread workgroup per CU (fewer for small graphs)
   const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, ((int64_t)a.n + 1023) / 1024));
   const bool pull = a.T.hdr != nullptr && a.pull_min >= 0;
