@@ -228,7 +228,8 @@ size_t dawn_tgraph_bytes(int32_t n, int32_t m);
 size_t dawn_tgraph_build_bytes(int32_t n, int32_t m);
 /* Build the reverse graph of a valid CSR (rowptr non-decreasing, column ids in
  * [0,n)) into tgraph_dev (256-byte aligned, >= dawn_tgraph_bytes).  Weights
- * are copied as 32-bit patterns, so one reverse graph serves u32 and f32.
+ * are copied as 32-bit patterns, so one reverse graph serves u32 and f32;
+ * weights_dev = NULL builds one without weights, for dawn_umsssp_ws only.
  * Stream-ordered; nothing is kept after the call. */
 dawn_status dawn_tgraph_build(const int32_t* rowptr_dev, const int32_t* colidx_dev,
                               const void* weights_dev, int32_t n, int32_t m, void* tgraph_dev,
@@ -241,6 +242,27 @@ dawn_status dawn_msssp_tg_ws(const int32_t* rowptr_dev, const int32_t* colidx_de
                              const void* tgraph_dev, const int32_t* sources_dev, int32_t k,
                              void* dist_out_dev, void* ws_dev, size_t ws_bytes,
                              dawn_run_info* info_dev, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Hop counts (every edge weight 1): the unweighted case of the method.  With
+ * unit weights each step finds exactly the vertices one hop further, so each
+ * shortest path is found once and never changes (mu = 1, Introduction) and a
+ * step is the boolean vector-matrix product of Section 3.1 ("Principle") over
+ * per-vertex source masks: no distances are read and no atomicMin is needed.
+ * dist_out_dev: uint32 [k][n], row j = hop counts from sources[j]
+ * (0xFFFFFFFF = unreachable); the values equal dawn_msssp's with all weights
+ * 1.  No weights are read.  tgraph_dev: NULL, or the reverse graph of the
+ * same CSR (dawn_tgraph_build; weights_dev may be NULL there), with which
+ * dense steps run as pull steps that stop reading a vertex's in-edges once
+ * all its missing sources are found.  Sources are tiled as in dawn_msssp.
+ * A source outside [0, n) ends the call with info.converged = -1 and no
+ * distances beyond the initial INF.
+ * ------------------------------------------------------------------------- */
+size_t dawn_umsssp_workspace_bytes(int32_t n, int32_t m, int32_t k);
+dawn_status dawn_umsssp_ws(const int32_t* rowptr_dev, const int32_t* colidx_dev, int32_t n,
+                           int32_t m, const void* tgraph_dev, const int32_t* sources_dev,
+                           int32_t k, uint32_t* dist_out_dev, void* ws_dev, size_t ws_bytes,
+                           dawn_run_info* info_dev, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Many graphs in one launch.  A batch concatenates `count` CSR graphs of one

@@ -86,6 +86,8 @@ def load():
         "dawn_tgraph_build": ([_vp, _vp, _vp, _i32, _i32, _vp, _sz, _vp, _sz, _vp], _i32),
         "dawn_msssp_tg_ws": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp,
                               _vp], _i32),
+        "dawn_umsssp_workspace_bytes": ([_i32, _i32, _i32], _sz),
+        "dawn_umsssp_ws": ([_vp, _vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp, _vp], _i32),
         "dawn_batch_create": ([ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp),
                                ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32, _vp], _i32),
@@ -123,7 +125,7 @@ def exported_symbols() -> list[str]:
         "dawn_set_tuning", "dawn_sssp", "dawn_sssp_workspace_bytes", "dawn_sssp_ws",
         "dawn_msssp", "dawn_msssp_workspace_bytes", "dawn_msssp_ws", "dawn_apsp",
         "dawn_tgraph_bytes", "dawn_tgraph_build_bytes", "dawn_tgraph_build", "dawn_msssp_tg_ws",
-        "dawn_batch_create", "dawn_batch_sizes", "dawn_batch_vertex_offset", "dawn_batch_run",
+        "dawn_umsssp_workspace_bytes", "dawn_umsssp_ws", "dawn_batch_create", "dawn_batch_sizes", "dawn_batch_vertex_offset", "dawn_batch_run",
         "dawn_batch_capture", "dawn_batch_replay", "dawn_batch_destroy", "dawn_tile_bytes",
         "dawn_tile_create", "dawn_tile_admit", "dawn_tile_run", "dawn_tile_read",
         "dawn_tile_steps", "dawn_tile_evict", "dawn_tile_destroy", "dawn_kernel_timer",
@@ -305,6 +307,33 @@ def tgraph(csr: Csr, stream=None):
     _torch().cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     csr._tgraph = buf
     return buf
+
+
+def umsssp_workspace_bytes(n: int, m: int, k: int) -> int:
+    return int(load().dawn_umsssp_workspace_bytes(n, m, k))
+
+
+def umsssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None, tgraph=None):
+    """Hop counts from each source, every edge weight taken as 1
+    (``dawn_umsssp_ws``): uint32 [k, n] tensor, row j = sources[j],
+    0xFFFFFFFF where unreachable.  The weights of `csr` are not read.  With
+    `tgraph` (from ``tgraph(csr)``) dense steps run as pull steps."""
+    torch = _torch()
+    dev = csr.rowptr.device
+    if not torch.is_tensor(sources):
+        sources = torch.as_tensor(np.asarray(sources, dtype=np.int32), device=dev)
+    sources = sources.to(device=dev, dtype=torch.int32).contiguous()
+    k = int(sources.numel())
+    if out is None:
+        out = torch.empty((k, csr.n), dtype=torch.uint32, device=dev)
+    if ws is None:
+        ws = workspace(umsssp_workspace_bytes(csr.n, csr.m, k), dev)
+    p, nb = _aligned(ws)
+    tp = _aligned(tgraph)[0] if tgraph is not None else None
+    L = load()
+    _check(L.dawn_umsssp_ws(_ptr(csr.rowptr), _ptr(csr.colidx), csr.n, csr.m, tp, _ptr(sources),
+                            k, _ptr(out), p, nb, _ptr(info), _stream(stream)))
+    return out
 
 
 def msssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None, tgraph=None):

@@ -71,12 +71,13 @@ static bool tuning_ok(const Tuning& t) {
 }
 
 static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
-                               dawn_wtype wt, int32_t n, int32_t m) {
+                               dawn_wtype wt, int32_t n, int32_t m, bool need_w = true) {
   if (n < 1) return set_error(DAWN_E_INVALID, "n must be >= 1 (got %d)", n);
   if (n == INT32_MAX) return set_error(DAWN_E_INVALID, "n too large");
   if (m < 0) return set_error(DAWN_E_INVALID, "m must be >= 0 (got %d)", m);
   if (!rowptr) return set_error(DAWN_E_INVALID, "rowptr is null");
-  if (m > 0 && (!colidx || !w)) return set_error(DAWN_E_INVALID, "colidx/weights are null");
+  if (m > 0 && !colidx) return set_error(DAWN_E_INVALID, "colidx is null");
+  if (m > 0 && need_w && !w) return set_error(DAWN_E_INVALID, "weights are null");
   if (wt != DAWN_W_U32 && wt != DAWN_W_F32) return set_error(DAWN_E_INVALID, "unknown wtype");
   if (!tuning_ok(g_tuning)) return set_error(DAWN_E_INVALID, "tuning out of range");
   return DAWN_OK;
@@ -345,10 +346,11 @@ __global__ void dawn_info_add_kernel(dawn_run_info* acc, const dawn_run_info* pa
 static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, const void* weights,
                               dawn_wtype wt, int32_t n, int32_t m, const int32_t* sources,
                               int32_t k, void* dist_out, void* ws, dawn_run_info* info,
-                              hipStream_t stream, const void* tgraph = nullptr) {
+                              hipStream_t stream, const void* tgraph = nullptr,
+                              bool unweighted = false) {
   const bool f32 = wt == DAWN_W_F32;
   const int32_t kt = std::min(k, g_tuning.tile_k);
-  const TileLayout L = tile_layout(n, m, kt);
+  const TileLayout L = tile_layout(n, m, kt, unweighted);
   TileArgs A = tile_args(rowptr, colidx, weights, n, m, L, ws);
   if (tgraph && g_tuning.tile_pull <= 1000) {
     A.T = tgraph_view(tgraph, n, m);
@@ -358,8 +360,9 @@ static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, cons
   dawn_run_info* part = reinterpret_cast<dawn_run_info*>(static_cast<char*>(ws) + L.info);
   dawn_status st;
   // auto: step launches (a tile step has plenty of work to fill the device
-  // at full occupancy, and R-MAT-like graphs take few steps)
-  const int mode = g_tuning.mode == 0 ? 1 : g_tuning.mode;
+  // at full occupancy, and R-MAT-like graphs take few steps); hop-count
+  // tiles always take step launches
+  const int mode = unweighted || g_tuning.mode == 0 ? 1 : g_tuning.mode;
   for (int32_t j0 = 0; j0 < k; j0 += kt) {
     const int32_t cnt = std::min(kt, k - j0);
     if ((st = tile_reset(A, f32, stream)) != DAWN_OK) return st;
@@ -373,7 +376,8 @@ static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, cons
       *done.p = 0;
       for (int64_t launched = 0; launched <= n;) {
         const int chunk = g_tuning.host_check;
-        if ((st = tile_steps(A, f32, false, chunk, stream)) != DAWN_OK) break;
+        st = unweighted ? utile_steps(A, chunk, stream) : tile_steps(A, f32, false, chunk, stream);
+        if (st != DAWN_OK) break;
         launched += chunk;
         hipMemcpyAsync(done.p, &A.ctl->done, 4, hipMemcpyDeviceToHost, stream);
         if (hipStreamSynchronize(stream) != hipSuccess || *done.p) break;
@@ -421,7 +425,7 @@ extern "C" dawn_status dawn_tgraph_build(const int32_t* rowptr, const int32_t* c
                                          const void* weights, int32_t n, int32_t m,
                                          void* tgraph, size_t tgraph_bytes_, void* scratch,
                                          size_t scratch_bytes, hipStream_t stream) {
-  dawn_status st = check_graph(rowptr, colidx, weights, DAWN_W_U32, n, m);
+  dawn_status st = check_graph(rowptr, colidx, weights, DAWN_W_U32, n, m, false);
   if (st != DAWN_OK) return st;
   if (!tgraph || !scratch) return set_error(DAWN_E_INVALID, "null buffer");
   if (((reinterpret_cast<uintptr_t>(tgraph) | reinterpret_cast<uintptr_t>(scratch)) & 255u) != 0)
@@ -452,6 +456,28 @@ extern "C" dawn_status dawn_msssp_tg_ws(const int32_t* rowptr, const int32_t* co
     return set_error(DAWN_E_WORKSPACE, "workspace too small (%zu < %zu)", ws_bytes, need);
   return msssp_impl(rowptr, colidx, weights, wt, n, m, sources, k, dist_out, ws, info, stream,
                     tgraph);
+}
+
+extern "C" size_t dawn_umsssp_workspace_bytes(int32_t n, int32_t m, int32_t k) {
+  if (n < 1 || m < 0 || k < 1) return 0;
+  return tile_layout(n, m, std::min(k, g_tuning.tile_k), true).total;
+}
+
+extern "C" dawn_status dawn_umsssp_ws(const int32_t* rowptr, const int32_t* colidx, int32_t n,
+                                      int32_t m, const void* tgraph, const int32_t* sources,
+                                      int32_t k, uint32_t* dist_out, void* ws, size_t ws_bytes,
+                                      dawn_run_info* info, hipStream_t stream) {
+  dawn_status st = check_graph(rowptr, colidx, nullptr, DAWN_W_U32, n, m, false);
+  if (st != DAWN_OK) return st;
+  if (!sources || !dist_out || !ws) return set_error(DAWN_E_INVALID, "null pointer");
+  if (k < 1) return set_error(DAWN_E_INVALID, "k must be >= 1 (got %d)", k);
+  if (((reinterpret_cast<uintptr_t>(ws) | reinterpret_cast<uintptr_t>(tgraph)) & 255u) != 0)
+    return set_error(DAWN_E_INVALID, "workspace and reverse graph must be 256-byte aligned");
+  const size_t need = tile_layout(n, m, std::min(k, g_tuning.tile_k), true).total;
+  if (ws_bytes < need)
+    return set_error(DAWN_E_WORKSPACE, "workspace too small (%zu < %zu)", ws_bytes, need);
+  return msssp_impl(rowptr, colidx, nullptr, DAWN_W_U32, n, m, sources, k, dist_out, ws, info,
+                    stream, tgraph, true);
 }
 
 extern "C" dawn_status dawn_msssp(const int32_t* rowptr, const int32_t* colidx,

@@ -331,6 +331,7 @@ struct TileArgs {
   TileCtl* ctl;
   TGraph T;                   // reverse graph, or hdr == nullptr
   long long pull_min;         // pull steps when the frontier has >= this many out-edges; < 0: never
+  unsigned long long* vis;    // unweighted tiles: reached (vertex, source) pairs [n][nseg]; else null
 };
 
 }  // namespace dawn

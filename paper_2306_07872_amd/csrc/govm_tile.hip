@@ -51,6 +51,8 @@ __global__ void tile_fill_kernel(TileArgs A) {
   const int64_t nm = (int64_t)A.n * A.nseg;
   for (int r = 0; r < 3; r++)
     for (int64_t i = tid; i < nm; i += stride) A.mk[r][i] = 0ull;
+  if (A.vis)
+    for (int64_t i = tid; i < nm; i += stride) A.vis[i] = 0ull;
   if (blockIdx.x == 0) {
     uint32_t* c = reinterpret_cast<uint32_t*>(A.ctl);
     for (int i = threadIdx.x; i < (int)(sizeof(TileCtl) / 4); i += blockDim.x) c[i] = 0u;
@@ -70,9 +72,19 @@ __device__ void tile_put_source(const TileArgs& A, int32_t col, int32_t s, uint3
   st_agent_i(&C->colsteps[col], 0);
 }
 
+// A source outside [0, n) ends the run before its first step, as failed
+// validation does (converged = -1).
 __global__ void tile_seed_kernel(TileArgs A, const int32_t* sources, int32_t count) {
   if (ld_agent(&A.ctl->done)) return;  // validation failed
-  for (int32_t j = threadIdx.x; j < count; j += blockDim.x) tile_put_source(A, j, sources[j], 0u);
+  for (int32_t j = threadIdx.x; j < count; j += blockDim.x) {
+    const int32_t s = sources[j];
+    if (s >= 0 && s < A.n) {
+      tile_put_source(A, j, s, 0u);
+    } else {
+      st_agent_i(&A.ctl->converged, -1);
+      st_agent(&A.ctl->done, 1u);
+    }
+  }
 }
 
 template <bool F32>
@@ -114,6 +126,13 @@ __device__ __forceinline__ void tile_prologue(TileCtl* C, uint32_t step, int K) 
   for (int j = threadIdx.x; j < K; j += blockDim.x)
     if ((ld_agent64(&C->colact[rc][j >> 6]) >> (j & 63)) & 1ull)
       st_agent_i(&C->colsteps[j], ld_agent_i(&C->colsteps[j]) + 1);
+}
+
+// Value of a 64-bit register in lane `src` (wave-uniform), as a scalar.
+__device__ __forceinline__ unsigned long long lane64(unsigned long long x, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // Queued vertices are gathered per workgroup in LDS (per tier) and written to
@@ -164,6 +183,10 @@ __device__ __forceinline__ void compact_flush(const TileArgs& A, int q, int rc,
 
 // Counts, from step 1 on, the (vertex, source) pairs whose distance the
 // previous step lowered (a pair lowered twice in one step counts once).
+// UW (hop-count tiles): the pairs of the step's masks were reached by the
+// previous step (or are the sources, at step 0): their distance is the step
+// number, written here, and they join the reached set `vis`.
+template <bool UW>
 __device__ __forceinline__ void tile_compact(const TileArgs& A, uint32_t step, uint32_t gb,
                                              uint32_t nb, Acc& acc, CompactShared& sh) {
   TileCtl* C = A.ctl;
@@ -180,13 +203,40 @@ __device__ __forceinline__ void tile_compact(const TileArgs& A, uint32_t step, u
     unsigned long long* mp = A.mk[q] + v * nseg;
     unsigned long long any = 0ull;
     uint32_t pairs = 0u;
-    if (v < hi)
-      for (int s = 0; s < nseg; s++) {
+    unsigned long long xs[kSegMax];
+#pragma unroll
+    for (int s = 0; s < kSegMax; s++) {
+      xs[s] = 0ull;
+      if (s < nseg && v < hi) {
         const unsigned long long x = mp[s];
         any |= x;
         pairs += (uint32_t)__popcll(x);
+        if constexpr (UW) xs[s] = x;
       }
+    }
     if (step > 0) acc.im += pairs;
+    if constexpr (UW) {
+      if (any) {
+        unsigned long long* vp = A.vis + v * nseg;
+#pragma unroll
+        for (int s = 0; s < kSegMax; s++)
+          if (s < nseg && xs[s]) vp[s] |= xs[s];
+      }
+      // distances: the wavefront writes one vertex at a time, 64 sources per store
+      const int lane = lane_id();
+      const int64_t vb = v0 + (threadIdx.x & ~(kWave - 1));
+      for (unsigned long long todo = __ballot(any != 0ull); todo; todo &= todo - 1ull) {
+        const int i = __ffsll((long long)todo) - 1;
+        uint32_t* row = A.D + (size_t)(vb + i) * A.K;
+#pragma unroll
+        for (int s = 0; s < kSegMax; s++) {
+          if (s < nseg) {
+            const unsigned long long xw = lane64(xs[s], i);
+            if ((xw >> lane) & 1ull) row[s * 64 + lane] = step;
+          }
+        }
+      }
+    }
     int32_t start = 0, deg = 0;
     if (any) {
       start = A.rowptr[v];
@@ -252,13 +302,6 @@ __device__ __forceinline__ uint32_t elem4(const uint4& x, int i) {
 // OR over the 16 lanes of a row of the wavefront (lanes 16r..16r+15); every
 // lane of the row gets the result.  DPP row rotations stay in the VALU (a
 // cross-lane shuffle would go through the LDS crossbar).
-// Value of a 64-bit register in lane `src` (wave-uniform), as a scalar.
-__device__ __forceinline__ unsigned long long lane64(unsigned long long x, int src) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
-  return ((unsigned long long)hi << 32) | lo;
-}
-
 __device__ __forceinline__ uint32_t row16_or(uint32_t x) {
   x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x121, 0xF, 0xF, false);  // row_ror:1
   x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x122, 0xF, 0xF, false);  // row_ror:2
@@ -641,7 +684,7 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   bool finished = false;
   for (;;) {
     if (blockIdx.x == 0) tile_prologue(C, step, A.K);
-    tile_compact(A, step, blockIdx.x, gridDim.x, acc, csh);
+    tile_compact<false>(A, step, blockIdx.x, gridDim.x, acc, csh);
     if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       finished = true;
@@ -674,6 +717,7 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
 
 // Step launches: the compaction of a step, then its relaxation, whose last
 // workgroup advances the step and detects the end.
+template <bool UW>
 __global__ void __launch_bounds__(1024) tile_compact_kernel(TileArgs A) {
   __shared__ CompactShared csh;
   TileCtl* C = A.ctl;
@@ -681,7 +725,7 @@ __global__ void __launch_bounds__(1024) tile_compact_kernel(TileArgs A) {
   const uint32_t step = ld_agent(&C->step);
   if (blockIdx.x == 0) tile_prologue(C, step, A.K);
   Acc acc;
-  tile_compact(A, step, blockIdx.x, gridDim.x, acc, csh);
+  tile_compact<UW>(A, step, blockIdx.x, gridDim.x, acc, csh);
   // frontier rows and pairs, improvements, and the frontier's out-edges
   CtrStripe& S = C->ctr[blockIdx.x % kCtrStripes];
   flush_acc(acc, &S.fe, &S.es, &S.im, &S.sa, &S.se, &S.fedges[step % kRot]);
@@ -893,6 +937,218 @@ __global__ void __launch_bounds__(kPullThreads) tile_pull_kernel(TileArgs A, int
 }
 
 // ---------------------------------------------------------------------------
+// hop-count tiles (unit weights)
+//
+// With every weight 1 a (vertex, source) pair's distance is set once, to the
+// number of the step that reaches it: the unweighted case, in which each
+// shortest path is found exactly once (mu = 1) and a step is the boolean
+// vector-matrix product of the Principle section.  A step then needs neither
+// distances nor atomicMin.  Push: a frontier row's mask, restricted to the
+// pairs not reached yet (`vis`), is ORed into each out-neighbour's next mask.
+// Pull: a target ORs the masks of its frontier in-neighbours, restricted the
+// same way, and stops reading in-edges once every pair it still lacks has
+// been found.  The compaction of the next step writes the distances.
+// ---------------------------------------------------------------------------
+
+// 64-bit OR over the 16 lanes of this lane's row.
+__device__ __forceinline__ unsigned long long row16_or64(unsigned long long x) {
+  return ((unsigned long long)row16_or((uint32_t)(x >> 32)) << 32) | row16_or((uint32_t)x);
+}
+
+// 64-bit OR over the wavefront (wave-uniform result).
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
+  const unsigned long long r = row16_or64(x);
+  return lane64(r, 0) | lane64(r, 16) | lane64(r, 32) | lane64(r, 48);
+}
+
+// 64-bit value of lane n (a constant, 0..15) of this lane's 16-lane row.
+__device__ __forceinline__ unsigned long long row_share64(unsigned long long x, int n) {
+  const uint32_t lo = (uint32_t)row_share((int)(uint32_t)x, n);
+  const uint32_t hi = (uint32_t)row_share((int)(uint32_t)(x >> 32), n);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long shfl64(unsigned long long x, int src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src, kWave);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, kWave);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Push over the rows (or row chunks) held one per lane -- edges
+// [start, start + len) of row u when ok -- one edge per lane over their
+// concatenated edge lists.  colacc[s]: sources of segment s reached.
+__device__ __forceinline__ void utile_push_rows(const TileArgs& A, int q, int qn, bool ok,
+                                                int32_t u, int32_t start, int32_t len,
+                                                unsigned long long* colacc) {
+  const int lane = lane_id(), nseg = A.nseg;
+  unsigned long long xs[kSegMax];
+#pragma unroll
+  for (int s = 0; s < kSegMax; s++) xs[s] = (ok && s < nseg) ? A.mk[q][(size_t)u * nseg + s] : 0ull;
+  const int32_t L = ok ? len : 0;
+  int32_t incl = L;  // inclusive prefix sum of the lengths
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t y = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += y;
+  }
+  const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+  for (int32_t e0 = 0; e0 < total; e0 += kWave) {
+    const int32_t g = e0 + lane;
+    int r = 0;  // the row of edge g: first lane whose inclusive prefix exceeds g
+    for (int st = kWave / 2; st > 0; st >>= 1)
+      if (__shfl(incl, r + st - 1, kWave) <= g) r += st;
+    const bool ge = g < total;
+    const int32_t ir = __shfl(incl, r, kWave), lr = __shfl(L, r, kWave);
+    const int32_t sr = __shfl(start, r, kWave);
+    const int32_t v = ge ? A.colidx[sr + g - (ir - lr)] : 0;
+#pragma unroll
+    for (int s = 0; s < kSegMax; s++) {
+      if (s < nseg) {
+        const unsigned long long xw = shfl64(xs[s], r);
+        if (ge && xw) {
+          const size_t i = (size_t)v * nseg + s;
+          const unsigned long long y = xw & ~A.vis[i] & ~A.mk[qn][i];
+          if (y) {
+            atomicOr(&A.mk[qn][i], y);
+            colacc[s] |= y;
+          }
+        }
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(1024) utile_push_kernel(TileArgs A, int32_t cap_n) {
+  __shared__ unsigned long long sh_colact[kSegMax];
+  TileCtl* C = A.ctl;
+  if (ld_agent(&C->done)) return;
+  const uint32_t step = ld_agent(&C->step);
+  if (tile_is_pull_step(A, step)) return;  // the pull kernel runs this step
+  const int q = step % 3, qn = (step + 1) % 3, rc = step % kRot, rn = (step + 1) % kRot;
+  tile_clear_prev(A, step, blockIdx.x, gridDim.x);
+  if (threadIdx.x < kSegMax) sh_colact[threadIdx.x] = 0ull;
+  __syncthreads();
+  const int lane = lane_id(), W = blockDim.x >> 6;
+  const uint32_t gw = blockIdx.x * W + (threadIdx.x >> 6), nwv = gridDim.x * W;
+  const uint32_t n0 = min(ld_agent(&C->cnt[rc][0]), A.cap_v);
+  const uint32_t n1 = min(ld_agent(&C->cnt[rc][1]), A.cap_v);
+  const uint32_t n2 = min(ld_agent(&C->cnt[rc][2]), A.cap_wg);
+  // batches: 64 rows of the group tier, 64 of the wave tier, 4 row chunks
+  const uint32_t b0 = (n0 + 63) / 64, b1 = b0 + (n1 + 63) / 64, b2 = b1 + (n2 + 3) / 4;
+  unsigned long long colacc[kSegMax];
+#pragma unroll
+  for (int s = 0; s < kSegMax; s++) colacc[s] = 0ull;
+  for (uint32_t b = gw; b < b2; b += nwv) {
+    bool ok = false;
+    int32_t u = 0, start = 0, len = 0;
+    if (b < b1) {
+      const bool grp = b < b0;
+      const uint32_t i = (grp ? b : b - b0) * 64 + (uint32_t)lane;
+      ok = i < (grp ? n0 : n1);
+      if (ok) {
+        u = ld_queue(grp ? A.qgrp[q] + i : A.qwave[q] + i);
+        start = A.rowptr[u];
+        len = A.rowptr[u + 1] - start;
+      }
+    } else {
+      const uint32_t i = (b - b1) * 4 + (uint32_t)lane;
+      ok = lane < 4 && i < n2;
+      if (ok) {
+        const int4 r = ld_queue4(&A.qwg[q][i]);
+        u = r.x;
+        start = r.y;
+        len = r.z;
+      }
+    }
+    utile_push_rows(A, q, qn, ok, u, start, len, colacc);
+  }
+#pragma unroll
+  for (int s = 0; s < kSegMax; s++) {
+    if (s < A.nseg) {
+      const unsigned long long x = wave_or64(colacc[s]);
+      if (lane == 0 && x) atomicOr(&sh_colact[s], x);
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < A.nseg && sh_colact[threadIdx.x])
+    atomicOr(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
+  tile_end_step(A, step, cap_n);
+}
+
+// Pull: each 16-lane group takes one in-edge chunk of a target v, 16 in-edges
+// at a time; lane j (< nseg) of the group holds v's segment-j words.
+__global__ void __launch_bounds__(kPullThreads) utile_pull_kernel(TileArgs A, int32_t cap_n) {
+  __shared__ unsigned long long sh_colact[kSegMax];
+  TileCtl* C = A.ctl;
+  if (ld_agent(&C->done)) return;
+  const uint32_t step = ld_agent(&C->step);
+  if (!tile_is_pull_step(A, step)) return;  // the push kernel runs this step
+  const int q = step % 3, qn = (step + 1) % 3, rn = (step + 1) % kRot;
+  tile_clear_prev(A, step, blockIdx.x, gridDim.x);
+  if (threadIdx.x < kSegMax) sh_colact[threadIdx.x] = 0ull;
+  __syncthreads();
+  const int lane = lane_id(), g = lane >> 4, j16 = lane & 15, nseg = A.nseg;
+  const uint32_t gw = blockIdx.x * (kPullThreads / kWave) + (threadIdx.x >> 6);
+  const uint32_t nwv = gridDim.x * (kPullThreads / kWave);
+  const uint32_t nch = (uint32_t)min((long long)A.T.hdr->nchunks, (long long)A.T.cap_chunks);
+  const uint32_t* fbm = A.fbm[step & 1];
+  const unsigned long long live = j16 < nseg ? ld_agent64(&C->live[j16]) : 0ull;
+  unsigned long long colacc = 0ull;  // lanes j16 < nseg: sources of segment j16 reached
+  for (uint32_t c0 = gw * 4; c0 < nch; c0 += nwv * 4) {
+    const uint32_t c = c0 + (uint32_t)g;
+    const bool cok = c < nch;
+    const int4 ch = cok ? A.T.chunks[c] : make_int4(0, 0, 0, 0);
+    const int32_t v = ch.x, start = ch.y, len = ch.z;
+    const bool split = ch.w != 0;
+    // the pairs of v not reached yet
+    const unsigned long long nd =
+        (cok && j16 < nseg) ? (~A.vis[(size_t)v * nseg + j16] & live) : 0ull;
+    unsigned long long need[kSegMax], acc[kSegMax];
+    bool open = false;
+#pragma unroll
+    for (int s = 0; s < kSegMax; s++) {
+      need[s] = s < nseg ? row_share64(nd, s) : 0ull;
+      acc[s] = 0ull;
+      open |= need[s] != 0ull;
+    }
+    for (int32_t b = 0; __ballot(open && b < len) != 0ull; b += 16) {
+      const bool act = open && b + j16 < len;
+      int32_t u = 0;
+      bool fr = false;
+      if (act) {
+        u = A.T.colidx[start + b + j16];
+        fr = ((fbm[u >> 5] >> (u & 31)) & 1u) != 0u;
+      }
+      bool full = true;
+#pragma unroll
+      for (int s = 0; s < kSegMax; s++) {
+        if (s < nseg) {
+          const unsigned long long a = fr ? (A.mk[q][(size_t)u * nseg + s] & need[s]) : 0ull;
+          acc[s] |= row16_or64(a);
+          full = full && acc[s] == need[s];
+        }
+      }
+      if (full) open = false;
+    }
+    // the pairs reached become v's next mask words, one lane per segment
+    unsigned long long x = 0ull;
+#pragma unroll
+    for (int s = 0; s < kSegMax; s++)
+      if (s == j16) x = acc[s];
+    if (cok && j16 < nseg && x) {
+      unsigned long long* mp = A.mk[qn] + (size_t)v * nseg + j16;
+      if (split) atomicOr(mp, x);
+      else *mp = x;
+      colacc |= x;
+    }
+  }
+  if (j16 < nseg && colacc) atomicOr(&sh_colact[j16], colacc);
+  __syncthreads();
+  if ((int)threadIdx.x < A.nseg && sh_colact[threadIdx.x])
+    atomicOr(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
+  tile_end_step(A, step, cap_n);
+}
+
+// ---------------------------------------------------------------------------
 // outputs
 // ---------------------------------------------------------------------------
 
@@ -970,8 +1226,9 @@ __global__ void tile_col_steps_kernel(const TileCtl* C, int32_t k, int32_t* out)
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-TileLayout tile_layout(int64_t n, int64_t m, int32_t k) {
+TileLayout tile_layout(int64_t n, int64_t m, int32_t k, bool unweighted) {
   TileLayout L{};
+  L.unweighted = unweighted;
   Carver c;
   L.nseg = (k + 63) / 64;
   L.K = L.nseg * 64;
@@ -987,6 +1244,7 @@ TileLayout tile_layout(int64_t n, int64_t m, int32_t k) {
   for (int i = 0; i < 3; i++) L.qwave[i] = c.take((size_t)n * 4);
   for (int i = 0; i < 3; i++) L.qwg[i] = c.take((size_t)L.cap_wg * 16);
   for (int i = 0; i < 2; i++) L.fbm[i] = c.take((size_t)((n + 63) / 64) * 8);
+  if (unweighted) L.vis = c.take((size_t)n * L.nseg * 8);
   L.total = c.off;
   return L;
 }
@@ -1021,6 +1279,7 @@ TileArgs tile_args(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.cap_v = L.cap_v;
   A.cap_wg = L.cap_wg;
   A.ctl = reinterpret_cast<TileCtl*>(base + L.ctl);
+  A.vis = L.unweighted ? reinterpret_cast<unsigned long long*>(base + L.vis) : nullptr;
   return A;
 }
 
@@ -1126,7 +1385,7 @@ static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_
   const bool pull = a.T.hdr != nullptr && a.pull_min >= 0;
   const int pgrid = 16 * cus;
   for (int s = 0; s < max_steps; s++) {
-    hipLaunchKernelGGL(tile_compact_kernel, dim3(cgrid), dim3(1024), 0, stream, a);
+    hipLaunchKernelGGL(tile_compact_kernel<false>, dim3(cgrid), dim3(1024), 0, stream, a);
     void* tk = ktimer_begin(stream);
     hipLaunchKernelGGL(tile_step_kernel<F32>, dim3(grid), dim3(threads), 0, stream, a, 0);
     if (pull)
@@ -1134,6 +1393,25 @@ static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_
     ktimer_end(tk, stream, 1);
   }
   return hip_check(hipGetLastError(), "tile step launches");
+}
+
+dawn_status utile_steps(const TileArgs& a, int32_t max_steps, hipStream_t stream) {
+  const Tuning& T = tuning();
+  const int threads = T.wg_threads > 0 ? T.wg_threads : 256;
+  const int cus = dev_info().cus;
+  const int grid = T.grid > 0 ? T.grid
+                              : (int)std::max<int64_t>(cus, std::min<int64_t>(4 * cus, ((int64_t)a.n + 63) / 64));
+  const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, ((int64_t)a.n + 1023) / 1024));
+  const bool pull = a.T.hdr != nullptr && a.pull_min >= 0;
+  const int pgrid = 16 * cus;
+  for (int s = 0; s < max_steps; s++) {
+    hipLaunchKernelGGL(tile_compact_kernel<true>, dim3(cgrid), dim3(1024), 0, stream, a);
+    void* tk = ktimer_begin(stream);
+    hipLaunchKernelGGL(utile_push_kernel, dim3(grid), dim3(threads), 0, stream, a, 0);
+    if (pull) hipLaunchKernelGGL(utile_pull_kernel, dim3(pgrid), dim3(kPullThreads), 0, stream, a, 0);
+    ktimer_end(tk, stream, 1);
+  }
+  return hip_check(hipGetLastError(), "hop-count tile step launches");
 }
 
 dawn_status tile_steps(const TileArgs& a, bool f32, bool persistent, int32_t max_steps,

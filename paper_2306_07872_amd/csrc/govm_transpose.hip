@@ -171,7 +171,7 @@ __global__ void tg_scatter_kernel(const int32_t* rowptr, const int32_t* colidx, 
     const int32_t v = colidx[e];
     const int32_t p = atomicAdd(&cursor[v], 1);
     t_colidx[p] = (int32_t)u;
-    t_w[p] = w[e];
+    if (w) t_w[p] = w[e];
   }
 }
 

@@ -96,3 +96,26 @@ def test_workspace_sizes_grow_with_graph(lib):
     # tile: the [n x K] distance tile dominates
     t = lib.dawn_msssp_workspace_bytes(1 << 20, 16 << 20, 256)
     assert t >= (1 << 20) * 256 * 4
+
+
+def test_hop_count_entry_point_host_checks(lib):
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    need = lib.dawn_umsssp_workspace_bytes(100, 1000, 64)
+    # the reached-pairs bitset on top of the weighted tile: n x K/64 words
+    assert need >= lib.dawn_msssp_workspace_bytes(100, 1000, 64) + 100 * 8
+    assert lib.dawn_umsssp_workspace_bytes(0, 10, 64) == 0
+    assert lib.dawn_umsssp_workspace_bytes(100, 1000, 0) == 0
+    # no weights needed; colidx is (m > 0)
+    assert lib.dawn_umsssp_ws(fake, null, 100, 1000, null, fake, 4, fake, ws, need, null,
+                              null) == 1
+    assert lib.dawn_umsssp_ws(fake, fake, 100, 1000, null, fake, 0, fake, ws, need, null,
+                              null) == 1
+    assert lib.dawn_umsssp_ws(fake, fake, 100, 1000, null, null, 4, fake, ws, need, null,
+                              null) == 1
+    assert lib.dawn_umsssp_ws(fake, fake, 100, 1000, null, fake, 4, fake, ws, need - 1, null,
+                              null) == 3
+    assert lib.dawn_umsssp_ws(fake, fake, 100, 1000, ctypes.c_void_p(0x2010), fake, 4, fake, ws,
+                              need, null, null) == 1
+    assert b"aligned" in lib.dawn_last_error()
