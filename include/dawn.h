@@ -111,7 +111,8 @@ typedef struct {
  * the rest; otherwise (and when captured) as one persistent launch; tiles: 1.
  * 1 step
  * launches (one kernel per step; the host checks termination every
- * `host_check` steps, so such a call waits for its stream), 2 one persistent
+ * `host_check` steps -- for tiles, the first two checks after host_check / 4
+ * steps each -- so such a call waits for its stream), 2 one persistent
  * launch for all steps with a grid
  * barrier between steps (the barrier gives up after a few seconds, so a grid
  * that cannot be co-resident ends with converged = -2 instead of hanging).

@@ -374,8 +374,11 @@ static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, cons
       PinnedWord done;
       if (!done.p) return set_error(DAWN_E_HIP, "hipHostMalloc failed");
       *done.p = 0;
-      for (int64_t launched = 0; launched <= n;) {
-        const int chunk = g_tuning.host_check;
+      // the first two checks come after host_check / 4 launches each: a
+      // small-world graph's tile takes about 8 to 16 steps, and every launch
+      // queued past the end costs a few microseconds for nothing
+      for (int64_t launched = 0, i = 0; launched <= n; i++) {
+        const int chunk = i < 2 ? std::max(1, g_tuning.host_check / 4) : g_tuning.host_check;
         st = unweighted ? utile_steps(A, chunk, stream) : tile_steps(A, f32, false, chunk, stream);
         if (st != DAWN_OK) break;
         launched += chunk;
@@ -385,7 +388,9 @@ static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, cons
       if (st != DAWN_OK) return st;
     }
     char* out = static_cast<char*>(dist_out) + (size_t)j0 * (size_t)n * 4;
-    if ((st = tile_store(A, 0, cnt, out, n, stream)) != DAWN_OK) return st;
+    st = unweighted ? utile_store(A, 0, cnt, reinterpret_cast<uint32_t*>(out), n, stream)
+                    : tile_store(A, 0, cnt, out, n, stream);
+    if (st != DAWN_OK) return st;
     if (info) {
       if ((st = tile_info(A, part, stream)) != DAWN_OK) return st;
       hipLaunchKernelGGL(dawn_info_add_kernel, dim3(1), dim3(64), 0, stream, info, part,

@@ -266,6 +266,17 @@ __device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* fe,
   }
 }
 
+// A control word read once per workgroup (thread 0, agent scope) and shared
+// through LDS: an agent-scope load misses in the L2, and one per wavefront
+// from a large grid queues on a single address.  Every thread must call it.
+__device__ __forceinline__ uint32_t ld_agent_block(const uint32_t* p) {
+  __shared__ uint32_t s_val;
+  __syncthreads();  // an earlier call's readers are done
+  if (threadIdx.x == 0) s_val = ld_agent(p);
+  __syncthreads();
+  return s_val;
+}
+
 // Sum of one counter over the stripes, in every lane (all lanes must be active).
 __device__ __forceinline__ unsigned long long ctr_sum(const CtrStripe* ctr, size_t offset) {
   const int lane = lane_id();
@@ -331,7 +342,11 @@ struct TileArgs {
   TileCtl* ctl;
   TGraph T;                   // reverse graph, or hdr == nullptr
   long long pull_min;         // pull steps when the frontier has >= this many out-edges; < 0: never
-  unsigned long long* vis;    // unweighted tiles: reached (vertex, source) pairs [n][nseg]; else null
+  unsigned long long* vis;    // hop-count tiles: reached (vertex, source) pairs [n][nseg]; else null
+  // hop-count tiles: the distances as bit planes, plane b = bit b of the step
+  // that reached each pair, [nplanes][n][nseg]; D is null there
+  unsigned long long* planes;
+  int32_t nplanes;
 };
 
 }  // namespace dawn

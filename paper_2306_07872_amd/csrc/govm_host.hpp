@@ -75,8 +75,9 @@ dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, 
 
 // ----- distance tile ---------------------------------------------------------
 struct TileLayout {
-  size_t ctl, info, D, mk[3], qgrp[3], qwave[3], qwg[3], fbm[2], vis, total;
+  size_t ctl, info, D, mk[3], qgrp[3], qwave[3], qwg[3], fbm[2], vis, planes, total;
   bool unweighted;
+  int32_t nplanes;
   uint32_t cap_v, cap_wg;
   int32_t K, nseg;
 };
@@ -103,8 +104,11 @@ dawn_status tile_store(const TileArgs& a, int32_t col0, int32_t count, void* out
 dawn_status tile_read_col(const TileArgs& a, int32_t col, void* out, hipStream_t stream);
 dawn_status tile_info(const TileArgs& a, dawn_run_info* info, hipStream_t stream);
 dawn_status tile_col_steps(const TileArgs& a, int32_t k, int32_t* out, hipStream_t stream);
-// Hop-count tiles (unit weights): `max_steps` step launches.
+// Hop-count tiles (unit weights): `max_steps` step launches; distances out
+// of the bit planes into out[j * ld + v] for columns [col0, col0 + count).
 dawn_status utile_steps(const TileArgs& a, int32_t max_steps, hipStream_t stream);
+dawn_status utile_store(const TileArgs& a, int32_t col0, int32_t count, uint32_t* out, int64_t ld,
+                        hipStream_t stream);
 
 // Persistent grid sizes (workgroups per CU, total) at `threads` per workgroup.
 void ss_persistent_occupancy(int threads, int* per_cu, int* grid);

@@ -47,7 +47,8 @@ __global__ void tile_fill_kernel(TileArgs A) {
   const int64_t nd4 = (int64_t)A.n * A.K / 4;
   const uint32_t inf = inf_bits<F32>();
   uint4* d4 = reinterpret_cast<uint4*>(A.D);
-  for (int64_t i = tid; i < nd4; i += stride) d4[i] = make_uint4(inf, inf, inf, inf);
+  if (A.D)
+    for (int64_t i = tid; i < nd4; i += stride) d4[i] = make_uint4(inf, inf, inf, inf);
   const int64_t nm = (int64_t)A.n * A.nseg;
   for (int r = 0; r < 3; r++)
     for (int64_t i = tid; i < nm; i += stride) A.mk[r][i] = 0ull;
@@ -65,7 +66,7 @@ __device__ void tile_put_source(const TileArgs& A, int32_t col, int32_t s, uint3
   TileCtl* C = A.ctl;
   const int seg = col >> 6;
   const unsigned long long bit = 1ull << (col & 63);
-  A.D[(size_t)s * A.K + col] = 0u;
+  if (A.D) A.D[(size_t)s * A.K + col] = 0u;
   atomicOr(&A.mk[t % 3][(size_t)s * A.nseg + seg], bit);
   atomicOr(&C->colact[t % kRot][seg], bit);
   atomicOr(&C->live[seg], bit);
@@ -185,7 +186,9 @@ __device__ __forceinline__ void compact_flush(const TileArgs& A, int q, int rc,
 // previous step lowered (a pair lowered twice in one step counts once).
 // UW (hop-count tiles): the pairs of the step's masks were reached by the
 // previous step (or are the sources, at step 0): their distance is the step
-// number, written here, and they join the reached set `vis`.
+// number t, recorded here in the bit planes (bit b of t set: the pair's bit
+// in plane b set), and they join the reached set `vis`.  Plane b is written
+// whole, zeros included, at step 2^b, its first use, so nothing clears it.
 template <bool UW>
 __device__ __forceinline__ void tile_compact(const TileArgs& A, uint32_t step, uint32_t gb,
                                              uint32_t nb, Acc& acc, CompactShared& sh) {
@@ -216,23 +219,25 @@ __device__ __forceinline__ void tile_compact(const TileArgs& A, uint32_t step, u
     }
     if (step > 0) acc.im += pairs;
     if constexpr (UW) {
+      const size_t pn = (size_t)n * nseg;
+      const bool first = step > 0 && (step & (step - 1u)) == 0u;  // step = 2^b
+      if (first && v < hi) {
+        unsigned long long* pp = A.planes + (size_t)(__ffs(step) - 1) * pn + v * nseg;
+#pragma unroll
+        for (int s = 0; s < kSegMax; s++)
+          if (s < nseg) pp[s] = xs[s];
+      }
       if (any) {
         unsigned long long* vp = A.vis + v * nseg;
 #pragma unroll
         for (int s = 0; s < kSegMax; s++)
           if (s < nseg && xs[s]) vp[s] |= xs[s];
-      }
-      // distances: the wavefront writes one vertex at a time, 64 sources per store
-      const int lane = lane_id();
-      const int64_t vb = v0 + (threadIdx.x & ~(kWave - 1));
-      for (unsigned long long todo = __ballot(any != 0ull); todo; todo &= todo - 1ull) {
-        const int i = __ffsll((long long)todo) - 1;
-        uint32_t* row = A.D + (size_t)(vb + i) * A.K;
+        if (!first) {
+          for (uint32_t bits = step; bits; bits &= bits - 1u) {
+            unsigned long long* pp = A.planes + (size_t)(__ffs(bits) - 1) * pn + v * nseg;
 #pragma unroll
-        for (int s = 0; s < kSegMax; s++) {
-          if (s < nseg) {
-            const unsigned long long xw = lane64(xs[s], i);
-            if ((xw >> lane) & 1ull) row[s * 64 + lane] = step;
+            for (int s = 0; s < kSegMax; s++)
+              if (s < nseg && xs[s]) pp[s] |= xs[s];
           }
         }
       }
@@ -1173,6 +1178,41 @@ __global__ void tile_store_kernel(const uint32_t* D, int32_t n, int32_t K, int32
   }
 }
 
+// Hop-count tiles: out[(c - col0) * ld + v] for columns c in [col0, col0 +
+// count): the pair's level assembled from the bit planes in use (levels up
+// to the last step, whose compaction ran at step - 1), INF if never reached.
+// A workgroup takes 64 vertices (lane = vertex) and one 64-column segment,
+// four rows at a time, so every store is 64 contiguous words; the segment is
+// the grid's second index, so the workgroups running together write the same
+// 64 output rows.
+__global__ void __launch_bounds__(256) utile_store_kernel(TileArgs A, int32_t col0, int32_t count,
+                                                          uint32_t* out, int64_t ld) {
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t v = (int64_t)blockIdx.x * 64 + tx;
+  const int nseg = A.nseg;
+  const uint32_t last = ld_agent_block(&A.ctl->step);  // levels are <= last - 1
+  int nb = 0;
+  while (nb < A.nplanes && ((uint32_t)1 << nb) < last) nb++;  // planes 0 .. nb-1 are in use
+  const size_t pn = (size_t)A.n * nseg;
+  const int s = (col0 >> 6) + (int)blockIdx.y;
+  // this thread's 16 columns of the segment: bits ty, ty + 4, ..., ty + 60
+  uint32_t lvl[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) lvl[i] = 0u;
+  for (int b = 0; b < nb; b++) {
+    const unsigned long long w = v < A.n ? A.planes[(size_t)b * pn + v * nseg + s] >> ty : 0ull;
+#pragma unroll
+    for (int i = 0; i < 16; i++) lvl[i] |= (uint32_t)((w >> (4 * i)) & 1ull) << b;
+  }
+  const unsigned long long vw = v < A.n ? A.vis[v * nseg + s] >> ty : 0ull;
+#pragma unroll
+  for (int i = 0; i < 16; i++) {
+    const int c = s * 64 + ty + 4 * i;
+    if (c >= col0 && c < col0 + count && v < A.n)
+      out[(size_t)(c - col0) * ld + v] = ((vw >> (4 * i)) & 1ull) ? lvl[i] : 0xFFFFFFFFu;
+  }
+}
+
 __global__ void tile_read_col_kernel(const uint32_t* D, int32_t n, int32_t K, int32_t col,
                                      uint32_t* out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1238,13 +1278,20 @@ TileLayout tile_layout(int64_t n, int64_t m, int32_t k, bool unweighted) {
   L.cap_wg = (uint32_t)(m / 33 + m / 64 + 2);
   L.ctl = c.take(sizeof(TileCtl));
   L.info = c.take(sizeof(dawn_run_info));
-  L.D = c.take((size_t)n * L.K * 4);
+  // hop-count tiles keep their distances as bit planes (levels < n), not in D
+  if (!unweighted) L.D = c.take((size_t)n * L.K * 4);
   for (int i = 0; i < 3; i++) L.mk[i] = c.take((size_t)n * L.nseg * 8);
   for (int i = 0; i < 3; i++) L.qgrp[i] = c.take((size_t)n * 4);
   for (int i = 0; i < 3; i++) L.qwave[i] = c.take((size_t)n * 4);
   for (int i = 0; i < 3; i++) L.qwg[i] = c.take((size_t)L.cap_wg * 16);
   for (int i = 0; i < 2; i++) L.fbm[i] = c.take((size_t)((n + 63) / 64) * 8);
-  if (unweighted) L.vis = c.take((size_t)n * L.nseg * 8);
+  if (unweighted) {
+    L.vis = c.take((size_t)n * L.nseg * 8);
+    int32_t p = 1;
+    while (p < 31 && ((int64_t)1 << p) < n) p++;
+    L.nplanes = p;
+    L.planes = c.take((size_t)p * n * L.nseg * 8);
+  }
   L.total = c.off;
   return L;
 }
@@ -1257,7 +1304,7 @@ TileArgs tile_args(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.rowptr = rowptr;
   A.colidx = colidx;
   A.w = static_cast<const uint32_t*>(w);
-  A.D = reinterpret_cast<uint32_t*>(base + L.D);
+  A.D = L.unweighted ? nullptr : reinterpret_cast<uint32_t*>(base + L.D);
   A.n = n;
   A.m = m;
   A.K = L.K;
@@ -1280,6 +1327,8 @@ TileArgs tile_args(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.cap_wg = L.cap_wg;
   A.ctl = reinterpret_cast<TileCtl*>(base + L.ctl);
   A.vis = L.unweighted ? reinterpret_cast<unsigned long long*>(base + L.vis) : nullptr;
+  A.planes = L.unweighted ? reinterpret_cast<unsigned long long*>(base + L.planes) : nullptr;
+  A.nplanes = L.unweighted ? L.nplanes : 0;
   return A;
 }
 
@@ -1431,6 +1480,15 @@ dawn_status tile_store(const TileArgs& a, int32_t col0, int32_t count, void* out
   hipLaunchKernelGGL(tile_store_kernel, grid, dim3(256), 0, stream, a.D, a.n, a.K, col0, count,
                      static_cast<uint32_t*>(out), ld);
   return hip_check(hipGetLastError(), "tile store");
+}
+
+dawn_status utile_store(const TileArgs& a, int32_t col0, int32_t count, uint32_t* out, int64_t ld,
+                        hipStream_t stream) {
+  if (count < 1) return DAWN_OK;
+  const unsigned segs = (unsigned)(((col0 + count - 1) >> 6) - (col0 >> 6) + 1);
+  hipLaunchKernelGGL(utile_store_kernel, dim3((unsigned)((a.n + 63) / 64), segs), dim3(256), 0,
+                     stream, a, col0, count, out, ld);
+  return hip_check(hipGetLastError(), "hop-count tile store");
 }
 
 dawn_status tile_read_col(const TileArgs& a, int32_t col, void* out, hipStream_t stream) {

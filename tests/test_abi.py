@@ -103,8 +103,9 @@ def test_hop_count_entry_point_host_checks(lib):
     fake = ctypes.c_void_p(0x1000)
     ws = ctypes.c_void_p(0x100000)
     need = lib.dawn_umsssp_workspace_bytes(100, 1000, 64)
-    # the reached-pairs bitset on top of the weighted tile: n x K/64 words
-    assert need >= lib.dawn_msssp_workspace_bytes(100, 1000, 64) + 100 * 8
+    # no [n x K] distance tile: the reached-pairs bitset and ceil(log2 n) = 7
+    # bit planes of n x K/64 words each
+    assert 100 * 8 * 8 <= need < lib.dawn_msssp_workspace_bytes(100, 1000, 64)
     assert lib.dawn_umsssp_workspace_bytes(0, 10, 64) == 0
     assert lib.dawn_umsssp_workspace_bytes(100, 1000, 0) == 0
     # no weights needed; colidx is (m > 0)
