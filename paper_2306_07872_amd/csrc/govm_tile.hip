@@ -979,16 +979,38 @@ __device__ __forceinline__ unsigned long long shfl64(unsigned long long x, int s
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// The nseg (<= S) mask words of a row: 16-byte loads when the row is a whole
+// number of them (nseg = S = 2, 4 or 8: rows are then 16-byte aligned).
+template <int S>
+__device__ __forceinline__ void load_mask_row(const unsigned long long* p, int nseg,
+                                              unsigned long long (&x)[S]) {
+  if constexpr (S >= 2) {
+    if (nseg == S) {
+#pragma unroll
+      for (int s = 0; s < S; s += 2) {
+        const ulonglong2 t = *reinterpret_cast<const ulonglong2*>(p + s);
+        x[s] = t.x;
+        x[s + 1] = t.y;
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < S; s++) x[s] = s < nseg ? p[s] : 0ull;
+}
+
 // Push over the rows (or row chunks) held one per lane -- edges
 // [start, start + len) of row u when ok -- one edge per lane over their
 // concatenated edge lists.  colacc[s]: sources of segment s reached.
+template <int S>
 __device__ __forceinline__ void utile_push_rows(const TileArgs& A, int q, int qn, bool ok,
                                                 int32_t u, int32_t start, int32_t len,
-                                                unsigned long long* colacc) {
+                                                unsigned long long (&colacc)[S]) {
   const int lane = lane_id(), nseg = A.nseg;
-  unsigned long long xs[kSegMax];
+  unsigned long long xs[S];
 #pragma unroll
-  for (int s = 0; s < kSegMax; s++) xs[s] = (ok && s < nseg) ? A.mk[q][(size_t)u * nseg + s] : 0ull;
+  for (int s = 0; s < S; s++) xs[s] = 0ull;
+  if (ok) load_mask_row<S>(A.mk[q] + (size_t)u * nseg, nseg, xs);
   const int32_t L = ok ? len : 0;
   int32_t incl = L;  // inclusive prefix sum of the lengths
   for (int off = 1; off < kWave; off <<= 1) {
@@ -1006,7 +1028,7 @@ __device__ __forceinline__ void utile_push_rows(const TileArgs& A, int q, int qn
     const int32_t sr = __shfl(start, r, kWave);
     const int32_t v = ge ? A.colidx[sr + g - (ir - lr)] : 0;
 #pragma unroll
-    for (int s = 0; s < kSegMax; s++) {
+    for (int s = 0; s < S; s++) {
       if (s < nseg) {
         const unsigned long long xw = shfl64(xs[s], r);
         if (ge && xw) {
@@ -1022,6 +1044,7 @@ __device__ __forceinline__ void utile_push_rows(const TileArgs& A, int q, int qn
   }
 }
 
+template <int S>
 __global__ void __launch_bounds__(1024) utile_push_kernel(TileArgs A, int32_t cap_n) {
   __shared__ unsigned long long sh_colact[kSegMax];
   TileCtl* C = A.ctl;
@@ -1039,9 +1062,9 @@ __global__ void __launch_bounds__(1024) utile_push_kernel(TileArgs A, int32_t ca
   const uint32_t n2 = min(ld_agent(&C->cnt[rc][2]), A.cap_wg);
   // batches: 64 rows of the group tier, 64 of the wave tier, 4 row chunks
   const uint32_t b0 = (n0 + 63) / 64, b1 = b0 + (n1 + 63) / 64, b2 = b1 + (n2 + 3) / 4;
-  unsigned long long colacc[kSegMax];
+  unsigned long long colacc[S];
 #pragma unroll
-  for (int s = 0; s < kSegMax; s++) colacc[s] = 0ull;
+  for (int s = 0; s < S; s++) colacc[s] = 0ull;
   for (uint32_t b = gw; b < b2; b += nwv) {
     bool ok = false;
     int32_t u = 0, start = 0, len = 0;
@@ -1064,10 +1087,10 @@ __global__ void __launch_bounds__(1024) utile_push_kernel(TileArgs A, int32_t ca
         len = r.z;
       }
     }
-    utile_push_rows(A, q, qn, ok, u, start, len, colacc);
+    utile_push_rows<S>(A, q, qn, ok, u, start, len, colacc);
   }
 #pragma unroll
-  for (int s = 0; s < kSegMax; s++) {
+  for (int s = 0; s < S; s++) {
     if (s < A.nseg) {
       const unsigned long long x = wave_or64(colacc[s]);
       if (lane == 0 && x) atomicOr(&sh_colact[s], x);
@@ -1081,6 +1104,7 @@ __global__ void __launch_bounds__(1024) utile_push_kernel(TileArgs A, int32_t ca
 
 // Pull: each 16-lane group takes one in-edge chunk of a target v, 16 in-edges
 // at a time; lane j (< nseg) of the group holds v's segment-j words.
+template <int S>
 __global__ void __launch_bounds__(kPullThreads) utile_pull_kernel(TileArgs A, int32_t cap_n) {
   __shared__ unsigned long long sh_colact[kSegMax];
   TileCtl* C = A.ctl;
@@ -1107,10 +1131,10 @@ __global__ void __launch_bounds__(kPullThreads) utile_pull_kernel(TileArgs A, in
     // the pairs of v not reached yet
     const unsigned long long nd =
         (cok && j16 < nseg) ? (~A.vis[(size_t)v * nseg + j16] & live) : 0ull;
-    unsigned long long need[kSegMax], acc[kSegMax];
+    unsigned long long need[S], acc[S];
     bool open = false;
 #pragma unroll
-    for (int s = 0; s < kSegMax; s++) {
+    for (int s = 0; s < S; s++) {
       need[s] = s < nseg ? row_share64(nd, s) : 0ull;
       acc[s] = 0ull;
       open |= need[s] != 0ull;
@@ -1123,12 +1147,15 @@ __global__ void __launch_bounds__(kPullThreads) utile_pull_kernel(TileArgs A, in
         u = A.T.colidx[start + b + j16];
         fr = ((fbm[u >> 5] >> (u & 31)) & 1u) != 0u;
       }
+      unsigned long long m[S];
+#pragma unroll
+      for (int s = 0; s < S; s++) m[s] = 0ull;
+      if (fr) load_mask_row<S>(A.mk[q] + (size_t)u * nseg, nseg, m);
       bool full = true;
 #pragma unroll
-      for (int s = 0; s < kSegMax; s++) {
+      for (int s = 0; s < S; s++) {
         if (s < nseg) {
-          const unsigned long long a = fr ? (A.mk[q][(size_t)u * nseg + s] & need[s]) : 0ull;
-          acc[s] |= row16_or64(a);
+          acc[s] |= row16_or64(m[s] & need[s]);
           full = full && acc[s] == need[s];
         }
       }
@@ -1137,7 +1164,7 @@ __global__ void __launch_bounds__(kPullThreads) utile_pull_kernel(TileArgs A, in
     // the pairs reached become v's next mask words, one lane per segment
     unsigned long long x = 0ull;
 #pragma unroll
-    for (int s = 0; s < kSegMax; s++)
+    for (int s = 0; s < S; s++)
       if (s == j16) x = acc[s];
     if (cok && j16 < nseg && x) {
       unsigned long long* mp = A.mk[qn] + (size_t)v * nseg + j16;
@@ -1453,11 +1480,16 @@ dawn_status utile_steps(const TileArgs& a, int32_t max_steps, hipStream_t stream
   const int cgrid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, ((int64_t)a.n + 1023) / 1024));
   const bool pull = a.T.hdr != nullptr && a.pull_min >= 0;
   const int pgrid = 16 * cus;
+  // kernels specialised for the largest segment count they serve
+  auto push = a.nseg <= 1 ? utile_push_kernel<1> : a.nseg <= 2 ? utile_push_kernel<2>
+            : a.nseg <= 4 ? utile_push_kernel<4> : utile_push_kernel<8>;
+  auto pullk = a.nseg <= 1 ? utile_pull_kernel<1> : a.nseg <= 2 ? utile_pull_kernel<2>
+             : a.nseg <= 4 ? utile_pull_kernel<4> : utile_pull_kernel<8>;
   for (int s = 0; s < max_steps; s++) {
     hipLaunchKernelGGL(tile_compact_kernel<true>, dim3(cgrid), dim3(1024), 0, stream, a);
     void* tk = ktimer_begin(stream);
-    hipLaunchKernelGGL(utile_push_kernel, dim3(grid), dim3(threads), 0, stream, a, 0);
-    if (pull) hipLaunchKernelGGL(utile_pull_kernel, dim3(pgrid), dim3(kPullThreads), 0, stream, a, 0);
+    hipLaunchKernelGGL(push, dim3(grid), dim3(threads), 0, stream, a, 0);
+    if (pull) hipLaunchKernelGGL(pullk, dim3(pgrid), dim3(kPullThreads), 0, stream, a, 0);
     ktimer_end(tk, stream, 1);
   }
   return hip_check(hipGetLastError(), "hop-count tile step launches");

@@ -152,3 +152,16 @@ def test_umsssp_source_out_of_range_is_reported(dawn):
         announce("umsssp bad source", bad)
         D, info = _umsssp(dawn, csr, np.array([0, bad, 3], np.int32))
         assert info["converged"] == -1
+
+
+def test_umsssp_eight_segments(dawn):
+    """k = 500 in one 512-column tile: mask rows of 8 words (16-byte loads)."""
+    g = graphgen.rmat(11, 16, 29, weights="u32")
+    csr = dawn.Csr.from_graph(g)
+    tg = dawn.tgraph(csr)
+    srcs = graphgen.pick_sources(g, 500, 12)
+    for tune in (dict(tile_pull=0, tile_k=512), dict(tile_pull=1001, tile_k=512), dict(tile_k=512)):
+        announce("umsssp k=500", tune)
+        D, info = _umsssp(dawn, csr, srcs, tg, **tune)
+        _assert_levels(g, srcs, D, (0, 127, 128, 383, 448, 499), f"k500 {tune}")
+        assert info["converged"] == 1
