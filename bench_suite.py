@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Measurements of the workloads other than bench.py's headline one.
 
-    python bench_suite.py [--only c1,c2,c3,c4b,c5,mu] [--out results.jsonl]
+    python bench_suite.py [--only c1,c2,c3,c4b,c5,hop,mu] [--out results.jsonl]
 
 c1   plain SSSP latency: directed ER n=1000 m=8000, uint32 weights [1,100],
      source 0; per-call latency percentiles (host-observed, with a device
@@ -17,6 +17,11 @@ c4b  64 uneven ER graphs (n = 10^U(4,6), m = 8n, fp32 lognormal), one source
 c5   serving: Poisson arrivals over 32 resident R-MAT graphs (scales 14 + i%9
      capped at --c5-max-scale, edge factors 8/16/32, half uint32 half fp32
      lognormal); p50/p99 latency and completed queries/s per offered rate.
+hop  hop counts (every weight 1, the unweighted case): the C4a graph (R-MAT
+     scale 20, edge factor 16) with its 256 sources as one hop-count tile with
+     the reverse graph resident; ms per call, GTEPS (reachable edges per
+     second, mu = 1), sources/s, two columns checked against BFS, and the
+     weighted tile on the same graph and sources for comparison.
 mu   the validation experiment of Section 4.2 on synthetic graphs: the same
      topology with fp32 weights all 1.0 and uniform on [0,2]; per graph, the
      share of distance updates beyond the first per reached vertex
@@ -271,6 +276,49 @@ def c5(args, dawn, torch, np):
     return recs
 
 
+def hop(args, dawn, torch, np):
+    import oracle
+    from graphgen import workloads
+    g, srcs = workloads.rmat20_tile()
+    csr = dawn.Csr.from_graph(g)
+    tg = dawn.tgraph(csr)
+    k = len(srcs)
+    src_t = torch.as_tensor(srcs, dtype=torch.int32, device="cuda")
+    out = torch.empty((k, g.n), dtype=torch.uint32, device="cuda")
+    ws = dawn.workspace(dawn.umsssp_workspace_bytes(g.n, g.m, k))
+    info = dawn.info_tensor()
+    dawn.umsssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg)
+    torch.cuda.synchronize()
+    ok = True
+    for j in (0, k - 1):
+        lv = oracle.bfs(g, int(srcs[j]))
+        ref = np.where(lv >= 0, lv, -1).astype(np.int64).astype(np.uint32)
+        ok &= bool(np.array_equal(out[j].cpu().numpy(), ref))
+    ts = []
+    for _ in range(args.hop_reps):
+        t0 = time.perf_counter()
+        dawn.umsssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    i = dawn.read_info(info)
+    t = float(np.median(ts))
+    wout = torch.empty((k, g.n), dtype=torch.uint32, device="cuda")
+    wws = dawn.workspace(dawn.msssp_workspace_bytes(g.n, g.m, k))
+    dawn.msssp(csr, src_t, out=wout, ws=wws, tgraph=tg)
+    torch.cuda.synchronize()
+    wts = []
+    for _ in range(args.hop_reps):
+        t0 = time.perf_counter()
+        dawn.msssp(csr, src_t, out=wout, ws=wws, tgraph=tg)
+        torch.cuda.synchronize()
+        wts.append(time.perf_counter() - t0)
+    # mu = 1: the edges scanned are exactly the reachable edges of the sources
+    return {"config": "hop_rmat20_ef16_k256", "n": g.n, "m": g.m, "k": k,
+            "ms_per_call": t * 1e3, "sources_per_s": k / t, "gteps": i["edges_scanned"] / t / 1e9,
+            "steps": i["steps"], "bfs_exact_cols_0_last": ok,
+            "weighted_tile_ms_same_sources": float(np.median(wts)) * 1e3}
+
+
 def mu(args, dawn, torch, np):
     import graphgen
     graphs = [("rmat18_ef16", lambda wk: graphgen.rmat(18, 16, 180, weights=wk)),
@@ -317,7 +365,7 @@ def mu(args, dawn, torch, np):
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
-    ap.add_argument("--only", default="c1,c2,c3,c4b,c5")
+    ap.add_argument("--only", default="c1,c2,c3,c4b,c5,hop")
     ap.add_argument("--out", default=None)
     ap.add_argument("--c1-reps", type=int, default=1000)
     ap.add_argument("--c2-scale", type=int, default=22)
@@ -333,6 +381,7 @@ def main() -> int:
     ap.add_argument("--c5-steps-per-tick", type=int, default=4)
     ap.add_argument("--c5-rates", default="0.1,0.25,0.5,0.7,0.8,0.9,1.0,1.2")
     ap.add_argument("--mu-sources", type=int, default=8)
+    ap.add_argument("--hop-reps", type=int, default=5)
     args = ap.parse_args()
     args.c5_rates = [float(x) for x in args.c5_rates.split(",")]
     import numpy as np
@@ -342,7 +391,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     dawn.load()
     for name in args.only.split(","):
-        fn = {"c1": c1, "c2": c2, "c3": c3, "c4b": c4b, "c5": c5, "mu": mu}[name]
+        fn = {"c1": c1, "c2": c2, "c3": c3, "c4b": c4b, "c5": c5, "hop": hop, "mu": mu}[name]
         log(f"== {name}")
         t = time.perf_counter()
         recs = fn(args, dawn, torch, np)

@@ -79,8 +79,8 @@ def _p(a: np.ndarray, t):
 class Graph:
     """Directed graph in CSR form (int32 rowptr/colidx) with per-edge weights.
 
-    ``wtype`` is ``"u32"`` (uint32 weights) or ``"f32"`` (float32 weights, all
-    finite, sign bit clear).
+    ``wtype`` is ``"u32"`` (uint32 weights), ``"f32"`` (float32 weights, all
+    finite, sign bit clear) or ``"i32"`` (int32 weights of either sign).
     """
     n: int
     rowptr: np.ndarray
@@ -188,7 +188,7 @@ def from_edges(n: int, src, dst, w, wtype: str | None = None, name: str = "custo
     w = np.asarray(w)
     if wtype is None:
         wtype = "f32" if np.issubdtype(w.dtype, np.floating) else "u32"
-    w = w.astype(np.float32 if wtype == "f32" else np.uint32)
+    w = w.astype({"f32": np.float32, "u32": np.uint32, "i32": np.int32}[wtype])
     order = np.lexsort((dst, src)) if src.size else np.zeros(0, dtype=np.int64)
     rowptr = np.zeros(n + 1, dtype=np.int64)
     if src.size:
@@ -252,6 +252,21 @@ def grid(rows: int, cols: int, del_frac: float, seed: int, weights: str = "f32un
     w, wt = make_weights(int(k), weights, seed * 7919 + 1 if wseed is None else wseed)
     return Graph(n, rowptr, colidx, w, wt, f"grid_{rows}x{cols}",
                  {"kind": "grid", "seed": seed, "weights": weights, "deleted_pairs": ndel})
+
+
+def potential_shift(g: Graph, pmax: int, seed: int) -> tuple[Graph, np.ndarray]:
+    """Signed weights without negative cycles: w'(u,v) = w(u,v) + p(u) - p(v)
+    for a uint32 graph g and integer potentials p uniform in [0, pmax] (every
+    cycle keeps its weight, so none becomes negative; many edges do).
+    Returns the int32-weighted graph and p."""
+    assert g.wtype == "u32"
+    rng = np.random.default_rng(seed)
+    p = rng.integers(0, pmax + 1, size=g.n).astype(np.int64)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), g.outdeg())
+    w = g.w.astype(np.int64) + p[src] - p[g.colidx.astype(np.int64)]
+    assert w.min() >= -(1 << 31) and w.max() < (1 << 31)
+    return Graph(g.n, g.rowptr, g.colidx, np.ascontiguousarray(w.astype(np.int32)), "i32",
+                 g.name + f"_shift{pmax}"), p
 
 
 def pick_sources(g: Graph, k: int, seed: int) -> np.ndarray:

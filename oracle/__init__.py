@@ -76,6 +76,8 @@ def _L():
         L.oracle_fw_f64.argtypes = [_i32, _i32p, _i32p, _f32p, _f64p]
         L.oracle_brute.argtypes = [_i32, _i32p, _i32p, _vp, _i32, _i32, _u64p, _f64p, _i32p]
         L.oracle_brute.restype = _i32
+        L.oracle_bellman_ford_i32.argtypes = [_i32, _i32p, _i32p, _i32p, _i32, _i64p]
+        L.oracle_bellman_ford_i32.restype = _i32
         L.oracle_bfs.argtypes = [_i32, _i32p, _i32p, _i32, _i32p]
         L.oracle_bfs.restype = _i32
         L.oracle_check_u32.argtypes = [_i32, _i32p, _i32p, _u32p, _i32, _u32p, _i32p]
@@ -157,6 +159,18 @@ def brute(g, s: int, mode: str | None = None):
     if rc != 0:
         raise ValueError("brute force needs n <= 12")
     return (du if code == 0 else df), hops
+
+
+def bellman_ford(g, s: int):
+    """Signed int32 weights: (dist, ok).  dist: int64, INT64_MAX where
+    unreachable; shortest paths of the graph without the edges into s (the
+    source's distance is never lowered, as in Algorithm 2).  ok = False when
+    a negative cycle is reachable (dist is then meaningless)."""
+    assert g.wtype == "i32"
+    n, rp, ci = _csr(g)
+    d = np.empty(n, dtype=np.int64)
+    ok = _L().oracle_bellman_ford_i32(n, rp, ci, _p(g.w, _i32p), int(s), _p(d, _i64p))
+    return d, bool(ok)
 
 
 def bfs(g, s: int):

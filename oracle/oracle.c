@@ -29,6 +29,9 @@
  * reference (source is 0; no edge can be relaxed; every finite vertex has a
  * tight in-edge chain back to the source; INF exactly on unreachable vertices).
  *
+ * Signed int32 weights (negative edges allowed) have their own reference,
+ * Bellman-Ford with Algorithm 2's source guard (oracle_bellman_ford_i32).
+ *
  * The one restatement of the method itself (oracle_govm_*) follows
  * Algorithm 2's steps in the paper's order.  It is used for step counts and
  * work counters (mu), never as the distance reference.
@@ -325,6 +328,40 @@ int32_t oracle_brute(int32_t n, const int32_t* rowptr, const int32_t* colidx, co
 /* ------------------------------------------------------------------------- */
 /* Breadth-first levels (reachability; the unit-weight special case).          */
 /* ------------------------------------------------------------------------- */
+/*
+ * Signed int32 weights: Bellman-Ford (Section 2.2).  With negative weights a
+ * shortest-path distance exists when no cycle of negative weight is reachable.
+ * Algorithm 2 never lowers the source's own distance (its "index != source"
+ * test), so the fixed point it reaches is the shortest-path distance of the
+ * graph without the edges into s; that is what this computes: rounds over
+ * every edge whose target is not s, exact 64-bit sums, until a round changes
+ * nothing (return 1) or n rounds have all changed something, which only a
+ * reachable negative cycle allows (return 0, dist then meaningless).
+ * dist: int64, INT64_MAX = unreachable.
+ */
+int32_t oracle_bellman_ford_i32(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                                const int32_t* w, int32_t s, int64_t* dist) {
+  for (int32_t v = 0; v < n; v++) dist[v] = INT64_MAX;
+  dist[s] = 0;
+  for (int32_t round = 0; round < n; round++) {
+    int changed = 0;
+    for (int32_t u = 0; u < n; u++) {
+      if (dist[u] == INT64_MAX) continue;
+      for (int32_t e = rowptr[u]; e < rowptr[u + 1]; e++) {
+        const int32_t v = colidx[e];
+        if (v == s) continue;
+        const int64_t c = dist[u] + (int64_t)w[e];
+        if (c < dist[v]) {
+          dist[v] = c;
+          changed = 1;
+        }
+      }
+    }
+    if (!changed) return 1;
+  }
+  return 0;
+}
+
 int32_t oracle_bfs(int32_t n, const int32_t* rowptr, const int32_t* colidx, int32_t s,
                    int32_t* level) {
   int32_t* q = (int32_t*)malloc((size_t)n * sizeof(int32_t));

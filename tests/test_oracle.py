@@ -347,3 +347,63 @@ def test_f32_tolerance_gate():
     assert v in oracle.f32_tolerance_violations(g, s, bad)
     bad = d32.copy(); bad[v] = np.inf
     assert v in oracle.f32_tolerance_violations(g, s, bad)
+
+
+# --- signed int32 weights: Bellman-Ford with the source guard ---------------
+
+I64MAX = np.iinfo(np.int64).max
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_bellman_ford_equals_dijkstra_on_nonnegative_weights(seed):
+    g = graphgen.rmat(9, 8, 300 + seed, weights="u32")
+    gi = graphgen.from_edges(g.n, np.repeat(np.arange(g.n), g.outdeg()), g.colidx,
+                             g.w.astype(np.int64), "i32")
+    for s in graphgen.pick_sources(g, 3, seed):
+        d, ok = oracle.bellman_ford(gi, int(s))
+        ref, _ = oracle.sssp(g, int(s), "u32")
+        assert ok
+        assert np.array_equal(np.where(d == I64MAX, 0xFFFFFFFF, d), ref.astype(np.int64))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_bellman_ford_potential_shift_identity(seed):
+    """w'(u,v) = w(u,v) + p(u) - p(v) keeps every cycle's weight, so the
+    shortest paths are those of w and d'(v) = d(v) + p(s) - p(v)."""
+    g = graphgen.er(300, 2400, 400 + seed, weights="u32", wlo=1, whi=50)
+    gs, p = graphgen.potential_shift(g, 500, seed)
+    assert (gs.w < 0).mean() > 0.2
+    for s in graphgen.pick_sources(g, 3, seed):
+        d, ok = oracle.bellman_ford(gs, int(s))
+        ref, _ = oracle.sssp(g, int(s), "u32")
+        assert ok
+        reach = ref != 0xFFFFFFFF
+        assert np.array_equal(d == I64MAX, ~reach)
+        assert np.array_equal(d[reach], ref[reach].astype(np.int64) + p[s] - p[reach])
+
+
+def _g(n, edges):
+    e = np.array(edges, dtype=np.int64).reshape(-1, 3)
+    return graphgen.from_edges(n, e[:, 0], e[:, 1], e[:, 2], "i32")
+
+
+def test_bellman_ford_worked_examples():
+    # 0->1 (4), 0->2 (5), 2->1 (-3), 1->3 (2), 3->2 (1): the cycle 2-1-3 weighs 0
+    g = _g(4, [(0, 1, 4), (0, 2, 5), (2, 1, -3), (1, 3, 2), (3, 2, 1)])
+    d, ok = oracle.bellman_ford(g, 0)
+    assert ok and d.tolist() == [0, 2, 5, 4]
+    # the same cycle at weight -1 is reachable: no shortest paths
+    g = _g(4, [(0, 1, 4), (0, 2, 5), (2, 1, -3), (1, 3, 2), (3, 2, 0)])
+    assert not oracle.bellman_ford(g, 0)[1]
+    # a negative cycle that the source cannot reach changes nothing
+    g = _g(4, [(0, 1, 3), (2, 3, -5), (3, 2, 1)])
+    d, ok = oracle.bellman_ford(g, 0)
+    assert ok and d.tolist() == [0, 3, I64MAX, I64MAX]
+    # a negative cycle through the source only: its edge back into the source
+    # is never relaxed (the source keeps 0), so the distances exist
+    g = _g(2, [(0, 1, -2), (1, 0, 1)])
+    d, ok = oracle.bellman_ford(g, 0)
+    assert ok and d.tolist() == [0, -2]
+    # from the other end the guard drops 0->1 instead
+    d1, ok1 = oracle.bellman_ford(g, 1)
+    assert ok1 and d1.tolist() == [1, 0]
