@@ -27,8 +27,20 @@
  *   path of total weight >= 2^32-1 reads as unreachable), or DAWN_W_F32 =
  *   float32, finite with the sign bit clear (no negatives, no -0.0, no NaN).
  *   fp32 sums are IEEE round-to-nearest-even, no flush to zero.
- * - Distances: uint32 (INF = 0xFFFFFFFF) or float32 (INF = +inf), matching
- *   the weight type.
+ *   DAWN_W_I32 = int32 of either sign (single-source calls only: dawn_sssp,
+ *   dawn_sssp_ws; every other call returns DAWN_E_UNSUPPORTED).  The paper
+ *   claims negative weights without giving the mechanism; here it is the
+ *   same GOVM iteration on int32 sums, ordered through keys (the int32 with
+ *   its sign bit flipped, so the unsigned atomicMin orders them), with
+ *   Algorithm 2's guard: the source's own distance is never lowered.  Result:
+ *   the shortest-path distances of the graph without the edges into the
+ *   source.  A reachable negative cycle keeps the iteration going to the
+ *   n-step cap: info.converged = 0, distances meaningless (Bellman-Ford's
+ *   criterion).  Finite distances must lie strictly between INT32_MIN and
+ *   INT32_MAX: a sum at or above INT32_MAX reads as unreachable, a sum at or
+ *   below INT32_MIN also makes the run report converged = 0.
+ * - Distances: uint32 (INF = 0xFFFFFFFF), float32 (INF = +inf) or int32
+ *   (INF = INT32_MAX), matching the weight type.
  * - Pointers named *_dev are DEVICE pointers (hipMalloc'd or torch CUDA
  *   tensors) owned by the caller.  The library never frees them and keeps no
  *   pointer after the call's stream work completes, except tile and batch
@@ -64,7 +76,7 @@ typedef enum {
   DAWN_E_HIP = 4          /* a HIP runtime call failed (allocation, launch) */
 } dawn_status;
 
-typedef enum { DAWN_W_U32 = 0, DAWN_W_F32 = 1 } dawn_wtype;
+typedef enum { DAWN_W_U32 = 0, DAWN_W_F32 = 1, DAWN_W_I32 = 2 } dawn_wtype;
 
 /* Device-written run summary (optional output of the *_ws calls).  Counters
  * follow the paper's cost model (Section 3.4: T = mu(s) * E_wcc(s)):

@@ -22,7 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdawn.so")
 
-W_U32, W_F32 = 0, 1
+W_U32, W_F32, W_I32 = 0, 1, 2
 TILE_K_MAX = 512
 
 _STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "workspace too small",
@@ -153,12 +153,12 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def wtype_code(wtype: str) -> int:
-    return {"u32": W_U32, "f32": W_F32}[wtype]
+    return {"u32": W_U32, "f32": W_F32, "i32": W_I32}[wtype]
 
 
 def dist_dtype(wtype: str):
     torch = _torch()
-    return torch.uint32 if wtype == "u32" else torch.float32
+    return {"u32": torch.uint32, "f32": torch.float32, "i32": torch.int32}[wtype]
 
 
 # ---------------------------------------------------------------------------
@@ -170,7 +170,7 @@ class Csr:
     """A CSR graph resident in device memory (torch tensors)."""
     rowptr: object   # int32 [n+1]
     colidx: object   # int32 [m]
-    w: object        # uint32 or float32 [m]
+    w: object        # uint32, float32 or int32 [m]
     n: int
     m: int
     wtype: str
@@ -183,7 +183,7 @@ class Csr:
         w = np.ascontiguousarray(w)
         if wtype is None:
             wtype = "f32" if np.issubdtype(w.dtype, np.floating) else "u32"
-        w = w.astype(np.float32 if wtype == "f32" else np.uint32, copy=False)
+        w = w.astype({"f32": np.float32, "u32": np.uint32, "i32": np.int32}[wtype], copy=False)
         n = int(rowptr.shape[0]) - 1
         m = int(colidx.shape[0])
         # keep at least one element so every pointer is valid even when m == 0

@@ -71,14 +71,18 @@ static bool tuning_ok(const Tuning& t) {
 }
 
 static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
-                               dawn_wtype wt, int32_t n, int32_t m, bool need_w = true) {
+                               dawn_wtype wt, int32_t n, int32_t m, bool need_w = true,
+                               bool allow_i32 = false) {
   if (n < 1) return set_error(DAWN_E_INVALID, "n must be >= 1 (got %d)", n);
   if (n == INT32_MAX) return set_error(DAWN_E_INVALID, "n too large");
   if (m < 0) return set_error(DAWN_E_INVALID, "m must be >= 0 (got %d)", m);
   if (!rowptr) return set_error(DAWN_E_INVALID, "rowptr is null");
   if (m > 0 && !colidx) return set_error(DAWN_E_INVALID, "colidx is null");
   if (m > 0 && need_w && !w) return set_error(DAWN_E_INVALID, "weights are null");
-  if (wt != DAWN_W_U32 && wt != DAWN_W_F32) return set_error(DAWN_E_INVALID, "unknown wtype");
+  if (wt != DAWN_W_U32 && wt != DAWN_W_F32 && wt != DAWN_W_I32)
+    return set_error(DAWN_E_INVALID, "unknown wtype");
+  if (wt == DAWN_W_I32 && !allow_i32)
+    return set_error(DAWN_E_UNSUPPORTED, "int32 weights: single-source calls only");
   if (!tuning_ok(g_tuning)) return set_error(DAWN_E_INVALID, "tuning out of range");
   return DAWN_OK;
 }
@@ -287,7 +291,7 @@ extern "C" dawn_status dawn_sssp_ws(const int32_t* rowptr, const int32_t* colidx
                                     const void* weights, dawn_wtype wt, int32_t n, int32_t m,
                                     int32_t source, void* dist_out, void* ws, size_t ws_bytes,
                                     dawn_run_info* info, hipStream_t stream) {
-  dawn_status st = check_graph(rowptr, colidx, weights, wt, n, m);
+  dawn_status st = check_graph(rowptr, colidx, weights, wt, n, m, true, true);
   if (st != DAWN_OK) return st;
   if (source < 0 || source >= n) return set_error(DAWN_E_INVALID, "source %d out of range", source);
   if (!dist_out) return set_error(DAWN_E_INVALID, "dist_out is null");
@@ -298,14 +302,14 @@ extern "C" dawn_status dawn_sssp_ws(const int32_t* rowptr, const int32_t* colidx
     return set_error(DAWN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, ss_layout(n, m).total);
   SsSeeds seeds;
   seeds.source = source;
-  return ss_run(rowptr, colidx, weights, wt == DAWN_W_F32, n, m, seeds, true, dist_out, ws, info,
-                stream, false);
+  return ss_run(rowptr, colidx, weights, (int)wt, n, m, seeds, true, dist_out, ws, info, stream,
+                false);
 }
 
 extern "C" dawn_status dawn_sssp(const int32_t* rowptr, const int32_t* colidx, const void* weights,
                                  dawn_wtype wt, int32_t n, int32_t m, int32_t source,
                                  void* dist_out, hipStream_t stream) {
-  dawn_status st = check_graph(rowptr, colidx, weights, wt, n, m);
+  dawn_status st = check_graph(rowptr, colidx, weights, wt, n, m, true, true);
   if (st != DAWN_OK) return st;
   if (source < 0 || source >= n) return set_error(DAWN_E_INVALID, "source %d out of range", source);
   if (!dist_out) return set_error(DAWN_E_INVALID, "dist_out is null");
@@ -578,6 +582,7 @@ extern "C" dawn_status dawn_batch_create(dawn_batch** out, int32_t count,
                                          const int32_t* ms, dawn_wtype wt, hipStream_t stream) {
   if (!out || count < 1 || !rowptrs || !colidxs || !weights || !ns || !ms)
     return set_error(DAWN_E_INVALID, "bad batch arguments");
+  if (wt == DAWN_W_I32) return set_error(DAWN_E_UNSUPPORTED, "int32 weights: single-source calls only");
   if (wt != DAWN_W_U32 && wt != DAWN_W_F32) return set_error(DAWN_E_INVALID, "unknown wtype");
   *out = nullptr;
   dawn_batch* b = new dawn_batch();
@@ -655,7 +660,7 @@ static dawn_status batch_enqueue(dawn_batch* b, const int32_t* sources, void* di
   seeds.voff_dev = b->voff;
   seeds.count = b->count;
   seeds.source = 0;
-  return ss_run(b->rowptr, b->colidx, b->w, b->wt == DAWN_W_F32, (int32_t)b->total_n,
+  return ss_run(b->rowptr, b->colidx, b->w, (int)b->wt, (int32_t)b->total_n,
                 (int32_t)b->total_m, seeds, false, dist_out, b->ws, info, stream, capture);
 }
 

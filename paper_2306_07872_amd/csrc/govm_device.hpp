@@ -37,6 +37,7 @@ struct alignas(256) SsCtl {
   uint32_t blocks_done;       // last-block detection of step launches
   uint32_t overflow;          // a queue capacity was exceeded (cannot happen on valid input)
   uint32_t bar_base;          // value of `bar` when the next persistent launch starts
+  uint32_t negfloor;          // int32 weights: a path sum fell to or below INT32_MIN
   unsigned long long fe, es, im;  // frontier rows, edges scanned, improvements
 };
 
@@ -76,6 +77,39 @@ __device__ __forceinline__ uint32_t relax_add(uint32_t d, uint32_t w) {
   } else {
     const uint32_t s = d + w;
     return s < d ? kInfU32 : s;  // saturate
+  }
+}
+
+// Weight modes of the single-source path.  Distances are kept as uint32 keys
+// that order like the values they stand for: the uint32 value; the fp32 bit
+// pattern (non-negative floats order like their bits); or, for int32 weights
+// of either sign, the int32 value with its sign bit flipped.
+constexpr int kWU32 = 0, kWF32 = 1, kWI32 = 2;
+
+template <int WT>
+__device__ __forceinline__ constexpr uint32_t inf_key() {
+  return WT == kWF32 ? 0x7F800000u : 0xFFFFFFFFu;  // int32: the key of INT32_MAX
+}
+
+template <int WT>
+__device__ __forceinline__ constexpr uint32_t zero_key() {
+  return WT == kWI32 ? 0x80000000u : 0u;
+}
+
+// d (+) w on keys.  uint32 and fp32 as relax_add.  int32: exact sum; a sum at
+// or above INT32_MAX reads as INF (as uint32 sums saturate), a sum at or
+// below INT32_MIN becomes key 0, which the caller reports (it cannot be a
+// distance: finite distances lie strictly between the two).
+template <int WT>
+__device__ __forceinline__ uint32_t relax_key(uint32_t d, uint32_t w) {
+  if constexpr (WT == kWI32) {
+    if (d == 0xFFFFFFFFu) return d;
+    const int64_t s = (int64_t)(int32_t)(d ^ 0x80000000u) + (int64_t)(int32_t)w;
+    if (s >= (int64_t)INT32_MAX) return 0xFFFFFFFFu;
+    if (s <= (int64_t)INT32_MIN) return 0u;
+    return (uint32_t)(int32_t)s ^ 0x80000000u;
+  } else {
+    return relax_add<WT == kWF32>(d, w);
   }
 }
 

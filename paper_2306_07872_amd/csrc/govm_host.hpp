@@ -69,7 +69,7 @@ struct SsSeeds {
 
 // Enqueue a full single-source (or many-seed) GOVM run on `stream`.
 // capture=true: never use a cooperative launch (HIP graph capture).
-dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, bool f32,
+dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, int wt,
                    int32_t n, int32_t m, const SsSeeds& seeds, bool guard_source, void* dist,
                    void* ws, dawn_run_info* info, hipStream_t stream, bool capture);
 

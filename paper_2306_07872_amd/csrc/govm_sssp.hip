@@ -36,12 +36,12 @@ namespace dawn {
 // ---------------------------------------------------------------------------
 // init
 // ---------------------------------------------------------------------------
-template <bool F32>
+template <int WT>
 __global__ void ss_fill_kernel(uint32_t* dist, int64_t n, uint32_t* bm0, uint32_t* bm1,
                                int64_t nwords, SsCtl* ctl) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = tid; i < n; i += stride) dist[i] = inf_bits<F32>();
+  for (int64_t i = tid; i < n; i += stride) dist[i] = inf_key<WT>();
   for (int64_t i = tid; i < nwords; i += stride) { bm0[i] = 0; bm1[i] = 0; }
   if (blockIdx.x == 0) {
     uint32_t* c = reinterpret_cast<uint32_t*>(ctl);
@@ -72,7 +72,7 @@ __global__ void ss_validate_kernel(const int32_t* rowptr, const int32_t* colidx,
 }
 
 // Put the seeds in step 0's delta: alpha[s] = 0, beta bit set, row queued.
-template <bool F32>
+template <int WT>
 __global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* voff,
                                int32_t count, int32_t single) {
   SsCtl* C = A.ctl;
@@ -80,7 +80,7 @@ __global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* 
   for (int j = threadIdx.x; j < count; j += blockDim.x) {
     int64_t s = sources ? (int64_t)sources[j] : (int64_t)single;
     if (voff) s += voff[j];
-    A.dist[s] = 0u;
+    A.dist[s] = zero_key<WT>();
     const uint32_t bit = 1u << (s & 31);
     const uint32_t old = atomicOr(&A.bm[0][s >> 5], bit);
     if (old & bit) continue;  // duplicate seed
@@ -104,7 +104,19 @@ __global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* 
   }
 }
 
-template <bool F32>
+// int32 weights: keys back to int32 values (INF -> INT32_MAX), and a path sum
+// that left the int32 range makes the run count as not converged.
+__global__ void ss_decode_i32_kernel(uint32_t* dist, int64_t n, const SsCtl* C,
+                                     dawn_run_info* info) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dist[i] ^= 0x80000000u;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && info && ld_agent(&C->negfloor) &&
+      info->converged == 1)
+    info->converged = 0;
+}
+
+template <int WT>
 __global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int32_t conv = ld_agent_i(&C->converged);
@@ -211,7 +223,7 @@ __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U]
 
 // Relax U edges per lane: all column/weight loads, then all target-distance
 // loads, then the atomic mins of the lanes whose candidate is smaller.
-template <bool F32, int U>
+template <int WT, int U>
 __device__ __forceinline__ void ss_relax_n(const SsArgs& A, const int32_t (&e)[U],
                                            const bool (&valid)[U], const uint32_t (&du)[U],
                                            bool (&imp)[U], int32_t (&v)[U]) {
@@ -222,7 +234,9 @@ __device__ __forceinline__ void ss_relax_n(const SsArgs& A, const int32_t (&e)[U
     cand[i] = 0u;
     if (valid[i]) {
       v[i] = A.colidx[e[i]];
-      cand[i] = relax_add<F32>(du[i], A.w[e[i]]);
+      cand[i] = relax_key<WT>(du[i], A.w[e[i]]);
+      if constexpr (WT == kWI32)
+        if (cand[i] == 0u) atomicOr(&A.ctl->negfloor, 1u);  // sum left the int32 range
     }
   }
   uint32_t cur[U];
@@ -235,7 +249,7 @@ __device__ __forceinline__ void ss_relax_n(const SsArgs& A, const int32_t (&e)[U
   }
 }
 
-template <bool F32>
+template <int WT>
 __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
                         SsShared& sh) {
   const int cur = step & 1, nxt = cur ^ 1;
@@ -277,7 +291,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
         e[j] = start + k;
         d[j] = du;
       }
-      ss_relax_n<F32, kUnroll>(A, e, ok, d, imp, v);
+      ss_relax_n<WT, kUnroll>(A, e, ok, d, imp, v);
       ss_enqueue<kUnroll>(A, imp, v, nxt, rn, acc, sh);
     }
   }
@@ -302,7 +316,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
         ok[j] = e[j] < end;
         d[j] = du;
       }
-      ss_relax_n<F32, kUnroll>(A, e, ok, d, imp, v);
+      ss_relax_n<WT, kUnroll>(A, e, ok, d, imp, v);
       ss_enqueue<kUnroll>(A, imp, v, nxt, rn, acc, sh);
     }
   }
@@ -347,7 +361,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
         e[j] = l_base[owner] + k;
         d[j] = (uint32_t)l_du[owner];
       }
-      ss_relax_n<F32, kUnrollLane>(A, e, ok, d, imp, v);
+      ss_relax_n<WT, kUnrollLane>(A, e, ok, d, imp, v);
       ss_enqueue<kUnrollLane>(A, imp, v, nxt, rn, acc, sh);
     }
     wave_lds_sync();
@@ -382,7 +396,7 @@ __device__ __forceinline__ void ss_zero_rotation(SsCtl* C, uint32_t step) {
 
 // All steps in one launch; a grid barrier separates the steps.  The grid must
 // be co-resident (its size comes from the occupancy query, halved).
-template <bool F32>
+template <int WT>
 __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
   __shared__ SsShared sh;
   SsCtl* C = A.ctl;
@@ -394,7 +408,7 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
   int32_t status = 1;
   for (;;) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
-    ss_step<F32>(A, step, blockIdx.x, gridDim.x, acc, sh);
+    ss_step<WT>(A, step, blockIdx.x, gridDim.x, acc, sh);
     if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       break;
@@ -414,7 +428,7 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
 }
 
 // One step per launch; the last block to finish advances the step.
-template <bool F32>
+template <int WT>
 __global__ void __launch_bounds__(1024) ss_step_kernel(SsArgs A) {
   __shared__ SsShared sh;
   SsCtl* C = A.ctl;
@@ -422,7 +436,7 @@ __global__ void __launch_bounds__(1024) ss_step_kernel(SsArgs A) {
   const uint32_t step = ld_agent(&C->step);
   if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
   Acc acc;
-  ss_step<F32>(A, step, blockIdx.x, gridDim.x, acc, sh);
+  ss_step<WT>(A, step, blockIdx.x, gridDim.x, acc, sh);
   flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
   if (last_block_done(&C->blocks_done)) {
     st_agent(&C->blocks_done, 0u);
@@ -457,7 +471,7 @@ struct SsSmallShared {
   uint32_t cnt_next, upd;
 };
 
-template <bool F32>
+template <int WT>
 __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t* sources,
                                                         const int64_t* voff, int32_t count,
                                                         int32_t single, int32_t check_valid,
@@ -472,7 +486,7 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
   if (check_valid && ld_agent(&C->done)) {
     status = -1;
   } else {
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) A.dist[i] = inf_bits<F32>();
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) A.dist[i] = inf_key<WT>();
     for (int64_t i = threadIdx.x; i < nwords; i += blockDim.x) {
       A.bm[0][i] = 0u;
       A.bm[1][i] = 0u;
@@ -480,6 +494,7 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
     if (threadIdx.x == 0) {
       sh.cnt_next = 0u;
       sh.upd = 0u;
+      atomicExch(&C->negfloor, 0u);  // (an atomic, as the later reports are)
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
@@ -488,7 +503,7 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
     for (int j = threadIdx.x; j < count; j += blockDim.x) {
       int64_t s = sources ? (int64_t)sources[j] : (int64_t)single;
       if (voff) s += voff[j];
-      st_agent(&A.dist[s], 0u);
+      st_agent(&A.dist[s], zero_key<WT>());
       const uint32_t bit = 1u << (s & 31);
       if (atomicOr(&A.bm[0][s >> 5], bit) & bit) continue;
       st_agent_i(&A.qlane[0][atomicAdd(&sh.cnt_next, 1u)], (int32_t)s);
@@ -539,7 +554,7 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
             e[j] = l_base[owner] + k;
             d[j] = (uint32_t)l_du[owner];
           }
-          ss_relax_n<F32, kUnrollLane>(A, e, ok, d, imp, v);
+          ss_relax_n<WT, kUnrollLane>(A, e, ok, d, imp, v);
 #pragma unroll
           for (int j = 0; j < kUnrollLane; j++) {
             bool newv = false;
@@ -623,7 +638,7 @@ struct SsTinyShared {
   uint32_t cnt_next, upd;
 };
 
-template <bool F32>
+template <int WT>
 __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* sources,
                                                        const int64_t* voff, int32_t count,
                                                        int32_t single, int32_t check_valid,
@@ -638,7 +653,7 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
   if (check_valid && ld_agent(&C->done)) {
     status = -1;
   } else {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) sh.dist[i] = inf_bits<F32>();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sh.dist[i] = inf_key<WT>();
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
       sh.bm[0][i] = 0u;
       sh.bm[1][i] = 0u;
@@ -646,12 +661,14 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
     if (threadIdx.x == 0) {
       sh.cnt_next = 0u;
       sh.upd = 0u;
+      atomicExch(&C->negfloor, 0u);  // (an atomic, as the later reports are)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
     __syncthreads();
     for (int j = threadIdx.x; j < count; j += blockDim.x) {
       int64_t s = sources ? (int64_t)sources[j] : (int64_t)single;
       if (voff) s += voff[j];
-      sh.dist[s] = 0u;
+      sh.dist[s] = zero_key<WT>();
       const uint32_t bit = 1u << (s & 31);
       if (atomicOr(&sh.bm[0][s >> 5], bit) & bit) continue;
       sh.q[0][atomicAdd(&sh.cnt_next, 1u)] = (uint16_t)s;
@@ -704,7 +721,9 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
             if (ok[j]) {
               const int32_t e = l_base[owner] + k;
               v[j] = A.colidx[e];
-              cand[j] = relax_add<F32>((uint32_t)l_du[owner], A.w[e]);
+              cand[j] = relax_key<WT>((uint32_t)l_du[owner], A.w[e]);
+              if constexpr (WT == kWI32)
+                if (cand[j] == 0u) atomicOr(&A.ctl->negfloor, 1u);  // sum left the int32 range
             }
           }
 #pragma unroll
@@ -807,10 +826,10 @@ static int persistent_grid(K kernel, int threads, int* per_cu_out = nullptr) {
 
 void ss_persistent_occupancy(int threads, int* per_cu, int* grid) {
   if (threads <= 0) threads = 1024;
-  *grid = persistent_grid(ss_persistent_kernel<false>, threads, per_cu);
+  *grid = persistent_grid(ss_persistent_kernel<kWU32>, threads, per_cu);
 }
 
-template <bool F32>
+template <int WT>
 static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_t* colidx,
                             const SsSeeds& seeds, const SsLayout& L, dawn_run_info* info,
                             hipStream_t stream, bool capture) {
@@ -825,32 +844,35 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
   if (T.mode == 0 && (int64_t)A.m <= (int64_t)T.small_m) {
     // one workgroup, one launch (after the optional device validation)
     if (T.validate) {
-      hipLaunchKernelGGL(ss_fill_kernel<F32>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
+      hipLaunchKernelGGL(ss_fill_kernel<WT>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
                          (int64_t)A.n, A.bm[0], A.bm[1], L.nwords, A.ctl);
       const int vb = (int)std::min<int64_t>(4096, ((int64_t)A.m + 255) / 256 + 1);
       hipLaunchKernelGGL(ss_validate_kernel, dim3(vb), dim3(256), 0, stream, rowptr, colidx, A.w,
-                         A.n, A.m, (int32_t)F32, &A.ctl->done, &A.ctl->converged);
+                         A.n, A.m, (int32_t)(WT == kWF32), &A.ctl->done, &A.ctl->converged);
     }
     void* tk = capture ? nullptr : ktimer_begin(stream);
     if (A.n <= kTinyN)
-      hipLaunchKernelGGL(ss_tiny_kernel<F32>, dim3(1), dim3(threads), 0, stream, A,
+      hipLaunchKernelGGL(ss_tiny_kernel<WT>, dim3(1), dim3(threads), 0, stream, A,
                          seeds.sources_dev, seeds.voff_dev, seeds.count, seeds.source,
                          (int32_t)(T.validate != 0), info);
     else
-      hipLaunchKernelGGL(ss_small_kernel<F32>, dim3(1), dim3(threads), 0, stream, A,
+      hipLaunchKernelGGL(ss_small_kernel<WT>, dim3(1), dim3(threads), 0, stream, A,
                          seeds.sources_dev, seeds.voff_dev, seeds.count, seeds.source,
                          (int32_t)(T.validate != 0), info);
     ktimer_end(tk, stream, 1);
+    if constexpr (WT == kWI32)
+      hipLaunchKernelGGL(ss_decode_i32_kernel, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
+                         (int64_t)A.n, A.ctl, info);
     return hip_check(hipGetLastError(), "small-graph launch");
   }
-  hipLaunchKernelGGL(ss_fill_kernel<F32>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
+  hipLaunchKernelGGL(ss_fill_kernel<WT>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
                      (int64_t)A.n, A.bm[0], A.bm[1], L.nwords, A.ctl);
   if (T.validate) {
     const int vb = (int)std::min<int64_t>(4096, ((int64_t)A.m + 255) / 256 + 1);
     hipLaunchKernelGGL(ss_validate_kernel, dim3(vb), dim3(256), 0, stream, rowptr, colidx, A.w,
-                       A.n, A.m, (int32_t)F32, &A.ctl->done, &A.ctl->converged);
+                       A.n, A.m, (int32_t)(WT == kWF32), &A.ctl->done, &A.ctl->converged);
   }
-  hipLaunchKernelGGL(ss_seed_kernel<F32>, dim3(1), dim3(256), 0, stream, A, seeds.sources_dev,
+  hipLaunchKernelGGL(ss_seed_kernel<WT>, dim3(1), dim3(256), 0, stream, A, seeds.sources_dev,
                      seeds.voff_dev, seeds.count, seeds.source);
   dawn_status st = hip_check(hipGetLastError(), "init launch");
   if (st != DAWN_OK) return st;
@@ -878,7 +900,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
       const int chunk = (int)std::min<int64_t>(T.host_check, cap - launched);
       void* tk = ktimer_begin(stream);
       for (int s = 0; s < chunk; s++)
-        hipLaunchKernelGGL(ss_step_kernel<F32>, dim3(grid), dim3(threads), 0, stream, A);
+        hipLaunchKernelGGL(ss_step_kernel<WT>, dim3(grid), dim3(threads), 0, stream, A);
       ktimer_end(tk, stream, chunk);
       launched += chunk;
       hipMemcpyAsync(done.p, &A.ctl->done, 4, hipMemcpyDeviceToHost, stream);
@@ -890,17 +912,17 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
     if (st != DAWN_OK) return st;
   }
   if (mode == 2 || (mode == 3 && !finished)) {
-    int grid = persistent_grid(ss_persistent_kernel<F32>, threads);
+    int grid = persistent_grid(ss_persistent_kernel<WT>, threads);
     if (T.grid > 0 && T.grid < grid) grid = T.grid;
     SsArgs a = A;
     void* args[] = {&a};
     hipError_t e;
     void* tk = capture ? nullptr : ktimer_begin(stream);
     if (!capture && di.coop && T.coop) {
-      e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&ss_persistent_kernel<F32>),
+      e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&ss_persistent_kernel<WT>),
                                      dim3(grid), dim3(threads), args, 0, stream);
     } else {
-      hipLaunchKernelGGL(ss_persistent_kernel<F32>, dim3(grid), dim3(threads), 0, stream, a);
+      hipLaunchKernelGGL(ss_persistent_kernel<WT>, dim3(grid), dim3(threads), 0, stream, a);
       e = hipGetLastError();
     }
     ktimer_end(tk, stream, 1);
@@ -908,13 +930,18 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
     if (st != DAWN_OK) return st;
   }
   if (info) {
-    hipLaunchKernelGGL(ss_finalize_kernel<F32>, dim3(1), dim3(64), 0, stream, A.ctl, info);
+    hipLaunchKernelGGL(ss_finalize_kernel<WT>, dim3(1), dim3(64), 0, stream, A.ctl, info);
     st = hip_check(hipGetLastError(), "finalize launch");
+  }
+  if constexpr (WT == kWI32) {
+    hipLaunchKernelGGL(ss_decode_i32_kernel, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
+                       (int64_t)A.n, A.ctl, info);
+    st = hip_check(hipGetLastError(), "decode launch");
   }
   return st;
 }
 
-dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, bool f32,
+dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, int wt,
                    int32_t n, int32_t m, const SsSeeds& seeds, bool guard_source, void* dist,
                    void* ws, dawn_run_info* info, hipStream_t stream, bool capture) {
   const Tuning& T = tuning();
@@ -940,8 +967,9 @@ dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.cap_v = L.cap_v;
   A.cap_wg = L.cap_wg;
   A.ctl = reinterpret_cast<SsCtl*>(base + L.ctl);
-  if (f32) return ss_run_t<true>(A, rowptr, colidx, seeds, L, info, stream, capture);
-  return ss_run_t<false>(A, rowptr, colidx, seeds, L, info, stream, capture);
+  if (wt == kWF32) return ss_run_t<kWF32>(A, rowptr, colidx, seeds, L, info, stream, capture);
+  if (wt == kWI32) return ss_run_t<kWI32>(A, rowptr, colidx, seeds, L, info, stream, capture);
+  return ss_run_t<kWU32>(A, rowptr, colidx, seeds, L, info, stream, capture);
 }
 
 }  // namespace dawn

@@ -120,3 +120,17 @@ def test_hop_count_entry_point_host_checks(lib):
     assert lib.dawn_umsssp_ws(fake, fake, 100, 1000, ctypes.c_void_p(0x2010), fake, 4, fake, ws,
                               need, null, null) == 1
     assert b"aligned" in lib.dawn_last_error()
+
+
+def test_int32_weights_are_single_source_only(lib):
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    # multi-source, all pairs, reverse-graph runs and tiles: unsupported (2)
+    assert lib.dawn_msssp(fake, fake, fake, 2, 5, 3, fake, 4, fake, null) == 2
+    assert lib.dawn_msssp_ws(fake, fake, fake, 2, 5, 3, fake, 4, fake, ws, 1 << 30, null,
+                             null) == 2
+    assert lib.dawn_apsp(fake, fake, fake, 2, 5, 3, fake, null) == 2
+    assert b"single-source" in lib.dawn_last_error()
+    # an unknown weight type stays invalid (1)
+    assert lib.dawn_sssp(fake, fake, fake, 3, 5, 3, 0, fake, null) == 1
