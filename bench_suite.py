@@ -244,9 +244,12 @@ def c5(args, dawn, torch, np):
             out.append((gi, int(pool[min(int(u[2 * j + 1] * len(pool)), len(pool) - 1)])))
         return out
 
+    if args.c5_pull_src is not None:
+        dawn.set_tuning(tile_pull_src=args.c5_pull_src)
+
     def new_server():
         srv = serve.Server(tile_k=args.c5_tile_k, steps_per_tick=args.c5_steps_per_tick,
-                           max_tiles_per_graph=2)
+                           max_tiles_per_graph=2, pull=not args.c5_no_pull)
         for i, c in enumerate(csrs):
             srv.add_graph(i, c)
         return srv
@@ -262,7 +265,7 @@ def c5(args, dawn, torch, np):
     cap = len(qs) / (time.perf_counter() - t0)
     closed = serve.percentiles([q.latency for q in qs])
     recs = [{"config": "c5_serving_closed_loop", "graphs": len(graphs), "queries": len(qs),
-             "capacity_qps": cap, **closed}]
+             "pull": not args.c5_no_pull, "capacity_qps": cap, **closed}]
     log(f"c5 closed-loop capacity {cap:.1f} queries/s")
     for frac in args.c5_rates:
         rate = frac * cap
@@ -378,6 +381,9 @@ def main() -> int:
     ap.add_argument("--c5-max-scale", type=int, default=22)
     ap.add_argument("--c5-queries", type=int, default=2000)
     ap.add_argument("--c5-tile-k", type=int, default=64)
+    ap.add_argument("--c5-no-pull", action="store_true", help="serve with push steps only")
+    ap.add_argument("--c5-pull-src", type=int, default=None,
+                    help="tuning tile_pull_src while serving (default: the library's)")
     ap.add_argument("--c5-steps-per-tick", type=int, default=4)
     ap.add_argument("--c5-rates", default="0.1,0.25,0.5,0.7,0.8,0.9,1.0,1.2")
     ap.add_argument("--mu-sources", type=int, default=8)

@@ -166,9 +166,13 @@ typedef struct {
                            sources are relaxed one edge per lane, 4 bytes per source,
                            instead of 16 lanes per 64-source segment; 0..512, default 8 */
   int32_t tile_pull;    /* with a reverse graph (dawn_msssp_tg_ws), a tile step whose
-                           frontier rows hold at least tile_pull / 1000 of the m edges is
-                           run as a pull step over the in-edges of every vertex; 0 = every
-                           step, 1001 = never; default 400 */
+                           frontier rows hold at least tile_pull / 1000 of the m edges, and
+                           whose frontier edges carry on average at least tile_pull_src
+                           active sources, is run as a pull step over the in-edges of every
+                           vertex; 0 = every step, 1001 = never; default 400 */
+  int32_t tile_pull_src; /* see tile_pull: a pull step reads a frontier in-neighbour's whole
+                           64-source segments, a push step only its active sources, so tiles
+                           holding few queries stay with push; 0..512, default 16 */
 } dawn_tuning;
 
 #define DAWN_TILE_K_MAX 512
@@ -331,6 +335,11 @@ dawn_status dawn_tile_admit(dawn_tile* t, int32_t col, int32_t source, hipStream
  * on the device once no column is active).  If done_bits_dev is non-NULL it
  * receives ceil(k/32) uint32 words (bit j of word j/32) with the bits of
  * admitted columns that have finished set. */
+/* Attach the reverse graph of the session's CSR (dawn_tgraph_build, with
+ * weights), or detach it with NULL: later runs take pull steps on dense
+ * frontiers (tuning field tile_pull), with identical results.  The caller
+ * keeps the buffer alive while it is attached. */
+dawn_status dawn_tile_set_tgraph(dawn_tile* t, const void* tgraph_dev);
 dawn_status dawn_tile_run(dawn_tile* t, int32_t max_steps, uint32_t* done_bits_dev,
                           hipStream_t stream);
 /* Copy column col (n distances) to dist_out_dev; valid once the column is done. */

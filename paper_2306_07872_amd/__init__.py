@@ -46,7 +46,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
                 ("t_lane", "t_wave", "t_chunk", "wg_threads", "grid", "mode", "host_check",
                  "tile_k", "tile_t_wave", "tile_t_chunk", "validate", "coop", "tile_t_group",
-                 "tile_skip", "small_m", "step_min_m", "tile_sparse", "tile_pull")]
+                 "tile_skip", "small_m", "step_min_m", "tile_sparse", "tile_pull",
+                 "tile_pull_src")]
 
 
 INFO_BYTES = ctypes.sizeof(RunInfo)
@@ -87,6 +88,7 @@ def load():
         "dawn_msssp_tg_ws": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp,
                               _vp], _i32),
         "dawn_umsssp_workspace_bytes": ([_i32, _i32, _i32], _sz),
+        "dawn_tile_set_tgraph": ([_vp, _vp], _i32),
         "dawn_umsssp_ws": ([_vp, _vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp, _vp], _i32),
         "dawn_batch_create": ([ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp),
                                ctypes.POINTER(_vp), ctypes.POINTER(_vp),
@@ -128,6 +130,7 @@ def exported_symbols() -> list[str]:
         "dawn_umsssp_workspace_bytes", "dawn_umsssp_ws", "dawn_batch_create", "dawn_batch_sizes", "dawn_batch_vertex_offset", "dawn_batch_run",
         "dawn_batch_capture", "dawn_batch_replay", "dawn_batch_destroy", "dawn_tile_bytes",
         "dawn_tile_create", "dawn_tile_admit", "dawn_tile_run", "dawn_tile_read",
+        "dawn_tile_set_tgraph",
         "dawn_tile_steps", "dawn_tile_evict", "dawn_tile_destroy", "dawn_kernel_timer",
         "dawn_kernel_time", "dawn_device_query"]
 
@@ -461,6 +464,12 @@ class Tile:
         torch = _torch()
         self.done_buf = torch.zeros((self.k + 31) // 32, dtype=torch.int32,
                                     device=csr.rowptr.device)
+
+    def set_tgraph(self, tgraph):
+        """Attach the reverse graph (``tgraph(csr)``) for pull steps, or None."""
+        self._tgraph = tgraph  # kept alive while attached
+        _check(load().dawn_tile_set_tgraph(self._h, _aligned(tgraph)[0] if tgraph is not None
+                                           else None))
 
     def admit(self, col: int, source: int, stream=None):
         _check(load().dawn_tile_admit(self._h, int(col), int(source), _stream(stream)))

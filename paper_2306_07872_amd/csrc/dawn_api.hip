@@ -67,7 +67,8 @@ static bool tuning_ok(const Tuning& t) {
          (t.coop == 0 || t.coop == 1) && t.tile_t_group >= 0 && t.tile_t_group <= 64 &&
          t.tile_t_group < t.tile_t_wave && (t.tile_skip == 0 || t.tile_skip == 1) &&
          t.small_m >= 0 && t.step_min_m >= 0 && t.tile_sparse >= 0 && t.tile_sparse <= 512 &&
-         t.tile_pull >= 0 && t.tile_pull <= 1001;
+         t.tile_pull >= 0 && t.tile_pull <= 1001 && t.tile_pull_src >= 0 &&
+         t.tile_pull_src <= 512;
 }
 
 static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
@@ -249,6 +250,7 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->step_min_m = t.step_min_m;
   out->tile_sparse = t.tile_sparse;
   out->tile_pull = t.tile_pull;
+  out->tile_pull_src = t.tile_pull_src;
   return DAWN_OK;
 }
 
@@ -273,6 +275,7 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.step_min_m = in->step_min_m;
     t.tile_sparse = in->tile_sparse;
     t.tile_pull = in->tile_pull;
+    t.tile_pull_src = in->tile_pull_src;
   }
   if (!tuning_ok(t)) return set_error(DAWN_E_INVALID, "tuning out of range");
   g_tuning = t;
@@ -359,6 +362,7 @@ static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, cons
   if (tgraph && g_tuning.tile_pull <= 1000) {
     A.T = tgraph_view(tgraph, n, m);
     A.pull_min = (long long)m * g_tuning.tile_pull / 1000;
+    A.pull_src = g_tuning.tile_pull_src;
   }
   // per-tile summary, inside the workspace (no allocation on this path)
   dawn_run_info* part = reinterpret_cast<dawn_run_info*>(static_cast<char*>(ws) + L.info);
@@ -727,6 +731,7 @@ struct dawn_tile {
   void* ws = nullptr;
   bool f32 = false;
   int32_t k = 0;
+  const void* tgraph = nullptr;  // reverse graph for pull steps, or null
 };
 
 extern "C" size_t dawn_tile_bytes(int32_t n, int32_t m, int32_t k) {
@@ -773,10 +778,24 @@ extern "C" dawn_status dawn_tile_run(dawn_tile* t, int32_t max_steps, uint32_t* 
                                      hipStream_t stream) {
   if (!t) return set_error(DAWN_E_INVALID, "null tile");
   if (max_steps < 1) return set_error(DAWN_E_INVALID, "max_steps must be >= 1");
-  dawn_status st = tile_steps(t->A, t->f32, false, max_steps, stream);
+  TileArgs a = t->A;
+  if (t->tgraph && g_tuning.tile_pull <= 1000) {
+    a.T = tgraph_view(t->tgraph, a.n, a.m);
+    a.pull_min = (long long)a.m * g_tuning.tile_pull / 1000;
+    a.pull_src = g_tuning.tile_pull_src;
+  }
+  dawn_status st = tile_steps(a, t->f32, false, max_steps, stream);
   if (st != DAWN_OK) return st;
   if (done_bits) st = tile_done_bits(t->A, t->k, done_bits, stream);
   return st;
+}
+
+extern "C" dawn_status dawn_tile_set_tgraph(dawn_tile* t, const void* tgraph) {
+  if (!t) return set_error(DAWN_E_INVALID, "null tile");
+  if ((reinterpret_cast<uintptr_t>(tgraph) & 255u) != 0)
+    return set_error(DAWN_E_INVALID, "reverse graph must be 256-byte aligned");
+  t->tgraph = tgraph;
+  return DAWN_OK;
 }
 
 extern "C" dawn_status dawn_tile_read(dawn_tile* t, int32_t col, void* dist_out,

@@ -49,6 +49,7 @@ struct alignas(256) CtrStripe {
   unsigned long long fe, es, im, sa, se;  // union rows, union edges, improvements,
                                           // per-source rows, per-source edges
   unsigned long long fedges[kRot];        // [step % 4]: out-edges of the step's frontier rows
+  unsigned long long fpairs[kRot];        // [step % 4]: their (edge, active source) pairs
 };
 
 struct alignas(256) TileCtl {
@@ -58,6 +59,7 @@ struct alignas(256) TileCtl {
   uint32_t step, done;
   int32_t converged;
   uint32_t bar, abort, blocks_done, overflow, bar_base;
+  uint32_t cstep;                      // the step whose compaction ran last
   CtrStripe ctr[kCtrStripes];           // statistics, summed over the stripes
   int32_t colsteps[kSegMax * 64];
 };
@@ -266,13 +268,14 @@ __device__ __forceinline__ bool last_block_done(uint32_t* blocks_done) {
 
 // Sum per-thread counters over the workgroup (wavefront sums, then LDS) and
 // add each total to its counter with one atomic (null pointer: not counted;
-// es2: a second counter that also takes the es total).
+// es2 / se2: second counters that also take the es / se totals).
 // One add per workgroup rather than per wavefront: device-scope atomics on one
 // address are serialised where they execute.  Every thread must call it.
 __device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* fe,
                                           unsigned long long* es, unsigned long long* im,
                                           unsigned long long* sa, unsigned long long* se,
-                                          unsigned long long* es2 = nullptr) {
+                                          unsigned long long* es2 = nullptr,
+                                          unsigned long long* se2 = nullptr) {
   __shared__ unsigned long long part[1024 / kWave][5];
   const unsigned long long v0 = wave_sum64(a.fe), v1 = wave_sum64(a.es), v2 = wave_sum64(a.im);
   const unsigned long long v3 = wave_sum64(a.sa), v4 = wave_sum64(a.se);
@@ -286,8 +289,8 @@ __device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* fe,
     part[w][4] = v4;
   }
   __syncthreads();
-  if (threadIdx.x < 6) {
-    const int c = threadIdx.x == 5 ? 1 : threadIdx.x;
+  if (threadIdx.x < 7) {
+    const int c = threadIdx.x == 5 ? 1 : threadIdx.x == 6 ? 4 : threadIdx.x;
     unsigned long long s = 0;
     for (int i = 0; i < nw; ++i) s += part[i][c];
     unsigned long long* dst = threadIdx.x == 0 ? fe
@@ -295,7 +298,8 @@ __device__ __forceinline__ void flush_acc(const Acc& a, unsigned long long* fe,
                               : threadIdx.x == 2 ? im
                               : threadIdx.x == 3 ? sa
                               : threadIdx.x == 4 ? se
-                                                 : es2;
+                              : threadIdx.x == 5 ? es2
+                                                 : se2;
     if (dst && s) atomicAdd(dst, s);
   }
 }
@@ -376,6 +380,7 @@ struct TileArgs {
   TileCtl* ctl;
   TGraph T;                   // reverse graph, or hdr == nullptr
   long long pull_min;         // pull steps when the frontier has >= this many out-edges; < 0: never
+  long long pull_src;         // ... and >= this many active sources per frontier edge on average
   unsigned long long* vis;    // hop-count tiles: reached (vertex, source) pairs [n][nseg]; else null
   // hop-count tiles: the distances as bit planes, plane b = bit b of the step
   // that reached each pair, [nplanes][n][nseg]; D is null there

@@ -29,6 +29,7 @@ struct Tuning {
   int32_t step_min_m = 1 << 25;
   int32_t tile_sparse = 8;
   int32_t tile_pull = 400;
+  int32_t tile_pull_src = 16;
 };
 
 Tuning& tuning();

@@ -122,7 +122,11 @@ __device__ __forceinline__ void tile_prologue(TileCtl* C, uint32_t step, int K) 
   // zero the counters of the next step and count this step for active columns
   const int rz = (step + 1) % kRot, rc = step % kRot;
   if (threadIdx.x < 4) st_agent(&C->cnt[rz][threadIdx.x], 0u);
-  if (threadIdx.x < kCtrStripes) st_agent64(&C->ctr[threadIdx.x].fedges[rz], 0ull);
+  if (threadIdx.x == 4) st_agent(&C->cstep, step);
+  if (threadIdx.x < kCtrStripes) {
+    st_agent64(&C->ctr[threadIdx.x].fedges[rz], 0ull);
+    st_agent64(&C->ctr[threadIdx.x].fpairs[rz], 0ull);
+  }
   if (threadIdx.x < kSegMax) st_agent64(&C->colact[rz][threadIdx.x], 0ull);
   for (int j = threadIdx.x; j < K; j += blockDim.x)
     if ((ld_agent64(&C->colact[rc][j >> 6]) >> (j & 63)) & 1ull)
@@ -733,16 +737,23 @@ __global__ void __launch_bounds__(1024) tile_compact_kernel(TileArgs A) {
   tile_compact<UW>(A, step, blockIdx.x, gridDim.x, acc, csh);
   // frontier rows and pairs, improvements, and the frontier's out-edges
   CtrStripe& S = C->ctr[blockIdx.x % kCtrStripes];
-  flush_acc(acc, &S.fe, &S.es, &S.im, &S.sa, &S.se, &S.fedges[step % kRot]);
+  flush_acc(acc, &S.fe, &S.es, &S.im, &S.sa, &S.se, &S.fedges[step % kRot], &S.fpairs[step % kRot]);
 }
 
-// A step is a pull step when the reverse graph is there and the frontier has
-// at least pull_min out-edges (counted by the compaction before both relaxation
-// kernels of the step run, so both take the same decision).
+// A step is a pull step when the reverse graph is there, the frontier has at
+// least pull_min out-edges and those carry at least pull_src active sources
+// each on average (a pull step reads whole segment rows; with few active
+// sources the push step reads far less).  Both counts come from the
+// compaction, before both relaxation kernels of the step run, so both take
+// the same decision.
 __device__ __forceinline__ bool tile_is_pull_step(const TileArgs& A, uint32_t step) {
   if (A.T.hdr == nullptr || A.pull_min < 0) return false;
   const size_t off = offsetof(CtrStripe, fedges) + (step % kRot) * sizeof(unsigned long long);
-  return ctr_sum(A.ctl->ctr, off) >= (unsigned long long)A.pull_min;
+  const unsigned long long fe = ctr_sum(A.ctl->ctr, off);
+  if (fe < (unsigned long long)A.pull_min) return false;
+  if (A.pull_src <= 0) return true;
+  const size_t offp = offsetof(CtrStripe, fpairs) + (step % kRot) * sizeof(unsigned long long);
+  return ctr_sum(A.ctl->ctr, offp) >= (unsigned long long)A.pull_src * fe;
 }
 
 // End of a step launch: the last workgroup advances the step and detects the end.
@@ -915,6 +926,9 @@ __global__ void __launch_bounds__(kPullThreads) tile_pull_kernel(TileArgs A, int
   TileCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
   const uint32_t step = ld_agent(&C->step);
+  // after a push step the push kernel has already advanced the step: the new
+  // one has no compaction yet
+  if (step != ld_agent(&C->cstep)) return;
   if (!tile_is_pull_step(A, step)) return;  // the push kernel runs this step
   const int qn = (step + 1) % 3, rn = (step + 1) % kRot;
   tile_clear_prev(A, step, blockIdx.x, gridDim.x);
@@ -1110,6 +1124,7 @@ __global__ void __launch_bounds__(kPullThreads) utile_pull_kernel(TileArgs A, in
   TileCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
   const uint32_t step = ld_agent(&C->step);
+  if (step != ld_agent(&C->cstep)) return;  // a push step ran (see tile_pull_kernel)
   if (!tile_is_pull_step(A, step)) return;  // the push kernel runs this step
   const int q = step % 3, qn = (step + 1) % 3, rn = (step + 1) % kRot;
   tile_clear_prev(A, step, blockIdx.x, gridDim.x);
@@ -1343,6 +1358,7 @@ TileArgs tile_args(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.sparse = T.tile_sparse;
   A.T = TGraph{};
   A.pull_min = -1;
+  A.pull_src = 0;
   for (int i = 0; i < 3; i++) {
     A.mk[i] = reinterpret_cast<unsigned long long*>(base + L.mk[i]);
     A.qgrp[i] = reinterpret_cast<int32_t*>(base + L.qgrp[i]);

@@ -38,7 +38,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Csr, Tile, dist_dtype, done_columns, tile_bytes
+from . import Csr, Tile, dist_dtype, done_columns, tgraph, tile_bytes
 
 
 @dataclass
@@ -65,7 +65,7 @@ class Query:
 class GpuTileExecutor:
     """One HIP tile session with its own stream, pinned host buffers and events."""
 
-    def __init__(self, csr: Csr, k: int, device="cuda"):
+    def __init__(self, csr: Csr, k: int, device="cuda", tgraph=None):
         import torch
         self.torch = torch
         self.csr = csr
@@ -73,6 +73,8 @@ class GpuTileExecutor:
         self.stream = torch.cuda.Stream(device=device)   # default priority
         with torch.cuda.stream(self.stream):
             self.tile = Tile(csr, k, stream=self.stream)
+        if tgraph is not None:
+            self.tile.set_tgraph(tgraph)
         self.done_host = torch.zeros((k + 31) // 32, dtype=torch.int32, pin_memory=True)
         self.nbytes = tile_bytes(csr.n, csr.m, k)
         self._run_event = None
@@ -153,14 +155,20 @@ class Server:
 
     def __init__(self, hbm_budget: int | None = None, tile_k: int = 64, steps_per_tick: int = 4,
                  max_tiles_per_graph: int = 4, tile_factory=None, clock=time.perf_counter,
-                 device="cuda"):
+                 device="cuda", pull: bool = True):
         self.graphs: dict[int, Csr] = {}
+        # pull steps need each graph's reverse graph, built when the graph is
+        # added and resident with it (like the CSR, outside the tile budget);
+        # only the HIP executor uses them
+        self.pull = pull and tile_factory is None
         self.tile_k = tile_k
         self.steps_per_tick = steps_per_tick
         self.max_tiles_per_graph = max_tiles_per_graph
         self.device = device
         self.clock = clock
-        self.tile_factory = tile_factory or (lambda csr, k: GpuTileExecutor(csr, k, device))
+        self.tile_factory = tile_factory or (
+            lambda csr, k: GpuTileExecutor(csr, k, device,
+                                           getattr(csr, "_tgraph", None) if self.pull else None))
         if hbm_budget is None:
             import torch
             free, _ = torch.cuda.mem_get_info()
@@ -177,6 +185,8 @@ class Server:
     # -- graphs and queries -------------------------------------------------
     def add_graph(self, gid: int, csr: Csr):
         self.graphs[gid] = csr
+        if self.pull:
+            tgraph(csr)
 
     def tile_cost(self, gid: int) -> int:
         c = self.graphs[gid]

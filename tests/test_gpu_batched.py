@@ -282,14 +282,16 @@ def test_full_size_tile_rmat20_sampled(dawn):
 # pull steps (reverse graph): same relaxations, so results are identical
 # ---------------------------------------------------------------------------
 PULL_TUNINGS = [
-    dict(tile_pull=0),                      # every step a pull step
-    dict(tile_pull=1001),                   # never
-    dict(),                                 # by frontier density
-    dict(tile_pull=0, tile_k=512),          # two 4-segment quads per target
-    dict(tile_pull=50, tile_t_wave=32, tile_t_chunk=64, tile_sparse=0, tile_t_group=0),
-    dict(tile_pull=0, tile_k=64),           # one segment: four in-edges at a time per wave
-    dict(tile_pull=0, tile_k=128),          # two segments: two in-edges at a time
-    dict(tile_pull=0, tile_k=192),          # three segments: one 16-lane group idle
+    dict(tile_pull=0, tile_pull_src=0),               # every step a pull step
+    dict(tile_pull=1001),                             # never
+    dict(),                                           # by frontier size and density
+    dict(tile_pull=0, tile_pull_src=0, tile_k=512),   # two 4-segment quads per target
+    dict(tile_pull=50, tile_pull_src=0, tile_t_wave=32, tile_t_chunk=64, tile_sparse=0,
+         tile_t_group=0),
+    dict(tile_pull=0, tile_pull_src=0, tile_k=64),    # one segment: four in-edges at a time
+    dict(tile_pull=0, tile_pull_src=0, tile_k=128),   # two segments: two in-edges at a time
+    dict(tile_pull=0, tile_pull_src=0, tile_k=192),   # three segments: one group idle
+    dict(tile_pull=0, tile_pull_src=64),              # only steps with many active sources
 ]
 
 
@@ -335,7 +337,7 @@ def test_msssp_pull_quads_of_four_and_one_segment(dawn, wk):
     tg = dawn.tgraph(csr)
     srcs = graphgen.pick_sources(g, 300, 9)
     announce("msssp pull k=300", wk)
-    D, info = _msssp_tg(dawn, csr, srcs, tg, tile_pull=0, tile_k=320)
+    D, info = _msssp_tg(dawn, csr, srcs, tg, tile_pull=0, tile_pull_src=0, tile_k=320)
     P, _ = _msssp(dawn, g, srcs, tile_k=320)
     assert np.array_equal(D.view(np.uint32), P.view(np.uint32))
     for j in (0, 255, 256, 299):
@@ -357,7 +359,7 @@ def test_msssp_pull_hub_target_with_many_chunks(dawn):
     tg = dawn.tgraph(csr)
     srcs = np.array([0, 5, 77777, 100000, 3], dtype=np.int32)
     announce("msssp pull star")
-    D, info = _msssp_tg(dawn, csr, srcs, tg, tile_pull=0)
+    D, info = _msssp_tg(dawn, csr, srcs, tg, tile_pull=0, tile_pull_src=0)
     for j, s in enumerate(srcs):
         assert_sssp_matches(g, int(s), D[j], tag=f"star pull source {s}")
 
@@ -368,6 +370,6 @@ def test_msssp_pull_grid_f32_many_steps(dawn):
     tg = dawn.tgraph(csr)
     srcs = graphgen.pick_sources(g, 70, 1)
     announce("msssp pull grid f32")
-    D, info = _msssp_tg(dawn, csr, srcs, tg, tile_pull=0)
+    D, info = _msssp_tg(dawn, csr, srcs, tg, tile_pull=0, tile_pull_src=0)
     for j in (0, 33, 69):
         assert_sssp_matches(g, int(srcs[j]), D[j], tag=f"pull grid col {j}")

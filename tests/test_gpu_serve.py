@@ -10,19 +10,31 @@ from gpu_helpers import announce, assert_sssp_matches, to_np
 pytestmark = pytest.mark.gpu
 
 
-def test_server_mix_equals_alone(dawn):
+@pytest.mark.parametrize("pull", [False, True])
+def test_server_mix_equals_alone(dawn, pull):
+    """pull=True: the tiles take pull steps (from 5 % of the edges in the
+    frontier) while queries join and leave them."""
+    prev = dawn.set_tuning(tile_pull=50, tile_pull_src=0) if pull else None
+    try:
+        _mix_equals_alone(dawn, pull)
+    finally:
+        if prev is not None:
+            dawn.set_tuning(**prev)
+
+
+def _mix_equals_alone(dawn, pull):
     import torch
     from paper_2306_07872_amd import serve
     gs = [graphgen.rmat(12, 8, 40, weights="u32"),
           graphgen.rmat(13, 16, 41, weights="f32lognormal"),
           graphgen.grid(48, 40, 0.01, 42, weights="f32unit")]
     csrs = [dawn.Csr.from_graph(g) for g in gs]
-    srv = serve.Server(tile_k=64, steps_per_tick=3, max_tiles_per_graph=2)
+    srv = serve.Server(tile_k=64, steps_per_tick=3, max_tiles_per_graph=2, pull=pull)
     for i, c in enumerate(csrs):
         srv.add_graph(i, c)
     rng = np.random.default_rng(7)
     qs = []
-    announce("server mix: 3 graphs, 90 queries")
+    announce("server mix: 3 graphs, 90 queries, pull", pull)
     for t in range(90):
         gi = int(rng.integers(0, 3))
         src = int(graphgen.pick_sources(gs[gi], 1, 1000 + t)[0])

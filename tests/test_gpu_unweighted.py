@@ -38,9 +38,9 @@ def _assert_levels(g, srcs, D, cols, tag):
                                f"first v={bad[0]} gpu={got[bad[0]]} ref={ref[bad[0]]}")
 
 
-PULL = [dict(tile_pull=1001), dict(tile_pull=0), dict(), dict(tile_pull=0, tile_k=64),
-        dict(tile_pull=0, tile_k=128), dict(tile_pull=0, tile_k=192),
-        dict(tile_pull=50, tile_t_wave=32, tile_t_chunk=64, tile_t_group=0)]
+PULL = [dict(tile_pull=1001), dict(tile_pull=0, tile_pull_src=0), dict(), dict(tile_pull=0, tile_pull_src=0, tile_k=64),
+        dict(tile_pull=0, tile_pull_src=0, tile_k=128), dict(tile_pull=0, tile_pull_src=0, tile_k=192),
+        dict(tile_pull=50, tile_pull_src=0, tile_t_wave=32, tile_t_chunk=64, tile_t_group=0)]
 
 
 @pytest.mark.parametrize("ti", range(len(PULL)))
@@ -75,7 +75,7 @@ def test_umsssp_counters_are_the_bfs_ones(dawn):
     csr = dawn.Csr.from_graph(g)
     tg = dawn.tgraph(csr)
     srcs = graphgen.pick_sources(g, 40, 2)
-    for tune in (dict(tile_pull=1001), dict(tile_pull=0), dict()):
+    for tune in (dict(tile_pull=1001), dict(tile_pull=0, tile_pull_src=0), dict()):
         announce("umsssp counters", tune)
         D, info = _umsssp(dawn, csr, srcs, tg, **tune)
         _assert_levels(g, srcs, D, range(len(srcs)), f"counters {tune}")
@@ -92,7 +92,7 @@ def test_umsssp_five_segments(dawn):
     csr = dawn.Csr.from_graph(g)
     tg = dawn.tgraph(csr)
     srcs = graphgen.pick_sources(g, 300, 9)
-    for tune in (dict(tile_pull=0, tile_k=320), dict(tile_pull=1001, tile_k=320)):
+    for tune in (dict(tile_pull=0, tile_pull_src=0, tile_k=320), dict(tile_pull=1001, tile_k=320)):
         announce("umsssp k=300", tune)
         D, info = _umsssp(dawn, csr, srcs, tg, **tune)
         _assert_levels(g, srcs, D, (0, 63, 64, 255, 256, 299), f"k300 {tune}")
@@ -110,7 +110,7 @@ def test_umsssp_hub_target_with_many_chunks(dawn):
     tg = dawn.tgraph(csr)
     srcs = np.array([0, 5, 77777, 100000, 3], dtype=np.int32)
     announce("umsssp star")
-    for tune in (dict(tile_pull=0), dict()):
+    for tune in (dict(tile_pull=0, tile_pull_src=0), dict()):
         D, info = _umsssp(dawn, csr, srcs, tg, **tune)
         _assert_levels(g, srcs, D, range(len(srcs)), f"star {tune}")
 
@@ -121,7 +121,7 @@ def test_umsssp_grid_many_steps(dawn):
     tg = dawn.tgraph(csr)
     srcs = graphgen.pick_sources(g, 70, 1)
     announce("umsssp grid")
-    D, info = _umsssp(dawn, csr, srcs, tg, tile_pull=100)
+    D, info = _umsssp(dawn, csr, srcs, tg, tile_pull=100, tile_pull_src=0)
     _assert_levels(g, srcs, D, (0, 33, 69), "grid")
     assert info["converged"] == 1
 
@@ -160,7 +160,7 @@ def test_umsssp_eight_segments(dawn):
     csr = dawn.Csr.from_graph(g)
     tg = dawn.tgraph(csr)
     srcs = graphgen.pick_sources(g, 500, 12)
-    for tune in (dict(tile_pull=0, tile_k=512), dict(tile_pull=1001, tile_k=512), dict(tile_k=512)):
+    for tune in (dict(tile_pull=0, tile_pull_src=0, tile_k=512), dict(tile_pull=1001, tile_k=512), dict(tile_k=512)):
         announce("umsssp k=500", tune)
         D, info = _umsssp(dawn, csr, srcs, tg, **tune)
         _assert_levels(g, srcs, D, (0, 127, 128, 383, 448, 499), f"k500 {tune}")
