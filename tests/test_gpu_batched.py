@@ -265,17 +265,19 @@ def test_full_size_tile_rmat20_sampled(dawn):
     import torch
     g, srcs = workloads.rmat20_tile()
     csr = dawn.Csr.from_graph(g)
-    announce("rmat20 tile k=256 full")
-    info = dawn.info_tensor()
-    D = dawn.msssp(csr, srcs, info=info)
-    torch.cuda.synchronize()
-    inf = dawn.read_info(info)
-    assert inf["converged"] == 1
-    for j in (0, 255):
-        assert_sssp_matches(g, int(srcs[j]), to_np(D[j]), tag=f"rmat20 col {j}")
-    for j in (17, 128):
-        rc, v = oracle.check(g, int(srcs[j]), to_np(D[j]))
-        assert rc == 0, f"col {j}: invariant V{rc} at {v}"
+    tg = dawn.tgraph(csr)
+    for use_tg in (True, False):  # the benchmark's configuration, then push steps only
+        announce("rmat20 tile k=256 full, reverse graph", use_tg)
+        info = dawn.info_tensor()
+        D = dawn.msssp(csr, srcs, info=info, tgraph=tg if use_tg else None)
+        torch.cuda.synchronize()
+        inf = dawn.read_info(info)
+        assert inf["converged"] == 1
+        for j in (0, 255):
+            assert_sssp_matches(g, int(srcs[j]), to_np(D[j]), tag=f"rmat20 col {j}")
+        for j in (17, 128):
+            rc, v = oracle.check(g, int(srcs[j]), to_np(D[j]))
+            assert rc == 0, f"col {j}: invariant V{rc} at {v}"
 
 
 # ---------------------------------------------------------------------------

@@ -165,3 +165,16 @@ def test_umsssp_eight_segments(dawn):
         D, info = _umsssp(dawn, csr, srcs, tg, **tune)
         _assert_levels(g, srcs, D, (0, 127, 128, 383, 448, 499), f"k500 {tune}")
         assert info["converged"] == 1
+
+
+@pytest.mark.slow
+def test_umsssp_full_size_rmat20_sampled(dawn):
+    """The benchmark-suite configuration (R-MAT scale 20, 256 sources, reverse
+    graph resident): sampled columns against BFS element by element."""
+    from graphgen import workloads
+    g, srcs = workloads.rmat20_tile()
+    csr = dawn.Csr.from_graph(g)
+    announce("umsssp rmat20 k=256 full")
+    D, info = _umsssp(dawn, csr, srcs, dawn.tgraph(csr))
+    assert info["converged"] == 1
+    _assert_levels(g, srcs, D, (0, 77, 255), "rmat20")
