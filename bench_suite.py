@@ -388,6 +388,8 @@ def main() -> int:
     ap.add_argument("--c5-rates", default="0.1,0.25,0.5,0.7,0.8,0.9,1.0,1.2")
     ap.add_argument("--mu-sources", type=int, default=8)
     ap.add_argument("--hop-reps", type=int, default=5)
+    ap.add_argument("--tuning", default=None,
+                    help="JSON object of tuning fields applied before every section")
     args = ap.parse_args()
     args.c5_rates = [float(x) for x in args.c5_rates.split(",")]
     import numpy as np
@@ -396,6 +398,8 @@ def main() -> int:
     import paper_2306_07872_amd as dawn
     torch.cuda.set_device(0)
     dawn.load()
+    if args.tuning:
+        dawn.set_tuning(**json.loads(args.tuning))
     for name in args.only.split(","):
         fn = {"c1": c1, "c2": c2, "c3": c3, "c4b": c4b, "c5": c5, "hop": hop, "mu": mu}[name]
         log(f"== {name}")

@@ -47,7 +47,7 @@ class Tuning(ctypes.Structure):
                 ("t_lane", "t_wave", "t_chunk", "wg_threads", "grid", "mode", "host_check",
                  "tile_k", "tile_t_wave", "tile_t_chunk", "validate", "coop", "tile_t_group",
                  "tile_skip", "small_m", "step_min_m", "tile_sparse", "tile_pull",
-                 "tile_pull_src")]
+                 "tile_pull_src", "ss_skip")]
 
 
 INFO_BYTES = ctypes.sizeof(RunInfo)

@@ -68,7 +68,7 @@ static bool tuning_ok(const Tuning& t) {
          t.tile_t_group < t.tile_t_wave && (t.tile_skip == 0 || t.tile_skip == 1) &&
          t.small_m >= 0 && t.step_min_m >= 0 && t.tile_sparse >= 0 && t.tile_sparse <= 512 &&
          t.tile_pull >= 0 && t.tile_pull <= 1001 && t.tile_pull_src >= 0 &&
-         t.tile_pull_src <= 512;
+         t.tile_pull_src <= 512 && (t.ss_skip == 0 || t.ss_skip == 1);
 }
 
 static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
@@ -251,6 +251,7 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->tile_sparse = t.tile_sparse;
   out->tile_pull = t.tile_pull;
   out->tile_pull_src = t.tile_pull_src;
+  out->ss_skip = t.ss_skip;
   return DAWN_OK;
 }
 
@@ -276,6 +277,7 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.tile_sparse = in->tile_sparse;
     t.tile_pull = in->tile_pull;
     t.tile_pull_src = in->tile_pull_src;
+    t.ss_skip = in->ss_skip;
   }
   if (!tuning_ok(t)) return set_error(DAWN_E_INVALID, "tuning out of range");
   g_tuning = t;

@@ -30,6 +30,7 @@ struct Tuning {
   int32_t tile_sparse = 8;
   int32_t tile_pull = 400;
   int32_t tile_pull_src = 16;
+  int32_t ss_skip = 1;
 };
 
 Tuning& tuning();

@@ -171,8 +171,8 @@ __device__ __forceinline__ void block_push(bool pred, int32_t v, int32_t* sq, ui
 // degree tier.  Reached by the whole wavefront.
 template <int U>
 __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U],
-                                           const int32_t (&v)[U], int nxt, int rn, Acc& acc,
-                                           SsShared& sh) {
+                                           const int32_t (&v)[U], const uint32_t (&cand)[U],
+                                           int nxt, int rn, Acc& acc, SsShared& sh) {
   bool any = false;
 #pragma unroll
   for (int i = 0; i < U; i++) any |= imp[i];
@@ -184,11 +184,16 @@ __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U]
   for (int i = 0; i < U; i++) {
     newv[i] = false;
     if (imp[i]) {
-      acc.im += 1;
       const uint32_t bit = 1u << (v[i] & 31);
       newv[i] = (atomicOr(&A.bm[nxt][v[i] >> 5], bit) & bit) == 0u;
     }
   }
+#pragma unroll
+  for (int i = 0; i < U; i++)
+    if (imp[i]) atomicMin(&A.dist[v[i]], cand[i]);  // result unused: not waited for
+#pragma unroll
+  for (int i = 0; i < U; i++)
+    if (newv[i]) acc.im += 1;  // a vertex lowered in this step counts once
   int32_t start[U], deg[U];
 #pragma unroll
   for (int i = 0; i < U; i++) {
@@ -249,6 +254,43 @@ __device__ __forceinline__ void ss_relax_n(const SsArgs& A, const int32_t (&e)[U
   }
 }
 
+// Candidates and the plain-load pre-check only, for ss_enqueue: it issues the
+// next-frontier test-and-set first and the non-returning atomicMin after it,
+// so waiting for the test-and-set does not wait for the atomicMin too (gfx9's
+// vector-memory counter retires in order).  A candidate that passes the
+// pre-check but loses to a lower value written in the same step only sets a
+// bit that the writer of that value sets as well.
+template <int WT, int U>
+__device__ __forceinline__ void ss_relax_pre(const SsArgs& A, const int32_t (&e)[U],
+                                             const bool (&valid)[U], const uint32_t (&du)[U],
+                                             bool (&imp)[U], int32_t (&v)[U],
+                                             uint32_t (&cand)[U]) {
+#pragma unroll
+  for (int i = 0; i < U; i++) {
+    v[i] = 0;
+    cand[i] = 0u;
+    if (valid[i]) {
+      v[i] = A.colidx[e[i]];
+      cand[i] = relax_key<WT>(du[i], A.w[e[i]]);
+      if constexpr (WT == kWI32)
+        if (cand[i] == 0u) atomicOr(&A.ctl->negfloor, 1u);  // sum left the int32 range
+    }
+  }
+  uint32_t cur[U];
+#pragma unroll
+  for (int i = 0; i < U; i++) cur[i] = valid[i] ? A.dist[v[i]] : 0u;
+#pragma unroll
+  for (int i = 0; i < U; i++) imp[i] = valid[i] && cand[i] < cur[i] && v[i] != A.src;
+}
+
+// With skipping (tuning ss_skip): a frontier row whose distance another row
+// lowered again during this step is already marked for the next step, where
+// it is expanded with a value at least as low; expanding it now as well would
+// only repeat that work.  Its current-bitmap word is still cleared.
+__device__ __forceinline__ bool ss_skip_row(const SsArgs& A, int nxt, int32_t u) {
+  return A.skip && ((ld_agent(&A.bm[nxt][u >> 5]) >> (u & 31)) & 1u);
+}
+
 template <int WT>
 __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
                         SsShared& sh) {
@@ -270,8 +312,9 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
   // workgroup tier: one chunk of one row per workgroup
   for (uint32_t i = gb; i < ng; i += nb) {
     const int4 r = ld_queue4(&A.qwg[cur][i]);
-    const int32_t u = r.x, start = r.y, len = r.z;
+    const int32_t u = r.x, start = r.y;
     const uint32_t du = ld_agent(&A.dist[u]);
+    const int32_t len = ss_skip_row(A, nxt, u) ? 0 : r.z;
     if (threadIdx.x == 0) {
       acc.es += (unsigned long long)len;
       if (r.w) {
@@ -283,7 +326,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
     for (int32_t base = 0; base < len; base += stride * kUnroll) {
       int32_t e[kUnroll], v[kUnroll];
       bool ok[kUnroll], imp[kUnroll];
-      uint32_t d[kUnroll];
+      uint32_t d[kUnroll], cand[kUnroll];
 #pragma unroll
       for (int j = 0; j < kUnroll; j++) {
         const int32_t k = base + j * stride + (int32_t)threadIdx.x;
@@ -291,15 +334,16 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
         e[j] = start + k;
         d[j] = du;
       }
-      ss_relax_n<WT, kUnroll>(A, e, ok, d, imp, v);
-      ss_enqueue<kUnroll>(A, imp, v, nxt, rn, acc, sh);
+      ss_relax_pre<WT, kUnroll>(A, e, ok, d, imp, v, cand);
+      ss_enqueue<kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
     }
   }
 
   // wave tier: one wavefront per row
   for (uint32_t i = gw; i < nw; i += nwv) {
     const int32_t u = ld_queue(&A.qwave[cur][i]);
-    const int32_t start = A.rowptr[u], end = A.rowptr[u + 1];
+    const int32_t start = A.rowptr[u];
+    const int32_t end = ss_skip_row(A, nxt, u) ? start : A.rowptr[u + 1];
     const uint32_t du = ld_agent(&A.dist[u]);
     if (lane == 0) {
       A.bm[cur][u >> 5] = 0u;
@@ -309,15 +353,15 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
     for (int32_t base = start; base < end; base += kWave * kUnroll) {
       int32_t e[kUnroll], v[kUnroll];
       bool ok[kUnroll], imp[kUnroll];
-      uint32_t d[kUnroll];
+      uint32_t d[kUnroll], cand[kUnroll];
 #pragma unroll
       for (int j = 0; j < kUnroll; j++) {
         e[j] = base + j * kWave + lane;
         ok[j] = e[j] < end;
         d[j] = du;
       }
-      ss_relax_n<WT, kUnroll>(A, e, ok, d, imp, v);
-      ss_enqueue<kUnroll>(A, imp, v, nxt, rn, acc, sh);
+      ss_relax_pre<WT, kUnroll>(A, e, ok, d, imp, v, cand);
+      ss_enqueue<kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
     }
   }
 
@@ -334,7 +378,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
     if (has) {
       u = ld_queue(&A.qlane[cur][i]);
       start = A.rowptr[u];
-      deg = A.rowptr[u + 1] - start;
+      deg = ss_skip_row(A, nxt, u) ? 0 : A.rowptr[u + 1] - start;
       du = ld_agent(&A.dist[u]);
       A.bm[cur][u >> 5] = 0u;
       acc.fe += 1;
@@ -349,7 +393,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
     for (int base = 0; base < total; base += kWave * kUnrollLane) {
       int32_t e[kUnrollLane], v[kUnrollLane];
       bool ok[kUnrollLane], imp[kUnrollLane];
-      uint32_t d[kUnrollLane];
+      uint32_t d[kUnrollLane], cand[kUnrollLane];
 #pragma unroll
       for (int j = 0; j < kUnrollLane; j++) {
         const int k = base + j * kWave + lane;
@@ -361,8 +405,8 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
         e[j] = l_base[owner] + k;
         d[j] = (uint32_t)l_du[owner];
       }
-      ss_relax_n<WT, kUnrollLane>(A, e, ok, d, imp, v);
-      ss_enqueue<kUnrollLane>(A, imp, v, nxt, rn, acc, sh);
+      ss_relax_pre<WT, kUnrollLane>(A, e, ok, d, imp, v, cand);
+      ss_enqueue<kUnrollLane>(A, imp, v, cand, nxt, rn, acc, sh);
     }
     wave_lds_sync();
   }
@@ -956,6 +1000,7 @@ dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.m = m;
   A.src = guard_source ? seeds.source : -1;
   A.t_lane = T.t_lane;
+  A.skip = T.ss_skip;
   A.t_wave = T.t_wave;
   A.t_chunk = T.t_chunk;
   for (int i = 0; i < 2; i++) {

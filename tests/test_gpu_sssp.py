@@ -59,6 +59,8 @@ TUNINGS = [
     dict(step_min_m=0, host_check=2),         # step launches, then a persistent launch
     dict(step_min_m=0, host_check=1, wg_threads=1024, t_lane=2, t_wave=64, t_chunk=256),
     dict(step_min_m=0),
+    dict(ss_skip=0, small_m=0),                # every frontier row expanded in its step
+    dict(ss_skip=0, small_m=0, mode=1, t_lane=2, t_wave=64, t_chunk=256, host_check=3),
 ]
 
 
