@@ -86,10 +86,13 @@ typedef enum { DAWN_W_U32 = 0, DAWN_W_F32 = 1, DAWN_W_I32 = 2 } dawn_wtype;
  *                    the n-step cap; -1 = input validation failed on the
  *                    device; -2 = a persistent launch gave up waiting at a grid
  *                    barrier (the result is then incomplete);
- *   frontier_entries sum over steps of the rows expanded (changed in the
+ *   frontier_entries sum over steps of the frontier rows (changed in the
  *                    previous step and having out-edges);
- *   edges_scanned    sum over steps of the out-degrees of those rows;
- *   improvements     successful strict decreases of a distance.
+ *   edges_scanned    sum over steps of the out-degrees of the rows expanded
+ *                    (single source with ss_skip: a row lowered again within
+ *                    its step is expanded, and counted, in the next step only);
+ *   improvements     per step, the vertices whose distance the step lowered
+ *                    (two decreases of one vertex in one step count once).
  * For a batched call the counters are summed over its sources and `steps` is
  * the largest per-source step count; union_rows / union_edges count the rows
  * and edges the tile actually read (each serving every source active there);
