@@ -39,8 +39,13 @@
  *   criterion).  Finite distances must lie strictly between INT32_MIN and
  *   INT32_MAX: a sum at or above INT32_MAX reads as unreachable, a sum at or
  *   below INT32_MIN also makes the run report converged = 0.
+ *   DAWN_W_UNIT = every edge weight 1, weights_dev not read (may be NULL):
+ *   uint32 hop counts, the unweighted case (each vertex reached once, at its
+ *   level, so a level is stored without atomicMin); dawn_msssp / dawn_apsp
+ *   run the hop-count tiles of dawn_umsssp_ws; batches and tile sessions
+ *   return DAWN_E_UNSUPPORTED.
  * - Distances: uint32 (INF = 0xFFFFFFFF), float32 (INF = +inf) or int32
- *   (INF = INT32_MAX), matching the weight type.
+ *   (INF = INT32_MAX), matching the weight type (uint32 for unit weights).
  * - Pointers named *_dev are DEVICE pointers (hipMalloc'd or torch CUDA
  *   tensors) owned by the caller.  The library never frees them and keeps no
  *   pointer after the call's stream work completes, except tile and batch
@@ -76,7 +81,7 @@ typedef enum {
   DAWN_E_HIP = 4          /* a HIP runtime call failed (allocation, launch) */
 } dawn_status;
 
-typedef enum { DAWN_W_U32 = 0, DAWN_W_F32 = 1, DAWN_W_I32 = 2 } dawn_wtype;
+typedef enum { DAWN_W_U32 = 0, DAWN_W_F32 = 1, DAWN_W_I32 = 2, DAWN_W_UNIT = 3 } dawn_wtype;
 
 /* Device-written run summary (optional output of the *_ws calls).  Counters
  * follow the paper's cost model (Section 3.4: T = mu(s) * E_wcc(s)):

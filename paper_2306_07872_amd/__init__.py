@@ -22,7 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdawn.so")
 
-W_U32, W_F32, W_I32 = 0, 1, 2
+W_U32, W_F32, W_I32, W_UNIT = 0, 1, 2, 3
 TILE_K_MAX = 512
 
 _STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "workspace too small",
@@ -156,12 +156,13 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 def wtype_code(wtype: str) -> int:
-    return {"u32": W_U32, "f32": W_F32, "i32": W_I32}[wtype]
+    return {"u32": W_U32, "f32": W_F32, "i32": W_I32, "unit": W_UNIT}[wtype]
 
 
 def dist_dtype(wtype: str):
     torch = _torch()
-    return {"u32": torch.uint32, "f32": torch.float32, "i32": torch.int32}[wtype]
+    return {"u32": torch.uint32, "f32": torch.float32, "i32": torch.int32,
+            "unit": torch.uint32}[wtype]
 
 
 # ---------------------------------------------------------------------------
@@ -186,18 +187,23 @@ class Csr:
         w = np.ascontiguousarray(w)
         if wtype is None:
             wtype = "f32" if np.issubdtype(w.dtype, np.floating) else "u32"
-        w = w.astype({"f32": np.float32, "u32": np.uint32, "i32": np.int32}[wtype], copy=False)
+        # unit weights are never read: keep a one-word placeholder
+        if wtype == "unit":
+            w = np.zeros(1, np.uint32)
+        w = w.astype({"f32": np.float32, "u32": np.uint32, "i32": np.int32,
+                      "unit": np.uint32}[wtype], copy=False)
         n = int(rowptr.shape[0]) - 1
         m = int(colidx.shape[0])
         # keep at least one element so every pointer is valid even when m == 0
         ci = colidx if m else np.zeros(1, np.int32)
-        ww = w if m else np.zeros(1, w.dtype)
+        ww = w if (m and wtype != "unit") else np.zeros(1, w.dtype)
         return Csr(torch.from_numpy(rowptr).to(device), torch.from_numpy(ci).to(device),
                    torch.from_numpy(ww).to(device), n, m, wtype)
 
     @staticmethod
-    def from_graph(g, device="cuda") -> "Csr":
-        return Csr.from_arrays(g.rowptr, g.colidx, g.w, g.wtype, device)
+    def from_graph(g, device="cuda", wtype: str | None = None) -> "Csr":
+        """wtype overrides the graph's ("unit": hop counts, weights dropped)."""
+        return Csr.from_arrays(g.rowptr, g.colidx, g.w, wtype or g.wtype, device)
 
     @property
     def code(self) -> int:
@@ -305,7 +311,8 @@ def tgraph(csr: Csr, stream=None):
     scratch = workspace(int(L.dawn_tgraph_build_bytes(csr.n, csr.m)), dev)
     bp, bn = _aligned(buf)
     sp, sn = _aligned(scratch)
-    _check(L.dawn_tgraph_build(_ptr(csr.rowptr), _ptr(csr.colidx), _ptr(csr.w), csr.n, csr.m,
+    w = None if csr.wtype == "unit" else _ptr(csr.w)  # unit graphs have no weight array
+    _check(L.dawn_tgraph_build(_ptr(csr.rowptr), _ptr(csr.colidx), w, csr.n, csr.m,
                                bp, bn, sp, sn, _stream(stream)))
     _torch().cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     csr._tgraph = buf

@@ -79,9 +79,9 @@ static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, con
   if (m < 0) return set_error(DAWN_E_INVALID, "m must be >= 0 (got %d)", m);
   if (!rowptr) return set_error(DAWN_E_INVALID, "rowptr is null");
   if (m > 0 && !colidx) return set_error(DAWN_E_INVALID, "colidx is null");
-  if (m > 0 && need_w && !w) return set_error(DAWN_E_INVALID, "weights are null");
-  if (wt != DAWN_W_U32 && wt != DAWN_W_F32 && wt != DAWN_W_I32)
+  if (wt != DAWN_W_U32 && wt != DAWN_W_F32 && wt != DAWN_W_I32 && wt != DAWN_W_UNIT)
     return set_error(DAWN_E_INVALID, "unknown wtype");
+  if (m > 0 && need_w && wt != DAWN_W_UNIT && !w) return set_error(DAWN_E_INVALID, "weights are null");
   if (wt == DAWN_W_I32 && !allow_i32)
     return set_error(DAWN_E_UNSUPPORTED, "int32 weights: single-source calls only");
   if (!tuning_ok(g_tuning)) return set_error(DAWN_E_INVALID, "tuning out of range");
@@ -357,6 +357,7 @@ static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, cons
                               int32_t k, void* dist_out, void* ws, dawn_run_info* info,
                               hipStream_t stream, const void* tgraph = nullptr,
                               bool unweighted = false) {
+  unweighted = unweighted || wt == DAWN_W_UNIT;  // unit weights: the hop-count tiles
   const bool f32 = wt == DAWN_W_F32;
   const int32_t kt = std::min(k, g_tuning.tile_k);
   const TileLayout L = tile_layout(n, m, kt, unweighted);
@@ -589,6 +590,7 @@ extern "C" dawn_status dawn_batch_create(dawn_batch** out, int32_t count,
   if (!out || count < 1 || !rowptrs || !colidxs || !weights || !ns || !ms)
     return set_error(DAWN_E_INVALID, "bad batch arguments");
   if (wt == DAWN_W_I32) return set_error(DAWN_E_UNSUPPORTED, "int32 weights: single-source calls only");
+  if (wt == DAWN_W_UNIT) return set_error(DAWN_E_UNSUPPORTED, "unit weights: not in a batch");
   if (wt != DAWN_W_U32 && wt != DAWN_W_F32) return set_error(DAWN_E_INVALID, "unknown wtype");
   *out = nullptr;
   dawn_batch* b = new dawn_batch();
@@ -748,6 +750,7 @@ extern "C" dawn_status dawn_tile_create(dawn_tile** out, const int32_t* rowptr,
   *out = nullptr;
   dawn_status st = check_graph(rowptr, colidx, weights, wt, n, m);
   if (st != DAWN_OK) return st;
+  if (wt == DAWN_W_UNIT) return set_error(DAWN_E_UNSUPPORTED, "unit weights: not in a tile session");
   if (k < 1) return set_error(DAWN_E_INVALID, "k must be >= 1");
   if (k > DAWN_TILE_K_MAX) return set_error(DAWN_E_UNSUPPORTED, "k above %d", DAWN_TILE_K_MAX);
   dawn_tile* t = new dawn_tile();

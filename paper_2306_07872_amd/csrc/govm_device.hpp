@@ -86,7 +86,8 @@ __device__ __forceinline__ uint32_t relax_add(uint32_t d, uint32_t w) {
 // that order like the values they stand for: the uint32 value; the fp32 bit
 // pattern (non-negative floats order like their bits); or, for int32 weights
 // of either sign, the int32 value with its sign bit flipped.
-constexpr int kWU32 = 0, kWF32 = 1, kWI32 = 2;
+// kWUNIT: every weight 1 and not read (hop counts, uint32 keys).
+constexpr int kWU32 = 0, kWF32 = 1, kWI32 = 2, kWUNIT = 3;
 
 template <int WT>
 __device__ __forceinline__ constexpr uint32_t inf_key() {
@@ -104,7 +105,9 @@ __device__ __forceinline__ constexpr uint32_t zero_key() {
 // distance: finite distances lie strictly between the two).
 template <int WT>
 __device__ __forceinline__ uint32_t relax_key(uint32_t d, uint32_t w) {
-  if constexpr (WT == kWI32) {
+  if constexpr (WT == kWUNIT) {
+    return d + 1u;  // levels stay below n
+  } else if constexpr (WT == kWI32) {
     if (d == 0xFFFFFFFFu) return d;
     const int64_t s = (int64_t)(int32_t)(d ^ 0x80000000u) + (int64_t)(int32_t)w;
     if (s >= (int64_t)INT32_MAX) return 0xFFFFFFFFu;

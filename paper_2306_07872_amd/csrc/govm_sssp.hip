@@ -169,7 +169,7 @@ __device__ __forceinline__ void block_push(bool pred, int32_t v, int32_t* sq, ui
 // Record improvements of alpha[v[i]] (lanes with imp[i]): the ptr flag, the
 // beta bitmap, and for the first setter of a bit, the next-step queue of v's
 // degree tier.  Reached by the whole wavefront.
-template <int U>
+template <int WT, int U>
 __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U],
                                            const int32_t (&v)[U], const uint32_t (&cand)[U],
                                            int nxt, int rn, Acc& acc, SsShared& sh) {
@@ -189,8 +189,15 @@ __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U]
     }
   }
 #pragma unroll
-  for (int i = 0; i < U; i++)
-    if (imp[i]) atomicMin(&A.dist[v[i]], cand[i]);  // result unused: not waited for
+  for (int i = 0; i < U; i++) {
+    if (imp[i]) {
+      // unit weights: every candidate of a step is the same level (the
+      // frontier holds exactly the vertices of the previous level), so the
+      // writers agree and a plain store will do
+      if constexpr (WT == kWUNIT) A.dist[v[i]] = cand[i];
+      else atomicMin(&A.dist[v[i]], cand[i]);  // result unused: not waited for
+    }
+  }
 #pragma unroll
   for (int i = 0; i < U; i++)
     if (newv[i]) acc.im += 1;  // a vertex lowered in this step counts once
@@ -239,7 +246,7 @@ __device__ __forceinline__ void ss_relax_n(const SsArgs& A, const int32_t (&e)[U
     cand[i] = 0u;
     if (valid[i]) {
       v[i] = A.colidx[e[i]];
-      cand[i] = relax_key<WT>(du[i], A.w[e[i]]);
+      cand[i] = relax_key<WT>(du[i], WT == kWUNIT ? 1u : A.w[e[i]]);
       if constexpr (WT == kWI32)
         if (cand[i] == 0u) atomicOr(&A.ctl->negfloor, 1u);  // sum left the int32 range
     }
@@ -271,7 +278,7 @@ __device__ __forceinline__ void ss_relax_pre(const SsArgs& A, const int32_t (&e)
     cand[i] = 0u;
     if (valid[i]) {
       v[i] = A.colidx[e[i]];
-      cand[i] = relax_key<WT>(du[i], A.w[e[i]]);
+      cand[i] = relax_key<WT>(du[i], WT == kWUNIT ? 1u : A.w[e[i]]);
       if constexpr (WT == kWI32)
         if (cand[i] == 0u) atomicOr(&A.ctl->negfloor, 1u);  // sum left the int32 range
     }
@@ -335,7 +342,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
         d[j] = du;
       }
       ss_relax_pre<WT, kUnroll>(A, e, ok, d, imp, v, cand);
-      ss_enqueue<kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
+      ss_enqueue<WT, kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
     }
   }
 
@@ -361,7 +368,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
         d[j] = du;
       }
       ss_relax_pre<WT, kUnroll>(A, e, ok, d, imp, v, cand);
-      ss_enqueue<kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
+      ss_enqueue<WT, kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
     }
   }
 
@@ -406,7 +413,7 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
         d[j] = (uint32_t)l_du[owner];
       }
       ss_relax_pre<WT, kUnrollLane>(A, e, ok, d, imp, v, cand);
-      ss_enqueue<kUnrollLane>(A, imp, v, cand, nxt, rn, acc, sh);
+      ss_enqueue<WT, kUnrollLane>(A, imp, v, cand, nxt, rn, acc, sh);
     }
     wave_lds_sync();
   }
@@ -765,7 +772,7 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
             if (ok[j]) {
               const int32_t e = l_base[owner] + k;
               v[j] = A.colidx[e];
-              cand[j] = relax_key<WT>((uint32_t)l_du[owner], A.w[e]);
+              cand[j] = relax_key<WT>((uint32_t)l_du[owner], WT == kWUNIT ? 1u : A.w[e]);
               if constexpr (WT == kWI32)
                 if (cand[j] == 0u) atomicOr(&A.ctl->negfloor, 1u);  // sum left the int32 range
             }
@@ -1013,6 +1020,7 @@ dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.cap_wg = L.cap_wg;
   A.ctl = reinterpret_cast<SsCtl*>(base + L.ctl);
   if (wt == kWF32) return ss_run_t<kWF32>(A, rowptr, colidx, seeds, L, info, stream, capture);
+  if (wt == kWUNIT) return ss_run_t<kWUNIT>(A, rowptr, colidx, seeds, L, info, stream, capture);
   if (wt == kWI32) return ss_run_t<kWI32>(A, rowptr, colidx, seeds, L, info, stream, capture);
   return ss_run_t<kWU32>(A, rowptr, colidx, seeds, L, info, stream, capture);
 }

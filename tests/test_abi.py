@@ -134,4 +134,7 @@ def test_int32_weights_are_single_source_only(lib):
     assert lib.dawn_apsp(fake, fake, fake, 2, 5, 3, fake, null) == 2
     assert b"single-source" in lib.dawn_last_error()
     # an unknown weight type stays invalid (1)
-    assert lib.dawn_sssp(fake, fake, fake, 3, 5, 3, 0, fake, null) == 1
+    assert lib.dawn_sssp(fake, fake, fake, 4, 5, 3, 0, fake, null) == 1
+    # unit weights (3): not in batches or tile sessions
+    h = ctypes.c_void_p()
+    assert lib.dawn_tile_create(ctypes.byref(h), fake, fake, null, 3, 5, 3, 64, null) == 2

@@ -178,3 +178,49 @@ def test_umsssp_full_size_rmat20_sampled(dawn):
     D, info = _umsssp(dawn, csr, srcs, dawn.tgraph(csr))
     assert info["converged"] == 1
     _assert_levels(g, srcs, D, (0, 77, 255), "rmat20")
+
+
+# --- the unit weight type (DAWN_W_UNIT): weights never read ------------------
+
+UNIT_SSSP_TUNINGS = [dict(), dict(small_m=0, mode=2), dict(small_m=0, mode=1, host_check=3),
+                     dict(small_m=0, step_min_m=0, host_check=2), dict(small_m=0, ss_skip=0)]
+
+
+@pytest.mark.parametrize("ti", range(len(UNIT_SSSP_TUNINGS)))
+def test_unit_weight_type_sssp_is_bfs(dawn, ti):
+    import torch
+    for g in (graphgen.rmat(11, 8, 61, weights="u32"), graphgen.rmat(14, 8, 62, weights="f32unit"),
+              graphgen.grid(40, 30, 0.02, 63, weights="f32unit")):
+        csr = dawn.Csr.from_graph(g, wtype="unit")
+        prev = dawn.set_tuning(**UNIT_SSSP_TUNINGS[ti]) if UNIT_SSSP_TUNINGS[ti] else None
+        try:
+            for s in graphgen.pick_sources(g, 2, 70 + ti):
+                announce("sssp unit", g.name, UNIT_SSSP_TUNINGS[ti], int(s))
+                info = dawn.info_tensor()
+                ws = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
+                d = dawn.sssp(csr, int(s), ws=ws, info=info)
+                torch.cuda.synchronize()
+                assert np.array_equal(to_np(d).view(np.uint32), _levels(g, s))
+                lv = oracle.bfs(g, int(s))
+                i = dawn.read_info(info)
+                assert i["steps"] == int(lv.max()) + 1 and i["improvements"] == int((lv >= 0).sum()) - 1
+        finally:
+            if prev is not None:
+                dawn.set_tuning(**prev)
+
+
+def test_unit_weight_type_batched_calls_are_hop_counts(dawn):
+    import torch
+    g = graphgen.rmat(10, 8, 64, weights="u32")
+    csr = dawn.Csr.from_graph(g, wtype="unit")
+    srcs = graphgen.pick_sources(g, 70, 3)
+    announce("msssp / apsp unit")
+    D = to_np(dawn.msssp(csr, srcs))
+    Dt = to_np(dawn.msssp(csr, srcs, tgraph=dawn.tgraph(csr)))  # reverse graph without weights
+    torch.cuda.synchronize()
+    for j in (0, 33, 69):
+        assert np.array_equal(D[j].view(np.uint32), _levels(g, srcs[j]))
+    assert np.array_equal(D.view(np.uint32), Dt.view(np.uint32))
+    A = to_np(dawn.apsp(csr))
+    for s in (0, 511, g.n - 1):
+        assert np.array_equal(A[s].view(np.uint32), _levels(g, s))
