@@ -104,17 +104,18 @@ def c2(args, dawn, torch, np):
     g, srcs = workloads.rmat22(nsrc=args.c2_sources, scale=args.c2_scale)
     log(f"c2 graph n={g.n} m={g.m} ({time.perf_counter() - t:.1f}s)")
     csr = dawn.Csr.from_graph(g)
+    tg = dawn.tgraph(csr) if args.c2_tgraph else None
     out = torch.empty(g.n, dtype=torch.uint32, device="cuda")
     ws = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
     info = dawn.info_tensor()
     outdeg = torch.as_tensor(np.diff(g.rowptr.astype(np.int64)), device="cuda")
-    dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info)
+    dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info, tgraph=tg)
     torch.cuda.synchronize()
     per, gteps, mu, steps, kb, kms = [], [], [], [], 0, 0.0
     for s in srcs:
         dawn.kernel_timer(True)
         t0 = time.perf_counter()
-        dawn.sssp(csr, int(s), out=out, ws=ws, info=info)
+        dawn.sssp(csr, int(s), out=out, ws=ws, info=info, tgraph=tg)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         dawn.kernel_timer(False)
@@ -128,6 +129,7 @@ def c2(args, dawn, torch, np):
         kb += ss_bytes(i, g.n)
         kms += ms
     rec = {"config": f"c2_rmat{args.c2_scale}_ef16_u32_plain", "n": g.n, "m": g.m,
+           "reverse_graph": tg is not None,
            "sources": len(srcs), "gteps_per_source_mean": float(np.mean(gteps)),
            "gteps_per_source_min": float(np.min(gteps)), "mu_e_mean": float(np.mean(mu)),
            "steps_mean": float(np.mean(steps)),
@@ -373,6 +375,8 @@ def main() -> int:
     ap.add_argument("--c1-reps", type=int, default=1000)
     ap.add_argument("--c2-scale", type=int, default=22)
     ap.add_argument("--c2-sources", type=int, default=16)
+    ap.add_argument("--c2-tgraph", action="store_true",
+                    help="keep the reverse graph resident (pull steps per tuning ss_pull)")
     ap.add_argument("--c3-side", type=int, default=2048)
     ap.add_argument("--c3-sources", type=int, default=8)
     ap.add_argument("--c4b-graphs", type=int, default=64)

@@ -185,6 +185,10 @@ typedef struct {
                            another row lowered again within the step is expanded only in the
                            next step (once, with the lower value); 0 or 1 (default: on
                            R-MAT scale 22 it scans 43 % fewer edges, 16 % faster) */
+  int32_t ss_pull;      /* single source with a reverse graph (dawn_sssp_tg_ws), step
+                           launches: a step whose frontier rows hold at least ss_pull / 1000
+                           of the m edges pulls over the in-edges of every vertex; 1001 =
+                           never (default) */
 } dawn_tuning;
 
 #define DAWN_TILE_K_MAX 512
@@ -214,6 +218,15 @@ dawn_status dawn_sssp_ws(const int32_t* rowptr_dev, const int32_t* colidx_dev,
                          const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
                          int32_t source, void* dist_out_dev, void* ws_dev, size_t ws_bytes,
                          dawn_run_info* info_dev, hipStream_t stream);
+
+/* dawn_sssp_ws with the reverse graph of the same CSR (dawn_tgraph_build):
+ * step launches whose frontier is dense (tuning field ss_pull) run as pull
+ * steps over the in-edges of every vertex, with the same results. */
+dawn_status dawn_sssp_tg_ws(const int32_t* rowptr_dev, const int32_t* colidx_dev,
+                            const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
+                            const void* tgraph_dev, int32_t source, void* dist_out_dev,
+                            void* ws_dev, size_t ws_bytes, dawn_run_info* info_dev,
+                            hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Multi source.  sources_dev: int32[k] on the device (duplicates allowed).

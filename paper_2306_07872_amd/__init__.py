@@ -47,7 +47,7 @@ class Tuning(ctypes.Structure):
                 ("t_lane", "t_wave", "t_chunk", "wg_threads", "grid", "mode", "host_check",
                  "tile_k", "tile_t_wave", "tile_t_chunk", "validate", "coop", "tile_t_group",
                  "tile_skip", "small_m", "step_min_m", "tile_sparse", "tile_pull",
-                 "tile_pull_src", "ss_skip")]
+                 "tile_pull_src", "ss_skip", "ss_pull")]
 
 
 INFO_BYTES = ctypes.sizeof(RunInfo)
@@ -88,6 +88,8 @@ def load():
         "dawn_msssp_tg_ws": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp,
                               _vp], _i32),
         "dawn_umsssp_workspace_bytes": ([_i32, _i32, _i32], _sz),
+        "dawn_sssp_tg_ws": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _sz, _vp, _vp],
+                            _i32),
         "dawn_tile_set_tgraph": ([_vp, _vp], _i32),
         "dawn_umsssp_ws": ([_vp, _vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp, _vp], _i32),
         "dawn_batch_create": ([ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp),
@@ -125,6 +127,7 @@ def exported_symbols() -> list[str]:
     return [
         "dawn_status_str", "dawn_last_error", "dawn_build_info", "dawn_get_tuning",
         "dawn_set_tuning", "dawn_sssp", "dawn_sssp_workspace_bytes", "dawn_sssp_ws",
+        "dawn_sssp_tg_ws",
         "dawn_msssp", "dawn_msssp_workspace_bytes", "dawn_msssp_ws", "dawn_apsp",
         "dawn_tgraph_bytes", "dawn_tgraph_build_bytes", "dawn_tgraph_build", "dawn_msssp_tg_ws",
         "dawn_umsssp_workspace_bytes", "dawn_umsssp_ws", "dawn_batch_create", "dawn_batch_sizes", "dawn_batch_vertex_offset", "dawn_batch_run",
@@ -275,14 +278,23 @@ def _aligned(buf):
     return ctypes.c_void_p((p + 255) & ~255), buf.numel() - (((p + 255) & ~255) - p)
 
 
-def sssp(csr: Csr, source: int, out=None, stream=None, ws=None, info=None):
-    """Distances from `source` (uint32 or float32 tensor of length n).
+def sssp(csr: Csr, source: int, out=None, stream=None, ws=None, info=None, tgraph=None):
+    """Distances from `source` (tensor of length n, of the graph's distance type).
     With `ws` (a buffer from ``workspace``) and/or `info` (from
-    ``info_tensor``) the ``dawn_sssp_ws`` entry point is used."""
+    ``info_tensor``) the ``dawn_sssp_ws`` entry point is used; with `tgraph`
+    (from ``tgraph(csr)``) ``dawn_sssp_tg_ws``, whose dense steps may pull
+    (tuning field ss_pull)."""
     torch = _torch()
     if out is None:
         out = torch.empty(csr.n, dtype=dist_dtype(csr.wtype), device=csr.rowptr.device)
     L = load()
+    if tgraph is not None:
+        if ws is None:
+            ws = workspace(sssp_workspace_bytes(csr.n, csr.m), csr.rowptr.device)
+        p, nb = _aligned(ws)
+        _check(L.dawn_sssp_tg_ws(*_csr_args(csr), _aligned(tgraph)[0], int(source), _ptr(out), p,
+                                 nb, _ptr(info), _stream(stream)))
+        return out
     if ws is None and info is None:
         _check(L.dawn_sssp(*_csr_args(csr), int(source), _ptr(out), _stream(stream)))
         return out

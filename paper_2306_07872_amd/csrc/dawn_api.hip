@@ -68,7 +68,8 @@ static bool tuning_ok(const Tuning& t) {
          t.tile_t_group < t.tile_t_wave && (t.tile_skip == 0 || t.tile_skip == 1) &&
          t.small_m >= 0 && t.step_min_m >= 0 && t.tile_sparse >= 0 && t.tile_sparse <= 512 &&
          t.tile_pull >= 0 && t.tile_pull <= 1001 && t.tile_pull_src >= 0 &&
-         t.tile_pull_src <= 512 && (t.ss_skip == 0 || t.ss_skip == 1);
+         t.tile_pull_src <= 512 && (t.ss_skip == 0 || t.ss_skip == 1) && t.ss_pull >= 0 &&
+         t.ss_pull <= 1001;
 }
 
 static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
@@ -252,6 +253,7 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->tile_pull = t.tile_pull;
   out->tile_pull_src = t.tile_pull_src;
   out->ss_skip = t.ss_skip;
+  out->ss_pull = t.ss_pull;
   return DAWN_OK;
 }
 
@@ -278,6 +280,7 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.tile_pull = in->tile_pull;
     t.tile_pull_src = in->tile_pull_src;
     t.ss_skip = in->ss_skip;
+    t.ss_pull = in->ss_pull;
   }
   if (!tuning_ok(t)) return set_error(DAWN_E_INVALID, "tuning out of range");
   g_tuning = t;
@@ -309,6 +312,26 @@ extern "C" dawn_status dawn_sssp_ws(const int32_t* rowptr, const int32_t* colidx
   seeds.source = source;
   return ss_run(rowptr, colidx, weights, (int)wt, n, m, seeds, true, dist_out, ws, info, stream,
                 false);
+}
+
+extern "C" dawn_status dawn_sssp_tg_ws(const int32_t* rowptr, const int32_t* colidx,
+                                       const void* weights, dawn_wtype wt, int32_t n, int32_t m,
+                                       const void* tgraph, int32_t source, void* dist_out,
+                                       void* ws, size_t ws_bytes, dawn_run_info* info,
+                                       hipStream_t stream) {
+  dawn_status st = check_graph(rowptr, colidx, weights, wt, n, m, true, true);
+  if (st != DAWN_OK) return st;
+  if (!tgraph) return set_error(DAWN_E_INVALID, "null reverse graph");
+  if (source < 0 || source >= n) return set_error(DAWN_E_INVALID, "source %d out of range", source);
+  if (!dist_out || !ws) return set_error(DAWN_E_INVALID, "null pointer");
+  if (((reinterpret_cast<uintptr_t>(ws) | reinterpret_cast<uintptr_t>(tgraph)) & 255u) != 0)
+    return set_error(DAWN_E_INVALID, "workspace and reverse graph must be 256-byte aligned");
+  if (ws_bytes < ss_layout(n, m).total)
+    return set_error(DAWN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, ss_layout(n, m).total);
+  SsSeeds seeds;
+  seeds.source = source;
+  return ss_run(rowptr, colidx, weights, (int)wt, n, m, seeds, true, dist_out, ws, info, stream,
+                false, tgraph);
 }
 
 extern "C" dawn_status dawn_sssp(const int32_t* rowptr, const int32_t* colidx, const void* weights,

@@ -39,6 +39,9 @@ struct alignas(256) SsCtl {
   uint32_t bar_base;          // value of `bar` when the next persistent launch starts
   uint32_t negfloor;          // int32 weights: a path sum fell to or below INT32_MIN
   unsigned long long fe, es, im;  // frontier rows, edges scanned, improvements
+  // [step % 4]: out-edges and rows of the step's frontier, counted as the
+  // previous step builds it (the pull decision of step launches)
+  unsigned long long fedges[kRot], frows[kRot];
 };
 
 // Counters of a tile run, striped: workgroup b adds to stripe b % kCtrStripes,
@@ -273,6 +276,21 @@ __device__ __forceinline__ bool last_block_done(uint32_t* blocks_done) {
   return s_last != 0 && threadIdx.x == 0;
 }
 
+// As last_block_done, but true in every thread of the last workgroup.
+__device__ __forceinline__ bool last_block_all(uint32_t* blocks_done) {
+  __shared__ int s_last_all;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t prev = __hip_atomic_fetch_add(blocks_done, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    s_last_all = (prev == gridDim.x - 1);
+    if (s_last_all) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  return s_last_all != 0;
+}
+
 // Sum per-thread counters over the workgroup (wavefront sums, then LDS) and
 // add each total to its counter with one atomic (null pointer: not counted;
 // es2 / se2: second counters that also take the es / se totals).
@@ -336,24 +354,6 @@ __device__ __forceinline__ unsigned long long ctr_sum(const CtrStripe* ctr, size
 
 namespace dawn {
 
-// Kernel arguments of a single-source (or many-seed) GOVM run.
-struct SsArgs {
-  const int32_t* rowptr;
-  const int32_t* colidx;
-  const uint32_t* w;      // uint32 weights, or fp32 weights as bits
-  uint32_t* dist;         // alpha
-  int32_t n, m;
-  int32_t src;            // the "index != source" guard; -1 with many seeds
-  int32_t skip;           // skip expanding a row already lowered again in this step
-  int32_t t_lane, t_wave, t_chunk;
-  int32_t* qlane[2];      // delta, lane tier   [step % 2]
-  int32_t* qwave[2];      // delta, wave tier
-  int4* qwg[2];           // delta, workgroup tier: {row, first edge, edges, first chunk?}
-  uint32_t* bm[2];        // beta dedup bitmaps [step % 2]
-  uint32_t cap_v, cap_wg;
-  SsCtl* ctl;
-};
-
 // The reverse graph for pull steps (built by tgraph_build): in-edge lists per
 // target, cut into chunks of at most kPullChunk in-edges.
 constexpr int kPullChunk = 1024;
@@ -368,6 +368,27 @@ struct TGraph {
   const int4* chunks;      // {target, first in-edge, count, split (target has several chunks)}
   int64_t cap_chunks;
 };
+
+// Kernel arguments of a single-source (or many-seed) GOVM run.
+struct SsArgs {
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const uint32_t* w;      // uint32 weights, or fp32 weights as bits
+  uint32_t* dist;         // alpha
+  int32_t n, m;
+  int32_t src;            // the "index != source" guard; -1 with many seeds
+  int32_t skip;           // skip expanding a row already lowered again in this step
+  TGraph T;               // reverse graph for pull steps, or hdr == nullptr
+  long long pull_min;     // pull when the frontier has >= this many out-edges; < 0: never
+  int32_t t_lane, t_wave, t_chunk;
+  int32_t* qlane[2];      // delta, lane tier   [step % 2]
+  int32_t* qwave[2];      // delta, wave tier
+  int4* qwg[2];           // delta, workgroup tier: {row, first edge, edges, first chunk?}
+  uint32_t* bm[2];        // beta dedup bitmaps [step % 2]
+  uint32_t cap_v, cap_wg;
+  SsCtl* ctl;
+};
+
 
 // Kernel arguments of a batched [n x K] distance-tile run (K = 64 * nseg).
 struct TileArgs {

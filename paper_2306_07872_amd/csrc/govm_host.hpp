@@ -31,6 +31,7 @@ struct Tuning {
   int32_t tile_pull = 400;
   int32_t tile_pull_src = 16;
   int32_t ss_skip = 1;
+  int32_t ss_pull = 1001;
 };
 
 Tuning& tuning();
@@ -73,7 +74,8 @@ struct SsSeeds {
 // capture=true: never use a cooperative launch (HIP graph capture).
 dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, int wt,
                    int32_t n, int32_t m, const SsSeeds& seeds, bool guard_source, void* dist,
-                   void* ws, dawn_run_info* info, hipStream_t stream, bool capture);
+                   void* ws, dawn_run_info* info, hipStream_t stream, bool capture,
+                   const void* tgraph = nullptr);
 
 // ----- distance tile ---------------------------------------------------------
 struct TileLayout {

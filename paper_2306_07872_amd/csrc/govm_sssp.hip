@@ -86,6 +86,8 @@ __global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* 
     if (old & bit) continue;  // duplicate seed
     const int32_t start = A.rowptr[s], deg = A.rowptr[s + 1] - start;
     if (deg == 0) continue;
+    atomicAdd(&C->fedges[0], (unsigned long long)deg);
+    atomicAdd(&C->frows[0], 1ull);
     if (deg <= A.t_lane) {
       const uint32_t p = atomicAdd(&C->cnt[0][0], 1u);
       A.qlane[0][p] = (int32_t)s;
@@ -209,6 +211,10 @@ __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U]
     if (newv[i]) {
       start[i] = A.rowptr[v[i]];
       deg[i] = A.rowptr[v[i] + 1] - start[i];
+      if (deg[i] > 0) {
+        acc.sa += (unsigned long long)deg[i];  // the next frontier's out-edges
+        acc.se += 1;                           // and rows
+      }
     }
   }
 #pragma unroll
@@ -290,6 +296,56 @@ __device__ __forceinline__ void ss_relax_pre(const SsArgs& A, const int32_t (&e)
   for (int i = 0; i < U; i++) imp[i] = valid[i] && cand[i] < cur[i] && v[i] != A.src;
 }
 
+// Minimum over the 16 lanes of this lane's row (DPP row rotations).
+__device__ __forceinline__ uint32_t row16_min(uint32_t x) {
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x121, 0xF, 0xF, false));
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x122, 0xF, 0xF, false));
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xF, 0xF, false));
+  x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false));
+  return x;
+}
+
+// A pull step (step launches on a dense frontier): each 16-lane group takes
+// one in-edge chunk of a target v from the reverse graph and relaxes the
+// in-edges whose source is in the step's frontier (its bit in the current
+// bitmap), 16 at a time; the best candidate goes through the same enqueue as
+// a push step's.  The (edge) relaxations are exactly the push step's; no
+// atomicMin per edge, one per improved target (a target whose in-edges span
+// several chunks may be improved from each).  The current bitmap is read
+// throughout and not cleared here (the step's last workgroup clears it).
+template <int WT>
+__device__ __forceinline__ void ss_pull(const SsArgs& A, int cur, int nxt, int rn, uint32_t gw,
+                                        uint32_t nwv, Acc& acc, SsShared& sh) {
+  const int lane = lane_id(), g = lane >> 4, j16 = lane & 15;
+  const uint32_t nch = (uint32_t)min((long long)A.T.hdr->nchunks, (long long)A.T.cap_chunks);
+  const uint32_t* fb = A.bm[cur];
+  for (uint32_t c0 = gw * 4; c0 < nch; c0 += nwv * 4) {
+    const uint32_t c = c0 + (uint32_t)g;
+    const bool cok = c < nch;
+    const int4 ch = cok ? A.T.chunks[c] : make_int4(0, 0, 0, 0);
+    const int32_t v = ch.x, start = ch.y, len = ch.z;
+    uint32_t best = inf_key<WT>();
+    for (int32_t b = 0; __ballot(cok && b < len) != 0ull; b += 16) {
+      if (cok && b + j16 < len) {
+        const int32_t u = A.T.colidx[start + b + j16];
+        if ((fb[u >> 5] >> (u & 31)) & 1u) {
+          const uint32_t w = WT == kWUNIT ? 1u : A.T.w[start + b + j16];
+          const uint32_t cand = relax_key<WT>(A.dist[u], w);
+          if constexpr (WT == kWI32)
+            if (cand == 0u) atomicOr(&A.ctl->negfloor, 1u);  // sum left the int32 range
+          best = min(best, cand);
+          acc.es += 1;
+        }
+      }
+    }
+    best = row16_min(best);
+    bool imp[1] = {cok && j16 == 0 && v != A.src && best < A.dist[v]};
+    const int32_t vv[1] = {v};
+    const uint32_t cc[1] = {best};
+    ss_enqueue<WT, 1>(A, imp, vv, cc, nxt, rn, acc, sh);
+  }
+}
+
 // With skipping (tuning ss_skip): a frontier row whose distance another row
 // lowered again during this step is already marked for the next step, where
 // it is expanded with a value at least as low; expanding it now as well would
@@ -298,8 +354,9 @@ __device__ __forceinline__ bool ss_skip_row(const SsArgs& A, int nxt, int32_t u)
   return A.skip && ((ld_agent(&A.bm[nxt][u >> 5]) >> (u & 31)) & 1u);
 }
 
+// Returns true when the step was a pull step.
 template <int WT>
-__device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
+__device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
                         SsShared& sh) {
   const int cur = step & 1, nxt = cur ^ 1;
   const int rc = step % kRot, rn = (step + 1) % kRot;
@@ -315,107 +372,115 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
   const uint32_t nl = ld_agent(&C->cnt[rc][0]);
   const uint32_t nw = ld_agent(&C->cnt[rc][1]);
   const uint32_t ng = ld_agent(&C->cnt[rc][2]);
+  const bool pull = A.T.hdr != nullptr && A.pull_min >= 0 &&
+                    ld_agent64(&C->fedges[rc]) >= (unsigned long long)A.pull_min;
+  if (pull) {
+    if (gb == 0 && threadIdx.x == 0) acc.fe += ld_agent64(&C->frows[rc]);
+    ss_pull<WT>(A, cur, nxt, rn, gw, nwv, acc, sh);
+  } else {
 
-  // workgroup tier: one chunk of one row per workgroup
-  for (uint32_t i = gb; i < ng; i += nb) {
-    const int4 r = ld_queue4(&A.qwg[cur][i]);
-    const int32_t u = r.x, start = r.y;
-    const uint32_t du = ld_agent(&A.dist[u]);
-    const int32_t len = ss_skip_row(A, nxt, u) ? 0 : r.z;
-    if (threadIdx.x == 0) {
-      acc.es += (unsigned long long)len;
-      if (r.w) {
+    // workgroup tier: one chunk of one row per workgroup
+    for (uint32_t i = gb; i < ng; i += nb) {
+      const int4 r = ld_queue4(&A.qwg[cur][i]);
+      const int32_t u = r.x, start = r.y;
+      const uint32_t du = ld_agent(&A.dist[u]);
+      const int32_t len = ss_skip_row(A, nxt, u) ? 0 : r.z;
+      if (threadIdx.x == 0) {
+        acc.es += (unsigned long long)len;
+        if (r.w) {
+          A.bm[cur][u >> 5] = 0u;
+          acc.fe += 1;
+        }
+      }
+      const int32_t stride = (int32_t)blockDim.x;
+      for (int32_t base = 0; base < len; base += stride * kUnroll) {
+        int32_t e[kUnroll], v[kUnroll];
+        bool ok[kUnroll], imp[kUnroll];
+        uint32_t d[kUnroll], cand[kUnroll];
+  #pragma unroll
+        for (int j = 0; j < kUnroll; j++) {
+          const int32_t k = base + j * stride + (int32_t)threadIdx.x;
+          ok[j] = k < len;
+          e[j] = start + k;
+          d[j] = du;
+        }
+        ss_relax_pre<WT, kUnroll>(A, e, ok, d, imp, v, cand);
+        ss_enqueue<WT, kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
+      }
+    }
+
+    // wave tier: one wavefront per row
+    for (uint32_t i = gw; i < nw; i += nwv) {
+      const int32_t u = ld_queue(&A.qwave[cur][i]);
+      const int32_t start = A.rowptr[u];
+      const int32_t end = ss_skip_row(A, nxt, u) ? start : A.rowptr[u + 1];
+      const uint32_t du = ld_agent(&A.dist[u]);
+      if (lane == 0) {
         A.bm[cur][u >> 5] = 0u;
         acc.fe += 1;
+        acc.es += (unsigned long long)(end - start);
+      }
+      for (int32_t base = start; base < end; base += kWave * kUnroll) {
+        int32_t e[kUnroll], v[kUnroll];
+        bool ok[kUnroll], imp[kUnroll];
+        uint32_t d[kUnroll], cand[kUnroll];
+  #pragma unroll
+        for (int j = 0; j < kUnroll; j++) {
+          e[j] = base + j * kWave + lane;
+          ok[j] = e[j] < end;
+          d[j] = du;
+        }
+        ss_relax_pre<WT, kUnroll>(A, e, ok, d, imp, v, cand);
+        ss_enqueue<WT, kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
       }
     }
-    const int32_t stride = (int32_t)blockDim.x;
-    for (int32_t base = 0; base < len; base += stride * kUnroll) {
-      int32_t e[kUnroll], v[kUnroll];
-      bool ok[kUnroll], imp[kUnroll];
-      uint32_t d[kUnroll], cand[kUnroll];
-#pragma unroll
-      for (int j = 0; j < kUnroll; j++) {
-        const int32_t k = base + j * stride + (int32_t)threadIdx.x;
-        ok[j] = k < len;
-        e[j] = start + k;
-        d[j] = du;
-      }
-      ss_relax_pre<WT, kUnroll>(A, e, ok, d, imp, v, cand);
-      ss_enqueue<WT, kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
-    }
-  }
 
-  // wave tier: one wavefront per row
-  for (uint32_t i = gw; i < nw; i += nwv) {
-    const int32_t u = ld_queue(&A.qwave[cur][i]);
-    const int32_t start = A.rowptr[u];
-    const int32_t end = ss_skip_row(A, nxt, u) ? start : A.rowptr[u + 1];
-    const uint32_t du = ld_agent(&A.dist[u]);
-    if (lane == 0) {
-      A.bm[cur][u >> 5] = 0u;
-      acc.fe += 1;
-      acc.es += (unsigned long long)(end - start);
-    }
-    for (int32_t base = start; base < end; base += kWave * kUnroll) {
-      int32_t e[kUnroll], v[kUnroll];
-      bool ok[kUnroll], imp[kUnroll];
-      uint32_t d[kUnroll], cand[kUnroll];
-#pragma unroll
-      for (int j = 0; j < kUnroll; j++) {
-        e[j] = base + j * kWave + lane;
-        ok[j] = e[j] < end;
-        d[j] = du;
+    // lane tier: 64 short rows per wavefront, their edges dealt out to the lanes
+    // through an LDS prefix sum of the row lengths
+    int* l_incl = sh.stage + wave * 3 * kWave;
+    int* l_base = l_incl + kWave;
+    int* l_du = l_base + kWave;
+    for (uint32_t bi = gw; (uint64_t)bi * kWave < nl; bi += nwv) {
+      const uint32_t i = bi * kWave + lane;
+      const bool has = i < nl;
+      int32_t u = 0, start = 0, deg = 0;
+      uint32_t du = 0;
+      if (has) {
+        u = ld_queue(&A.qlane[cur][i]);
+        start = A.rowptr[u];
+        deg = ss_skip_row(A, nxt, u) ? 0 : A.rowptr[u + 1] - start;
+        du = ld_agent(&A.dist[u]);
+        A.bm[cur][u >> 5] = 0u;
+        acc.fe += 1;
+        acc.es += (unsigned long long)deg;
       }
-      ss_relax_pre<WT, kUnroll>(A, e, ok, d, imp, v, cand);
-      ss_enqueue<WT, kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
+      const int incl = wave_incl_scan(deg);
+      const int total = __shfl(incl, kWave - 1, kWave);
+      l_incl[lane] = incl;
+      l_base[lane] = start - (incl - deg);
+      l_du[lane] = (int)du;
+      wave_lds_sync();
+      for (int base = 0; base < total; base += kWave * kUnrollLane) {
+        int32_t e[kUnrollLane], v[kUnrollLane];
+        bool ok[kUnrollLane], imp[kUnrollLane];
+        uint32_t d[kUnrollLane], cand[kUnrollLane];
+  #pragma unroll
+        for (int j = 0; j < kUnrollLane; j++) {
+          const int k = base + j * kWave + lane;
+          int owner = 0;  // first lane whose inclusive prefix exceeds k
+  #pragma unroll
+          for (int s = 32; s >= 1; s >>= 1)
+            if (l_incl[owner + s - 1] <= k) owner += s;
+          ok[j] = k < total;
+          e[j] = l_base[owner] + k;
+          d[j] = (uint32_t)l_du[owner];
+        }
+        ss_relax_pre<WT, kUnrollLane>(A, e, ok, d, imp, v, cand);
+        ss_enqueue<WT, kUnrollLane>(A, imp, v, cand, nxt, rn, acc, sh);
+      }
+      wave_lds_sync();
     }
-  }
 
-  // lane tier: 64 short rows per wavefront, their edges dealt out to the lanes
-  // through an LDS prefix sum of the row lengths
-  int* l_incl = sh.stage + wave * 3 * kWave;
-  int* l_base = l_incl + kWave;
-  int* l_du = l_base + kWave;
-  for (uint32_t bi = gw; (uint64_t)bi * kWave < nl; bi += nwv) {
-    const uint32_t i = bi * kWave + lane;
-    const bool has = i < nl;
-    int32_t u = 0, start = 0, deg = 0;
-    uint32_t du = 0;
-    if (has) {
-      u = ld_queue(&A.qlane[cur][i]);
-      start = A.rowptr[u];
-      deg = ss_skip_row(A, nxt, u) ? 0 : A.rowptr[u + 1] - start;
-      du = ld_agent(&A.dist[u]);
-      A.bm[cur][u >> 5] = 0u;
-      acc.fe += 1;
-      acc.es += (unsigned long long)deg;
-    }
-    const int incl = wave_incl_scan(deg);
-    const int total = __shfl(incl, kWave - 1, kWave);
-    l_incl[lane] = incl;
-    l_base[lane] = start - (incl - deg);
-    l_du[lane] = (int)du;
-    wave_lds_sync();
-    for (int base = 0; base < total; base += kWave * kUnrollLane) {
-      int32_t e[kUnrollLane], v[kUnrollLane];
-      bool ok[kUnrollLane], imp[kUnrollLane];
-      uint32_t d[kUnrollLane], cand[kUnrollLane];
-#pragma unroll
-      for (int j = 0; j < kUnrollLane; j++) {
-        const int k = base + j * kWave + lane;
-        int owner = 0;  // first lane whose inclusive prefix exceeds k
-#pragma unroll
-        for (int s = 32; s >= 1; s >>= 1)
-          if (l_incl[owner + s - 1] <= k) owner += s;
-        ok[j] = k < total;
-        e[j] = l_base[owner] + k;
-        d[j] = (uint32_t)l_du[owner];
-      }
-      ss_relax_pre<WT, kUnrollLane>(A, e, ok, d, imp, v, cand);
-      ss_enqueue<WT, kUnrollLane>(A, imp, v, cand, nxt, rn, acc, sh);
-    }
-    wave_lds_sync();
   }
 
   // publish the workgroup's next-frontier entries and ptr flag
@@ -437,12 +502,15 @@ __device__ void ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
     if (p < A.cap_v) A.qwave[nxt][p] = sh.qw[j];
     else atomicOr(&C->overflow, 1u);
   }
+  return pull;
 }
 
 __device__ __forceinline__ void ss_zero_rotation(SsCtl* C, uint32_t step) {
   const int rz = (step + 2) % kRot;
   for (int t = 0; t < 4; t++) st_agent(&C->cnt[rz][t], 0u);
   st_agent(&C->upd[rz], 0u);
+  st_agent64(&C->fedges[rz], 0ull);
+  st_agent64(&C->frows[rz], 0ull);
 }
 
 // All steps in one launch; a grid barrier separates the steps.  The grid must
@@ -487,9 +555,17 @@ __global__ void __launch_bounds__(1024) ss_step_kernel(SsArgs A) {
   const uint32_t step = ld_agent(&C->step);
   if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
   Acc acc;
-  ss_step<WT>(A, step, blockIdx.x, gridDim.x, acc, sh);
-  flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
-  if (last_block_done(&C->blocks_done)) {
+  const bool pulled = ss_step<WT>(A, step, blockIdx.x, gridDim.x, acc, sh);
+  // counters, and the next frontier's out-edges and rows (its pull decision)
+  flush_acc(acc, &C->fe, &C->es, &C->im, &C->fedges[(step + 1) % kRot],
+            &C->frows[(step + 1) % kRot]);
+  if (last_block_all(&C->blocks_done)) {
+    // a pull step read the current bitmap throughout: clear it now, before it
+    // serves as the next step's next-frontier bitmap
+    if (pulled)
+      for (int64_t i = threadIdx.x; i < ((int64_t)A.n + 31) / 32; i += blockDim.x)
+        A.bm[step & 1][i] = 0u;
+    if (threadIdx.x != 0) return;
     st_agent(&C->blocks_done, 0u);
     const uint32_t upd = ld_agent(&C->upd[(step + 1) % kRot]);
     const uint32_t ns = step + 1;
@@ -966,6 +1042,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
     int grid = persistent_grid(ss_persistent_kernel<WT>, threads);
     if (T.grid > 0 && T.grid < grid) grid = T.grid;
     SsArgs a = A;
+    a.pull_min = -1;  // pull steps need step launches (the last workgroup clears the bitmap)
     void* args[] = {&a};
     hipError_t e;
     void* tk = capture ? nullptr : ktimer_begin(stream);
@@ -994,7 +1071,8 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
 
 dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, int wt,
                    int32_t n, int32_t m, const SsSeeds& seeds, bool guard_source, void* dist,
-                   void* ws, dawn_run_info* info, hipStream_t stream, bool capture) {
+                   void* ws, dawn_run_info* info, hipStream_t stream, bool capture,
+                   const void* tgraph) {
   const Tuning& T = tuning();
   const SsLayout L = ss_layout(n, m);
   char* base = static_cast<char*>(ws);
@@ -1008,6 +1086,12 @@ dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.src = guard_source ? seeds.source : -1;
   A.t_lane = T.t_lane;
   A.skip = T.ss_skip;
+  A.T = TGraph{};
+  A.pull_min = -1;
+  if (tgraph && T.ss_pull <= 1000) {
+    A.T = tgraph_view(tgraph, n, m);
+    A.pull_min = (long long)m * T.ss_pull / 1000;
+  }
   A.t_wave = T.t_wave;
   A.t_chunk = T.t_chunk;
   for (int i = 0; i < 2; i++) {

@@ -50,7 +50,7 @@ def test_tuning_roundtrip_and_range_checks(lib):
                 dict(tile_k=1024), dict(mode=3), dict(t_chunk=8), dict(tile_t_wave=4),
                 dict(tile_t_group=65), dict(tile_t_group=64, tile_t_wave=64),
                 dict(tile_skip=2), dict(small_m=-1), dict(step_min_m=-1), dict(tile_pull=1002),
-                dict(tile_pull_src=-1), dict(tile_pull_src=513), dict(ss_skip=2),
+                dict(tile_pull_src=-1), dict(tile_pull_src=513), dict(ss_skip=2), dict(ss_pull=1002),
                 dict(tile_sparse=513)):
         with pytest.raises(dawn.DawnError) as e:
             dawn.set_tuning(**bad)

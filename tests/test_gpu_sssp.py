@@ -256,3 +256,67 @@ def test_full_size_grid_sampled(dawn):
     torch.cuda.synchronize()
     assert_sssp_matches(g, s, to_np(out), tag="grid2048")
     assert dawn.read_info(info)["steps"] > 2000
+
+
+# --- pull steps on the single-source path (dawn_sssp_tg_ws) -------------------
+
+PULL_SS = [dict(small_m=0, mode=1, ss_pull=0),                 # every step a pull step
+           dict(small_m=0, mode=1, ss_pull=200, host_check=3), # by frontier size
+           dict(small_m=0, step_min_m=0, ss_pull=0, host_check=2),  # steps, then persistent
+           dict(small_m=0, mode=2, ss_pull=0),                 # persistent: never pulls
+           dict(small_m=0, mode=1, ss_pull=0, ss_skip=0, t_lane=2, t_wave=64, t_chunk=256)]
+
+
+def _sssp_tg(dawn, csr, s, tg, **tune):
+    import torch
+    prev = dawn.set_tuning(**tune)
+    try:
+        info = dawn.info_tensor()
+        d = dawn.sssp(csr, int(s), info=info, tgraph=tg)
+        torch.cuda.synchronize()
+        return to_np(d), dawn.read_info(info)
+    finally:
+        dawn.set_tuning(**prev)
+
+
+@pytest.mark.parametrize("ti", range(len(PULL_SS)))
+@pytest.mark.parametrize("wk", ["u32", "f32lognormal", "grid"])
+def test_sssp_pull_steps_match_oracle(dawn, wk, ti):
+    if wk == "grid":
+        g = graphgen.grid(60, 50, 0.01, 81, weights="f32unit")
+    else:
+        g = graphgen.rmat(13, 16, 80, weights=wk)   # hubs: targets with several in-edge chunks
+    csr = dawn.Csr.from_graph(g)
+    tg = dawn.tgraph(csr)
+    for s in graphgen.pick_sources(g, 3, 90 + ti):
+        announce("sssp pull", wk, PULL_SS[ti], int(s))
+        d, info = _sssp_tg(dawn, csr, s, tg, **PULL_SS[ti])
+        assert info["converged"] == 1
+        assert_sssp_matches(g, int(s), d, tag=f"pull {PULL_SS[ti]}")
+
+
+def test_sssp_pull_signed_and_unit_weights(dawn):
+    g0 = graphgen.rmat(12, 16, 82, weights="u32", wlo=1, whi=100)
+    gi, p = graphgen.potential_shift(g0, 2000, 5)
+    csr = dawn.Csr.from_graph(gi)
+    tg = dawn.tgraph(csr)
+    for s in graphgen.pick_sources(g0, 2, 6):
+        announce("sssp pull i32", int(s))
+        d, info = _sssp_tg(dawn, csr, s, tg, **PULL_SS[0])
+        ref, ok = oracle.bellman_ford(gi, int(s))
+        assert ok and info["converged"] == 1
+        ref = np.where(ref == np.iinfo(np.int64).max, np.iinfo(np.int32).max, ref)
+        assert np.array_equal(d.view(np.int32).astype(np.int64), ref)
+    cu = dawn.Csr.from_graph(g0, wtype="unit")
+    tgu = dawn.tgraph(cu)
+    for s in graphgen.pick_sources(g0, 2, 7):
+        announce("sssp pull unit", int(s))
+        d, info = _sssp_tg(dawn, cu, s, tgu, **PULL_SS[0])
+        lv = oracle.bfs(g0, int(s))
+        ref = np.where(lv >= 0, lv, -1).astype(np.int64).astype(np.uint32)
+        assert np.array_equal(d.view(np.uint32), ref)
+        # every step exact at unit weights: the counters are the BFS ones
+        assert info["edges_scanned"] == oracle.m_reach(g0, int(s))
+        assert info["improvements"] == int((lv >= 0).sum()) - 1
+        assert info["frontier_entries"] == int(((lv >= 0) & (g0.outdeg() > 0)).sum())
+        assert info["steps"] == int(lv.max()) + 1
