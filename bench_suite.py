@@ -134,7 +134,7 @@ def c2(args, dawn, torch, np):
            "gteps_per_source_min": float(np.min(gteps)), "mu_e_mean": float(np.mean(mu)),
            "steps_mean": float(np.mean(steps)),
            "roofline": {"bound": "hbm",
-                        "kernel": ("ss_step_kernel<0> (uint32 weights)" if g.m >= dawn.get_tuning()["step_min_m"]
+                        "kernel": ("ss_step_kernel<0, false> (uint32 weights)" if g.m >= dawn.get_tuning()["step_min_m"]
                                    else "ss_persistent_kernel<0> (uint32 weights)"),
                         "achieved": kb / (kms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
                         "frac": kb / (kms * 1e-3) / 1e9 / 8000.0}}

@@ -25,29 +25,43 @@ constexpr int kMaxWavesPerBlock = 16;      // 1024-thread workgroups
 constexpr int kRot = 4;                    // rotation of per-step counters
 constexpr int kSegMax = 8;                 // 8 x 64 = 512 tile columns
 
-// Per-run control block in device memory (zeroed before a run).
-struct alignas(256) SsCtl {
-  uint32_t cnt[kRot][4];      // [step % 4][tier]: lane, wave, workgroup-chunk records
-  uint32_t upd[kRot];         // [step % 4]: any improvement during the previous step
-  uint32_t step;              // next step to run
-  uint32_t done;              // 1 once the loop has stopped
-  int32_t converged;          // see dawn_run_info
-  uint32_t bar;               // grid barrier arrivals (monotone within a launch)
-  uint32_t abort;             // set when a barrier wait gives up
-  uint32_t blocks_done;       // last-block detection of step launches
-  uint32_t overflow;          // a queue capacity was exceeded (cannot happen on valid input)
-  uint32_t bar_base;          // value of `bar` when the next persistent launch starts
-  uint32_t negfloor;          // int32 weights: a path sum fell to or below INT32_MIN
+// Counters that every workgroup of a step adds to are striped: workgroup b
+// adds to stripe b % kCtrStripes, each on its own 256-byte line, so that the
+// adds of many workgroups do not queue on one line; a reader sums the stripes.
+constexpr int kCtrStripes = 32;
+
+// A 32-bit control word alone on its cache line.
+struct alignas(128) LineU32 {
+  uint32_t v;
+};
+
+// Counters of a single-source run.
+struct alignas(256) SsStripe {
   unsigned long long fe, es, im;  // frontier rows, edges scanned, improvements
   // [step % 4]: out-edges and rows of the step's frontier, counted as the
   // previous step builds it (the pull decision of step launches)
   unsigned long long fedges[kRot], frows[kRot];
 };
 
-// Counters of a tile run, striped: workgroup b adds to stripe b % kCtrStripes,
-// each on its own 256-byte line, so that the adds of many workgroups do not
-// queue on one address; a reader sums the stripes.
-constexpr int kCtrStripes = 32;
+// Per-run control block in device memory (zeroed before a run).  Words that
+// workgroups update concurrently sit on lines of their own, apart from the
+// words every workgroup reads at the start of a step.
+struct alignas(256) SsCtl {
+  uint32_t step;              // next step to run
+  uint32_t done;              // 1 once the loop has stopped
+  int32_t converged;          // see dawn_run_info
+  uint32_t abort;             // set when a barrier wait gives up
+  uint32_t overflow;          // a queue capacity was exceeded (cannot happen on valid input)
+  uint32_t bar_base;          // value of `bar` when the next persistent launch starts
+  uint32_t negfloor;          // int32 weights: a path sum fell to or below INT32_MIN
+  alignas(128) uint32_t upd[kRot];  // [step % 4]: any improvement during the previous step
+  LineU32 bar;                // grid barrier arrivals (monotone within a launch)
+  LineU32 arrive;             // last-block detection of step launches
+  LineU32 cnt[kRot][4];       // [step % 4][tier]: lane, wave, workgroup-chunk records
+  SsStripe ctr[kCtrStripes];
+};
+
+// Counters of a tile run, striped like those of a single-source run.
 struct alignas(256) CtrStripe {
   unsigned long long fe, es, im, sa, se;  // union rows, union edges, improvements,
                                           // per-source rows, per-source edges
@@ -56,13 +70,15 @@ struct alignas(256) CtrStripe {
 };
 
 struct alignas(256) TileCtl {
-  uint32_t cnt[kRot][4];               // [step % 4][tier]: group, wave, workgroup-chunk
   unsigned long long colact[kRot][kSegMax];  // [step % 4]: columns improved in step-1
   unsigned long long live[kSegMax];    // admitted columns
   uint32_t step, done;
   int32_t converged;
-  uint32_t bar, abort, blocks_done, overflow, bar_base;
+  uint32_t abort, overflow, bar_base;
   uint32_t cstep;                      // the step whose compaction ran last
+  LineU32 bar;                         // grid barrier arrivals (monotone within a launch)
+  LineU32 arrive;                      // last-block detection of step launches
+  LineU32 cnt[kRot][4];                // [step % 4][tier]: group, wave, workgroup-chunk
   CtrStripe ctr[kCtrStripes];           // statistics, summed over the stripes
   int32_t colsteps[kSegMax * 64];
 };
@@ -260,35 +276,34 @@ __device__ __forceinline__ bool grid_sync(uint32_t* bar, uint32_t* abort_flag, u
   return s_ok != 0;
 }
 
-// Last-block detection for step launches: returns true in thread 0 of the
-// block that finishes last (after all others' writes are visible).
-__device__ __forceinline__ bool last_block_done(uint32_t* blocks_done) {
+// Last-block detection for step launches: returns true in every thread of
+// the workgroup that arrives last, once all other workgroups' writes are
+// visible to it, and leaves the arrival word at zero for the next launch.
+// Every thread must call it.  (Arrivals in two levels, over striped words,
+// measured no faster: a step's workgroups do not finish all at once.)
+__device__ __forceinline__ bool last_block_arrive(LineU32* arrive) {
   __shared__ int s_last;
   __syncthreads();
   if (threadIdx.x == 0) {
+    int last = 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t prev = __hip_atomic_fetch_add(blocks_done, 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == gridDim.x - 1);
-    if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (__hip_atomic_fetch_add(&arrive->v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+        gridDim.x - 1) {
+      st_agent(&arrive->v, 0u);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      last = 1;
+    }
+    s_last = last;
   }
   __syncthreads();
-  return s_last != 0 && threadIdx.x == 0;
+  return s_last != 0;
 }
 
-// As last_block_done, but true in every thread of the last workgroup.
-__device__ __forceinline__ bool last_block_all(uint32_t* blocks_done) {
-  __shared__ int s_last_all;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t prev = __hip_atomic_fetch_add(blocks_done, 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    s_last_all = (prev == gridDim.x - 1);
-    if (s_last_all) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-  return s_last_all != 0;
+// OR x into a word that only gains bits during a step, unless they are all
+// there already: a memory-side load instead of a memory-side atomic, and in a
+// dense step most workgroups find every bit set.
+__device__ __forceinline__ void or_new_bits(unsigned long long* p, unsigned long long x) {
+  if ((ld_agent64(p) & x) != x) atomicOr(p, x);
 }
 
 // Sum per-thread counters over the workgroup (wavefront sums, then LDS) and
@@ -341,7 +356,8 @@ __device__ __forceinline__ uint32_t ld_agent_block(const uint32_t* p) {
 }
 
 // Sum of one counter over the stripes, in every lane (all lanes must be active).
-__device__ __forceinline__ unsigned long long ctr_sum(const CtrStripe* ctr, size_t offset) {
+template <typename Stripe>
+__device__ __forceinline__ unsigned long long ctr_sum(const Stripe* ctr, size_t offset) {
   const int lane = lane_id();
   unsigned long long x = 0;
   if (lane < kCtrStripes)

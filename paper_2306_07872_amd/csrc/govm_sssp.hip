@@ -86,17 +86,17 @@ __global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* 
     if (old & bit) continue;  // duplicate seed
     const int32_t start = A.rowptr[s], deg = A.rowptr[s + 1] - start;
     if (deg == 0) continue;
-    atomicAdd(&C->fedges[0], (unsigned long long)deg);
-    atomicAdd(&C->frows[0], 1ull);
+    atomicAdd(&C->ctr[0].fedges[0], (unsigned long long)deg);
+    atomicAdd(&C->ctr[0].frows[0], 1ull);
     if (deg <= A.t_lane) {
-      const uint32_t p = atomicAdd(&C->cnt[0][0], 1u);
+      const uint32_t p = atomicAdd(&C->cnt[0][0].v, 1u);
       A.qlane[0][p] = (int32_t)s;
     } else if (deg <= A.t_wave) {
-      const uint32_t p = atomicAdd(&C->cnt[0][1], 1u);
+      const uint32_t p = atomicAdd(&C->cnt[0][1].v, 1u);
       A.qwave[0][p] = (int32_t)s;
     } else {
       const uint32_t nch = (deg + A.t_chunk - 1) / A.t_chunk;
-      const uint32_t p = atomicAdd(&C->cnt[0][2], nch);
+      const uint32_t p = atomicAdd(&C->cnt[0][2].v, nch);
       for (uint32_t c = 0; c < nch; c++) {
         const int32_t off = (int32_t)c * A.t_chunk;
         if (p + c < A.cap_wg)
@@ -118,18 +118,23 @@ __global__ void ss_decode_i32_kernel(uint32_t* dist, int64_t n, const SsCtl* C,
     info->converged = 0;
 }
 
+// One wavefront: the counters summed over their stripes.
 template <int WT>
 __global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (blockIdx.x != 0 || threadIdx.x >= kWave) return;
+  const unsigned long long fe = ctr_sum(C->ctr, offsetof(SsStripe, fe));
+  const unsigned long long es = ctr_sum(C->ctr, offsetof(SsStripe, es));
+  const unsigned long long im = ctr_sum(C->ctr, offsetof(SsStripe, im));
+  if (threadIdx.x != 0) return;
   int32_t conv = ld_agent_i(&C->converged);
   if (ld_agent(&C->abort)) conv = -2;
   info->steps = (int32_t)ld_agent(&C->step);
   info->converged = conv;
-  info->frontier_entries = (int64_t)ld_agent64(&C->fe);
-  info->edges_scanned = (int64_t)ld_agent64(&C->es);
-  info->improvements = (int64_t)ld_agent64(&C->im);
-  info->union_rows = (int64_t)ld_agent64(&C->fe);
-  info->union_edges = (int64_t)ld_agent64(&C->es);
+  info->frontier_entries = (int64_t)fe;
+  info->edges_scanned = (int64_t)es;
+  info->improvements = (int64_t)im;
+  info->union_rows = (int64_t)fe;
+  info->union_edges = (int64_t)es;
 }
 
 // ---------------------------------------------------------------------------
@@ -170,8 +175,9 @@ __device__ __forceinline__ void block_push(bool pred, int32_t v, int32_t* sq, ui
 
 // Record improvements of alpha[v[i]] (lanes with imp[i]): the ptr flag, the
 // beta bitmap, and for the first setter of a bit, the next-step queue of v's
-// degree tier.  Reached by the whole wavefront.
-template <int WT, int U>
+// degree tier.  Reached by the whole wavefront.  CNT: also count the next
+// frontier's rows and out-edges (the pull decision of the next step).
+template <int WT, int U, bool CNT>
 __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U],
                                            const int32_t (&v)[U], const uint32_t (&cand)[U],
                                            int nxt, int rn, Acc& acc, SsShared& sh) {
@@ -211,7 +217,7 @@ __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U]
     if (newv[i]) {
       start[i] = A.rowptr[v[i]];
       deg[i] = A.rowptr[v[i] + 1] - start[i];
-      if (deg[i] > 0) {
+      if (CNT && deg[i] > 0) {
         acc.sa += (unsigned long long)deg[i];  // the next frontier's out-edges
         acc.se += 1;                           // and rows
       }
@@ -221,13 +227,13 @@ __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U]
   for (int i = 0; i < U; i++) {
     const bool tl = newv[i] && deg[i] > 0 && deg[i] <= A.t_lane;
     const bool tw = newv[i] && deg[i] > A.t_lane && deg[i] <= A.t_wave;
-    block_push(tl, v[i], sh.ql, &sh.nql, kLdsQLane, A.qlane[nxt], &C->cnt[rn][0], A.cap_v,
+    block_push(tl, v[i], sh.ql, &sh.nql, kLdsQLane, A.qlane[nxt], &C->cnt[rn][0].v, A.cap_v,
                &C->overflow);
-    block_push(tw, v[i], sh.qw, &sh.nqw, kLdsQWave, A.qwave[nxt], &C->cnt[rn][1], A.cap_v,
+    block_push(tw, v[i], sh.qw, &sh.nqw, kLdsQWave, A.qwave[nxt], &C->cnt[rn][1].v, A.cap_v,
                &C->overflow);
     if (newv[i] && deg[i] > A.t_wave) {
       const uint32_t nch = (uint32_t)((deg[i] + A.t_chunk - 1) / A.t_chunk);
-      const uint32_t base = atomicAdd(&C->cnt[rn][2], nch);
+      const uint32_t base = atomicAdd(&C->cnt[rn][2].v, nch);
       for (uint32_t c = 0; c < nch; c++) {
         const int32_t off = (int32_t)c * A.t_chunk;
         if (base + c < A.cap_wg)
@@ -342,7 +348,7 @@ __device__ __forceinline__ void ss_pull(const SsArgs& A, int cur, int nxt, int r
     bool imp[1] = {cok && j16 == 0 && v != A.src && best < A.dist[v]};
     const int32_t vv[1] = {v};
     const uint32_t cc[1] = {best};
-    ss_enqueue<WT, 1>(A, imp, vv, cc, nxt, rn, acc, sh);
+    ss_enqueue<WT, 1, true>(A, imp, vv, cc, nxt, rn, acc, sh);
   }
 }
 
@@ -355,7 +361,9 @@ __device__ __forceinline__ bool ss_skip_row(const SsArgs& A, int nxt, int32_t u)
 }
 
 // Returns true when the step was a pull step.
-template <int WT>
+// PULL: pull steps may run (step launches with a reverse graph); the push-only
+// instance keeps none of their code.
+template <int WT, bool PULL>
 __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
                         SsShared& sh) {
   const int cur = step & 1, nxt = cur ^ 1;
@@ -369,13 +377,20 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
     sh.upd = 0u;
   }
   __syncthreads();
-  const uint32_t nl = ld_agent(&C->cnt[rc][0]);
-  const uint32_t nw = ld_agent(&C->cnt[rc][1]);
-  const uint32_t ng = ld_agent(&C->cnt[rc][2]);
-  const bool pull = A.T.hdr != nullptr && A.pull_min >= 0 &&
-                    ld_agent64(&C->fedges[rc]) >= (unsigned long long)A.pull_min;
+  const uint32_t nl = ld_agent(&C->cnt[rc][0].v);
+  const uint32_t nw = ld_agent(&C->cnt[rc][1].v);
+  const uint32_t ng = ld_agent(&C->cnt[rc][2].v);
+  // (uniform over the workgroup: every wavefront sums the stripes)
+  const bool pull =
+      PULL && A.T.hdr != nullptr && A.pull_min >= 0 &&
+      ctr_sum(C->ctr, offsetof(SsStripe, fedges) + rc * sizeof(unsigned long long)) >=
+          (unsigned long long)A.pull_min;
   if (pull) {
-    if (gb == 0 && threadIdx.x == 0) acc.fe += ld_agent64(&C->frows[rc]);
+    if (gb == 0 && threadIdx.x < kWave) {
+      const unsigned long long rows =
+          ctr_sum(C->ctr, offsetof(SsStripe, frows) + rc * sizeof(unsigned long long));
+      if (threadIdx.x == 0) acc.fe += rows;
+    }
     ss_pull<WT>(A, cur, nxt, rn, gw, nwv, acc, sh);
   } else {
 
@@ -405,7 +420,7 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
           d[j] = du;
         }
         ss_relax_pre<WT, kUnroll>(A, e, ok, d, imp, v, cand);
-        ss_enqueue<WT, kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
+        ss_enqueue<WT, kUnroll, PULL>(A, imp, v, cand, nxt, rn, acc, sh);
       }
     }
 
@@ -431,7 +446,7 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
           d[j] = du;
         }
         ss_relax_pre<WT, kUnroll>(A, e, ok, d, imp, v, cand);
-        ss_enqueue<WT, kUnroll>(A, imp, v, cand, nxt, rn, acc, sh);
+        ss_enqueue<WT, kUnroll, PULL>(A, imp, v, cand, nxt, rn, acc, sh);
       }
     }
 
@@ -476,7 +491,7 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
           d[j] = (uint32_t)l_du[owner];
         }
         ss_relax_pre<WT, kUnrollLane>(A, e, ok, d, imp, v, cand);
-        ss_enqueue<WT, kUnrollLane>(A, imp, v, cand, nxt, rn, acc, sh);
+        ss_enqueue<WT, kUnrollLane, PULL>(A, imp, v, cand, nxt, rn, acc, sh);
       }
       wave_lds_sync();
     }
@@ -487,8 +502,8 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
   __syncthreads();
   const uint32_t n_l = min(sh.nql, (uint32_t)kLdsQLane), n_w = min(sh.nqw, (uint32_t)kLdsQWave);
   if (threadIdx.x == 0) {
-    if (n_l) sh.gbase_l = atomicAdd(&C->cnt[rn][0], n_l);
-    if (n_w) sh.gbase_w = atomicAdd(&C->cnt[rn][1], n_w);
+    if (n_l) sh.gbase_l = atomicAdd(&C->cnt[rn][0].v, n_l);
+    if (n_w) sh.gbase_w = atomicAdd(&C->cnt[rn][1].v, n_w);
     if (sh.upd) st_agent(&C->upd[rn], 1u);
   }
   __syncthreads();
@@ -505,12 +520,15 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
   return pull;
 }
 
+// Threads 0 .. kCtrStripes-1 of one workgroup.
 __device__ __forceinline__ void ss_zero_rotation(SsCtl* C, uint32_t step) {
   const int rz = (step + 2) % kRot;
-  for (int t = 0; t < 4; t++) st_agent(&C->cnt[rz][t], 0u);
-  st_agent(&C->upd[rz], 0u);
-  st_agent64(&C->fedges[rz], 0ull);
-  st_agent64(&C->frows[rz], 0ull);
+  if (threadIdx.x == 0) {
+    for (int t = 0; t < 4; t++) st_agent(&C->cnt[rz][t].v, 0u);
+    st_agent(&C->upd[rz], 0u);
+  }
+  st_agent64(&C->ctr[threadIdx.x].fedges[rz], 0ull);
+  st_agent64(&C->ctr[threadIdx.x].frows[rz], 0ull);
 }
 
 // All steps in one launch; a grid barrier separates the steps.  The grid must
@@ -526,9 +544,9 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
   uint32_t step = ld_agent(&C->step);
   int32_t status = 1;
   for (;;) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
-    ss_step<WT>(A, step, blockIdx.x, gridDim.x, acc, sh);
-    if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
+    if (blockIdx.x == 0 && threadIdx.x < kCtrStripes) ss_zero_rotation(C, step);
+    ss_step<WT, false>(A, step, blockIdx.x, gridDim.x, acc, sh);
+    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       break;
     }
@@ -537,7 +555,8 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
     if (!upd) { status = 1; break; }
     if (step >= (uint32_t)A.n) { status = 0; break; }
   }
-  flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
+  SsStripe& S = C->ctr[blockIdx.x % kCtrStripes];
+  flush_acc(acc, &S.fe, &S.es, &S.im, nullptr, nullptr);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st_agent(&C->step, step);
     st_agent_i(&C->converged, status);
@@ -547,26 +566,25 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
 }
 
 // One step per launch; the last block to finish advances the step.
-template <int WT>
+template <int WT, bool PULL>
 __global__ void __launch_bounds__(1024) ss_step_kernel(SsArgs A) {
   __shared__ SsShared sh;
   SsCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
   const uint32_t step = ld_agent(&C->step);
-  if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
+  if (blockIdx.x == 0 && threadIdx.x < kCtrStripes) ss_zero_rotation(C, step);
   Acc acc;
-  const bool pulled = ss_step<WT>(A, step, blockIdx.x, gridDim.x, acc, sh);
+  const bool pulled = ss_step<WT, PULL>(A, step, blockIdx.x, gridDim.x, acc, sh);
   // counters, and the next frontier's out-edges and rows (its pull decision)
-  flush_acc(acc, &C->fe, &C->es, &C->im, &C->fedges[(step + 1) % kRot],
-            &C->frows[(step + 1) % kRot]);
-  if (last_block_all(&C->blocks_done)) {
+  SsStripe& S = C->ctr[blockIdx.x % kCtrStripes];
+  flush_acc(acc, &S.fe, &S.es, &S.im, &S.fedges[(step + 1) % kRot], &S.frows[(step + 1) % kRot]);
+  if (last_block_arrive(&C->arrive)) {
     // a pull step read the current bitmap throughout: clear it now, before it
     // serves as the next step's next-frontier bitmap
     if (pulled)
       for (int64_t i = threadIdx.x; i < ((int64_t)A.n + 31) / 32; i += blockDim.x)
         A.bm[step & 1][i] = 0u;
     if (threadIdx.x != 0) return;
-    st_agent(&C->blocks_done, 0u);
     const uint32_t upd = ld_agent(&C->upd[(step + 1) % kRot]);
     const uint32_t ns = step + 1;
     st_agent(&C->step, ns);
@@ -722,10 +740,11 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
   }
   // counters, state and run info
   // thread i zeroes the counter that it then adds to (flush_acc: fe, es, im)
-  if (threadIdx.x == 0) st_agent64(&C->fe, 0ull);
-  if (threadIdx.x == 1) st_agent64(&C->es, 0ull);
-  if (threadIdx.x == 2) st_agent64(&C->im, 0ull);
-  flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
+  SsStripe& S = C->ctr[0];  // one workgroup: one stripe
+  if (threadIdx.x == 0) st_agent64(&S.fe, 0ull);
+  if (threadIdx.x == 1) st_agent64(&S.es, 0ull);
+  if (threadIdx.x == 2) st_agent64(&S.im, 0ull);
+  flush_acc(acc, &S.fe, &S.es, &S.im, nullptr, nullptr);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -738,9 +757,9 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
     if (info) {
       info->steps = (int32_t)ld_agent(&C->step);
       info->converged = ld_agent_i(&C->converged);
-      info->frontier_entries = (int64_t)ld_agent64(&C->fe);
-      info->edges_scanned = (int64_t)ld_agent64(&C->es);
-      info->improvements = (int64_t)ld_agent64(&C->im);
+      info->frontier_entries = (int64_t)ld_agent64(&S.fe);
+      info->edges_scanned = (int64_t)ld_agent64(&S.es);
+      info->improvements = (int64_t)ld_agent64(&S.im);
       info->union_rows = info->frontier_entries;
       info->union_edges = info->edges_scanned;
     }
@@ -891,10 +910,11 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
     for (int i = threadIdx.x; i < n; i += blockDim.x) A.dist[i] = sh.dist[i];
   }
   // thread i zeroes the counter that it then adds to (flush_acc: fe, es, im)
-  if (threadIdx.x == 0) st_agent64(&C->fe, 0ull);
-  if (threadIdx.x == 1) st_agent64(&C->es, 0ull);
-  if (threadIdx.x == 2) st_agent64(&C->im, 0ull);
-  flush_acc(acc, &C->fe, &C->es, &C->im, nullptr, nullptr);
+  SsStripe& S = C->ctr[0];  // one workgroup: one stripe
+  if (threadIdx.x == 0) st_agent64(&S.fe, 0ull);
+  if (threadIdx.x == 1) st_agent64(&S.es, 0ull);
+  if (threadIdx.x == 2) st_agent64(&S.im, 0ull);
+  flush_acc(acc, &S.fe, &S.es, &S.im, nullptr, nullptr);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -907,9 +927,9 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
     if (info) {
       info->steps = (int32_t)ld_agent(&C->step);
       info->converged = ld_agent_i(&C->converged);
-      info->frontier_entries = (int64_t)ld_agent64(&C->fe);
-      info->edges_scanned = (int64_t)ld_agent64(&C->es);
-      info->improvements = (int64_t)ld_agent64(&C->im);
+      info->frontier_entries = (int64_t)ld_agent64(&S.fe);
+      info->edges_scanned = (int64_t)ld_agent64(&S.es);
+      info->improvements = (int64_t)ld_agent64(&S.im);
       info->union_rows = info->frontier_entries;
       info->union_edges = info->edges_scanned;
     }
@@ -1018,6 +1038,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
   if (mode == 1 || mode == 3) {
     if (capture) return set_error(DAWN_E_UNSUPPORTED, "step launches cannot be captured");
     const int grid = T.grid > 0 ? T.grid : 4 * di.cus;
+    auto stepk = A.pull_min >= 0 ? ss_step_kernel<WT, true> : ss_step_kernel<WT, false>;
     PinnedWord done;
     if (!done.p) return set_error(DAWN_E_HIP, "hipHostMalloc failed");
     *done.p = 0;
@@ -1027,7 +1048,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
       const int chunk = (int)std::min<int64_t>(T.host_check, cap - launched);
       void* tk = ktimer_begin(stream);
       for (int s = 0; s < chunk; s++)
-        hipLaunchKernelGGL(ss_step_kernel<WT>, dim3(grid), dim3(threads), 0, stream, A);
+        hipLaunchKernelGGL(stepk, dim3(grid), dim3(threads), 0, stream, A);
       ktimer_end(tk, stream, chunk);
       launched += chunk;
       hipMemcpyAsync(done.p, &A.ctl->done, 4, hipMemcpyDeviceToHost, stream);

@@ -121,7 +121,7 @@ __global__ void tile_evict_kernel(TileArgs A, int32_t col) {
 __device__ __forceinline__ void tile_prologue(TileCtl* C, uint32_t step, int K) {
   // zero the counters of the next step and count this step for active columns
   const int rz = (step + 1) % kRot, rc = step % kRot;
-  if (threadIdx.x < 4) st_agent(&C->cnt[rz][threadIdx.x], 0u);
+  if (threadIdx.x < 4) st_agent(&C->cnt[rz][threadIdx.x].v, 0u);
   if (threadIdx.x == 4) st_agent(&C->cstep, step);
   if (threadIdx.x < kCtrStripes) {
     st_agent64(&C->ctr[threadIdx.x].fedges[rz], 0ull);
@@ -170,7 +170,7 @@ __device__ __forceinline__ void compact_flush(const TileArgs& A, int q, int rc,
   __syncthreads();
   if (threadIdx.x < 2) {
     const uint32_t c = sh.cnt[threadIdx.x];
-    sh.base[threadIdx.x] = c ? atomicAdd(&C->cnt[rc][threadIdx.x], c) : 0u;
+    sh.base[threadIdx.x] = c ? atomicAdd(&C->cnt[rc][threadIdx.x].v, c) : 0u;
   }
   __syncthreads();
   for (int t = 0; t < 2; t++) {
@@ -278,7 +278,7 @@ __device__ __forceinline__ void tile_compact(const TileArgs& A, uint32_t step, u
     if (hub) loc = atomicAdd(&sh.nch, nch);
     __syncthreads();
     if (threadIdx.x == 0) {
-      sh.chbase = sh.nch ? atomicAdd(&C->cnt[rc][2], sh.nch) : 0u;
+      sh.chbase = sh.nch ? atomicAdd(&C->cnt[rc][2].v, sh.nch) : 0u;
       sh.nch = 0u;
     }
     __syncthreads();
@@ -535,9 +535,9 @@ __device__ __forceinline__ void tile_clear_prev(const TileArgs& A, uint32_t step
   const int qp = (step + 2) % 3, rp = (step + 3) % kRot;
   const int nseg = A.nseg;
   {
-    const uint32_t pg = min(ld_agent(&C->cnt[rp][0]), A.cap_v);
-    const uint32_t pw = min(ld_agent(&C->cnt[rp][1]), A.cap_v);
-    const uint32_t pc = min(ld_agent(&C->cnt[rp][2]), A.cap_wg);
+    const uint32_t pg = min(ld_agent(&C->cnt[rp][0].v), A.cap_v);
+    const uint32_t pw = min(ld_agent(&C->cnt[rp][1].v), A.cap_v);
+    const uint32_t pc = min(ld_agent(&C->cnt[rp][2].v), A.cap_wg);
     const uint32_t tot = pg + pw + pc;
     for (uint32_t i = gb * blockDim.x + threadIdx.x; i < tot; i += nb * blockDim.x) {
       int32_t u;
@@ -577,7 +577,7 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
   tile_clear_prev(A, step, gb, nb);
 
   // (b) workgroup tier: the 16-lane groups of the workgroup share a chunk
-  const uint32_t nc = min(ld_agent(&C->cnt[rc][2]), A.cap_wg);
+  const uint32_t nc = min(ld_agent(&C->cnt[rc][2].v), A.cap_wg);
   for (uint32_t i = gb; i < nc; i += nb) {
     const int4 r = ld_queue4(&A.qwg[q][i]);
     const unsigned long long x = lane < nseg ? tile_row_mask(A, q, qn, r.x, lane) : 0ull;
@@ -611,7 +611,7 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
   // active segments, counters), so the setup round trips of a batch overlap;
   // the rows are then walked from registers.
   // Each wavefront takes an even, contiguous share of a queue.
-  const uint32_t nw = min(ld_agent(&C->cnt[rc][1]), A.cap_v);
+  const uint32_t nw = min(ld_agent(&C->cnt[rc][1].v), A.cap_v);
   const uint32_t pw = (nw + nwv - 1) / nwv, hw = min(nw, gw * pw + pw);
   for (uint32_t b0 = gw * pw; b0 < hw; b0 += kWave) {
     int32_t u, start, deg;
@@ -638,7 +638,7 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
     }
   }
 
-  const uint32_t ng = min(ld_agent(&C->cnt[rc][0]), A.cap_v);
+  const uint32_t ng = min(ld_agent(&C->cnt[rc][0].v), A.cap_v);
   const uint32_t pg = (ng + nwv - 1) / nwv, hg = min(ng, gw * pg + pg);
   const int grp = lane >> 4;
   for (uint32_t b0 = gw * pg; b0 < hg; b0 += kWave) {
@@ -666,7 +666,7 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
   // (e) publish the workgroup's column activity
   __syncthreads();
   if ((int)threadIdx.x < nseg && sh_colact[threadIdx.x])
-    atomicOr(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
+    or_new_bits(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
 }
 
 __device__ __forceinline__ bool any_active(const TileCtl* C, int rn, int nseg) {
@@ -694,13 +694,13 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   for (;;) {
     if (blockIdx.x == 0) tile_prologue(C, step, A.K);
     tile_compact<false>(A, step, blockIdx.x, gridDim.x, acc, csh);
-    if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
+    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       finished = true;
       break;
     }
     tile_relax<F32>(A, step, blockIdx.x, gridDim.x, sh_colact);
-    if (!grid_sync(&C->bar, &C->abort, gridDim.x, bar_base, epoch)) {
+    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
       finished = true;
       break;
@@ -759,8 +759,7 @@ __device__ __forceinline__ bool tile_is_pull_step(const TileArgs& A, uint32_t st
 // End of a step launch: the last workgroup advances the step and detects the end.
 __device__ __forceinline__ void tile_end_step(const TileArgs& A, uint32_t step, int32_t cap_n) {
   TileCtl* C = A.ctl;
-  if (last_block_done(&C->blocks_done)) {
-    st_agent(&C->blocks_done, 0u);
+  if (last_block_arrive(&C->arrive) && threadIdx.x == 0) {
     const bool act = any_active(C, (step + 1) % kRot, A.nseg);
     const uint32_t ns = step + 1;
     st_agent(&C->step, ns);
@@ -951,7 +950,7 @@ __global__ void __launch_bounds__(kPullThreads) tile_pull_kernel(TileArgs A, int
   }
   __syncthreads();
   if ((int)threadIdx.x < A.nseg && sh_colact[threadIdx.x])
-    atomicOr(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
+    or_new_bits(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
   tile_end_step(A, step, cap_n);
 }
 
@@ -1071,9 +1070,9 @@ __global__ void __launch_bounds__(1024) utile_push_kernel(TileArgs A, int32_t ca
   __syncthreads();
   const int lane = lane_id(), W = blockDim.x >> 6;
   const uint32_t gw = blockIdx.x * W + (threadIdx.x >> 6), nwv = gridDim.x * W;
-  const uint32_t n0 = min(ld_agent(&C->cnt[rc][0]), A.cap_v);
-  const uint32_t n1 = min(ld_agent(&C->cnt[rc][1]), A.cap_v);
-  const uint32_t n2 = min(ld_agent(&C->cnt[rc][2]), A.cap_wg);
+  const uint32_t n0 = min(ld_agent(&C->cnt[rc][0].v), A.cap_v);
+  const uint32_t n1 = min(ld_agent(&C->cnt[rc][1].v), A.cap_v);
+  const uint32_t n2 = min(ld_agent(&C->cnt[rc][2].v), A.cap_wg);
   // batches: 64 rows of the group tier, 64 of the wave tier, 4 row chunks
   const uint32_t b0 = (n0 + 63) / 64, b1 = b0 + (n1 + 63) / 64, b2 = b1 + (n2 + 3) / 4;
   unsigned long long colacc[S];
@@ -1112,7 +1111,7 @@ __global__ void __launch_bounds__(1024) utile_push_kernel(TileArgs A, int32_t ca
   }
   __syncthreads();
   if ((int)threadIdx.x < A.nseg && sh_colact[threadIdx.x])
-    atomicOr(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
+    or_new_bits(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
   tile_end_step(A, step, cap_n);
 }
 
@@ -1191,7 +1190,7 @@ __global__ void __launch_bounds__(kPullThreads) utile_pull_kernel(TileArgs A, in
   if (j16 < nseg && colacc) atomicOr(&sh_colact[j16], colacc);
   __syncthreads();
   if ((int)threadIdx.x < A.nseg && sh_colact[threadIdx.x])
-    atomicOr(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
+    or_new_bits(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
   tile_end_step(A, step, cap_n);
 }
 
