@@ -86,8 +86,8 @@ __global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* 
     if (old & bit) continue;  // duplicate seed
     const int32_t start = A.rowptr[s], deg = A.rowptr[s + 1] - start;
     if (deg == 0) continue;
-    atomicAdd(&C->ctr[0].fedges[0], (unsigned long long)deg);
-    atomicAdd(&C->ctr[0].frows[0], 1ull);
+    atomicAdd(&C->ctr.fedges[0], (unsigned long long)deg);
+    atomicAdd(&C->ctr.frows[0], 1ull);
     if (deg <= A.t_lane) {
       const uint32_t p = atomicAdd(&C->cnt[0][0].v, 1u);
       A.qlane[0][p] = (int32_t)s;
@@ -118,14 +118,12 @@ __global__ void ss_decode_i32_kernel(uint32_t* dist, int64_t n, const SsCtl* C,
     info->converged = 0;
 }
 
-// One wavefront: the counters summed over their stripes.
 template <int WT>
 __global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info) {
-  if (blockIdx.x != 0 || threadIdx.x >= kWave) return;
-  const unsigned long long fe = ctr_sum(C->ctr, offsetof(SsStripe, fe));
-  const unsigned long long es = ctr_sum(C->ctr, offsetof(SsStripe, es));
-  const unsigned long long im = ctr_sum(C->ctr, offsetof(SsStripe, im));
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const unsigned long long fe = ld_agent64(&C->ctr.fe);
+  const unsigned long long es = ld_agent64(&C->ctr.es);
+  const unsigned long long im = ld_agent64(&C->ctr.im);
   int32_t conv = ld_agent_i(&C->converged);
   if (ld_agent(&C->abort)) conv = -2;
   info->steps = (int32_t)ld_agent(&C->step);
@@ -380,17 +378,10 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
   const uint32_t nl = ld_agent(&C->cnt[rc][0].v);
   const uint32_t nw = ld_agent(&C->cnt[rc][1].v);
   const uint32_t ng = ld_agent(&C->cnt[rc][2].v);
-  // (uniform over the workgroup: every wavefront sums the stripes)
-  const bool pull =
-      PULL && A.T.hdr != nullptr && A.pull_min >= 0 &&
-      ctr_sum(C->ctr, offsetof(SsStripe, fedges) + rc * sizeof(unsigned long long)) >=
-          (unsigned long long)A.pull_min;
+  const bool pull = PULL && A.T.hdr != nullptr && A.pull_min >= 0 &&
+                    ld_agent64(&C->ctr.fedges[rc]) >= (unsigned long long)A.pull_min;
   if (pull) {
-    if (gb == 0 && threadIdx.x < kWave) {
-      const unsigned long long rows =
-          ctr_sum(C->ctr, offsetof(SsStripe, frows) + rc * sizeof(unsigned long long));
-      if (threadIdx.x == 0) acc.fe += rows;
-    }
+    if (gb == 0 && threadIdx.x == 0) acc.fe += ld_agent64(&C->ctr.frows[rc]);
     ss_pull<WT>(A, cur, nxt, rn, gw, nwv, acc, sh);
   } else {
 
@@ -520,15 +511,12 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
   return pull;
 }
 
-// Threads 0 .. kCtrStripes-1 of one workgroup.
 __device__ __forceinline__ void ss_zero_rotation(SsCtl* C, uint32_t step) {
   const int rz = (step + 2) % kRot;
-  if (threadIdx.x == 0) {
-    for (int t = 0; t < 4; t++) st_agent(&C->cnt[rz][t].v, 0u);
-    st_agent(&C->upd[rz], 0u);
-  }
-  st_agent64(&C->ctr[threadIdx.x].fedges[rz], 0ull);
-  st_agent64(&C->ctr[threadIdx.x].frows[rz], 0ull);
+  for (int t = 0; t < 4; t++) st_agent(&C->cnt[rz][t].v, 0u);
+  st_agent(&C->upd[rz], 0u);
+  st_agent64(&C->ctr.fedges[rz], 0ull);
+  st_agent64(&C->ctr.frows[rz], 0ull);
 }
 
 // All steps in one launch; a grid barrier separates the steps.  The grid must
@@ -544,7 +532,7 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
   uint32_t step = ld_agent(&C->step);
   int32_t status = 1;
   for (;;) {
-    if (blockIdx.x == 0 && threadIdx.x < kCtrStripes) ss_zero_rotation(C, step);
+    if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
     ss_step<WT, false>(A, step, blockIdx.x, gridDim.x, acc, sh);
     if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch)) {
       status = -2;
@@ -555,7 +543,7 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
     if (!upd) { status = 1; break; }
     if (step >= (uint32_t)A.n) { status = 0; break; }
   }
-  SsStripe& S = C->ctr[blockIdx.x % kCtrStripes];
+  SsCounters& S = C->ctr;
   flush_acc(acc, &S.fe, &S.es, &S.im, nullptr, nullptr);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st_agent(&C->step, step);
@@ -572,11 +560,11 @@ __global__ void __launch_bounds__(1024) ss_step_kernel(SsArgs A) {
   SsCtl* C = A.ctl;
   if (ld_agent(&C->done)) return;
   const uint32_t step = ld_agent(&C->step);
-  if (blockIdx.x == 0 && threadIdx.x < kCtrStripes) ss_zero_rotation(C, step);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
   Acc acc;
   const bool pulled = ss_step<WT, PULL>(A, step, blockIdx.x, gridDim.x, acc, sh);
   // counters, and the next frontier's out-edges and rows (its pull decision)
-  SsStripe& S = C->ctr[blockIdx.x % kCtrStripes];
+  SsCounters& S = C->ctr;
   flush_acc(acc, &S.fe, &S.es, &S.im, &S.fedges[(step + 1) % kRot], &S.frows[(step + 1) % kRot]);
   if (last_block_arrive(&C->arrive)) {
     // a pull step read the current bitmap throughout: clear it now, before it
@@ -740,7 +728,7 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
   }
   // counters, state and run info
   // thread i zeroes the counter that it then adds to (flush_acc: fe, es, im)
-  SsStripe& S = C->ctr[0];  // one workgroup: one stripe
+  SsCounters& S = C->ctr;
   if (threadIdx.x == 0) st_agent64(&S.fe, 0ull);
   if (threadIdx.x == 1) st_agent64(&S.es, 0ull);
   if (threadIdx.x == 2) st_agent64(&S.im, 0ull);
@@ -910,7 +898,7 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
     for (int i = threadIdx.x; i < n; i += blockDim.x) A.dist[i] = sh.dist[i];
   }
   // thread i zeroes the counter that it then adds to (flush_acc: fe, es, im)
-  SsStripe& S = C->ctr[0];  // one workgroup: one stripe
+  SsCounters& S = C->ctr;
   if (threadIdx.x == 0) st_agent64(&S.fe, 0ull);
   if (threadIdx.x == 1) st_agent64(&S.es, 0ull);
   if (threadIdx.x == 2) st_agent64(&S.im, 0ull);
