@@ -251,7 +251,8 @@ def c5(args, dawn, torch, np):
 
     def new_server():
         srv = serve.Server(tile_k=args.c5_tile_k, steps_per_tick=args.c5_steps_per_tick,
-                           max_tiles_per_graph=2, pull=not args.c5_no_pull)
+                           max_tiles_per_graph=2, pull=not args.c5_no_pull,
+                           graphs=not args.c5_no_graphs)
         for i, c in enumerate(csrs):
             srv.add_graph(i, c)
         return srv
@@ -267,7 +268,8 @@ def c5(args, dawn, torch, np):
     cap = len(qs) / (time.perf_counter() - t0)
     closed = serve.percentiles([q.latency for q in qs])
     recs = [{"config": "c5_serving_closed_loop", "graphs": len(graphs), "queries": len(qs),
-             "pull": not args.c5_no_pull, "capacity_qps": cap, **closed}]
+             "pull": not args.c5_no_pull, "graphs": not args.c5_no_graphs, "capacity_qps": cap,
+             **closed}]
     log(f"c5 closed-loop capacity {cap:.1f} queries/s")
     for frac in args.c5_rates:
         rate = frac * cap
@@ -386,6 +388,8 @@ def main() -> int:
     ap.add_argument("--c5-queries", type=int, default=2000)
     ap.add_argument("--c5-tile-k", type=int, default=64)
     ap.add_argument("--c5-no-pull", action="store_true", help="serve with push steps only")
+    ap.add_argument("--c5-no-graphs", action="store_true",
+                    help="launch each tick's steps one by one instead of replaying a captured run")
     ap.add_argument("--c5-pull-src", type=int, default=None,
                     help="tuning tile_pull_src while serving (default: the library's)")
     ap.add_argument("--c5-steps-per-tick", type=int, default=4)

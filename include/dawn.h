@@ -356,17 +356,29 @@ dawn_status dawn_tile_create(dawn_tile** out, const int32_t* rowptr_dev, const i
                              int32_t k, hipStream_t stream);
 /* Start query `source` in free column col (0..k-1). */
 dawn_status dawn_tile_admit(dawn_tile* t, int32_t col, int32_t source, hipStream_t stream);
-/* Run up to max_steps GOVM steps for every admitted column (steps stop early
- * on the device once no column is active).  If done_bits_dev is non-NULL it
- * receives ceil(k/32) uint32 words (bit j of word j/32) with the bits of
- * admitted columns that have finished set. */
 /* Attach the reverse graph of the session's CSR (dawn_tgraph_build, with
  * weights), or detach it with NULL: later runs take pull steps on dense
  * frontiers (tuning field tile_pull), with identical results.  The caller
  * keeps the buffer alive while it is attached. */
 dawn_status dawn_tile_set_tgraph(dawn_tile* t, const void* tgraph_dev);
+/* Run up to max_steps GOVM steps for every admitted column (steps stop early
+ * on the device once no column is active).  If done_bits_dev is non-NULL it
+ * receives ceil(k/32) uint32 words (bit j of word j/32) with the bits of
+ * admitted columns that have finished set. */
 dawn_status dawn_tile_run(dawn_tile* t, int32_t max_steps, uint32_t* done_bits_dev,
                           hipStream_t stream);
+/* Capture the launches of dawn_tile_run(t, max_steps, done_bits_dev) once into
+ * a HIP graph held by the session; dawn_tile_replay enqueues that graph on
+ * `stream`, doing what the same dawn_tile_run call does (one graph launch
+ * instead of 3 * max_steps + 1 kernel launches, for a server that runs the
+ * same step chunk of a tile every tick).  Every run reads its state from
+ * device memory, so admissions, evictions and reads between replays are
+ * fine.  The graph keeps the tuning, the attached reverse graph and
+ * done_bits_dev as they were at capture: capture again after changing them.
+ * A new capture replaces the previous one; dawn_tile_destroy frees it.
+ * Replay without a capture: DAWN_E_INVALID. */
+dawn_status dawn_tile_capture(dawn_tile* t, int32_t max_steps, uint32_t* done_bits_dev);
+dawn_status dawn_tile_replay(dawn_tile* t, hipStream_t stream);
 /* Copy column col (n distances) to dist_out_dev; valid once the column is done. */
 dawn_status dawn_tile_read(dawn_tile* t, int32_t col, void* dist_out_dev, hipStream_t stream);
 /* Per-column step counts (int32[k], k as given to dawn_tile_create) to steps_out_dev. */

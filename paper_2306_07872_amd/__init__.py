@@ -106,6 +106,8 @@ def load():
                              _i32),
         "dawn_tile_admit": ([_vp, _i32, _i32, _vp], _i32),
         "dawn_tile_run": ([_vp, _i32, _vp, _vp], _i32),
+        "dawn_tile_capture": ([_vp, _i32, _vp], _i32),
+        "dawn_tile_replay": ([_vp, _vp], _i32),
         "dawn_tile_read": ([_vp, _i32, _vp, _vp], _i32),
         "dawn_tile_steps": ([_vp, _vp, _vp], _i32),
         "dawn_tile_evict": ([_vp, _i32, _vp], _i32),
@@ -132,7 +134,8 @@ def exported_symbols() -> list[str]:
         "dawn_tgraph_bytes", "dawn_tgraph_build_bytes", "dawn_tgraph_build", "dawn_msssp_tg_ws",
         "dawn_umsssp_workspace_bytes", "dawn_umsssp_ws", "dawn_batch_create", "dawn_batch_sizes", "dawn_batch_vertex_offset", "dawn_batch_run",
         "dawn_batch_capture", "dawn_batch_replay", "dawn_batch_destroy", "dawn_tile_bytes",
-        "dawn_tile_create", "dawn_tile_admit", "dawn_tile_run", "dawn_tile_read",
+        "dawn_tile_create", "dawn_tile_admit", "dawn_tile_run", "dawn_tile_capture",
+        "dawn_tile_replay", "dawn_tile_read",
         "dawn_tile_set_tgraph",
         "dawn_tile_steps", "dawn_tile_evict", "dawn_tile_destroy", "dawn_kernel_timer",
         "dawn_kernel_time", "dawn_device_query"]
@@ -497,6 +500,15 @@ class Tile:
         """Enqueue up to max_steps steps; the done bits land in self.done_buf."""
         _check(load().dawn_tile_run(self._h, int(max_steps), _ptr(self.done_buf),
                                     _stream(stream)))
+        return self.done_buf
+
+    def capture(self, max_steps: int):
+        """Capture run(max_steps) once as a HIP graph (done bits to self.done_buf)."""
+        _check(load().dawn_tile_capture(self._h, int(max_steps), _ptr(self.done_buf)))
+
+    def replay(self, stream=None):
+        """Enqueue the captured run; returns self.done_buf."""
+        _check(load().dawn_tile_replay(self._h, _stream(stream)))
         return self.done_buf
 
     def read(self, col: int, out=None, stream=None):

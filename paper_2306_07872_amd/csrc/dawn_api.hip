@@ -139,6 +139,9 @@ void* ktimer_begin(hipStream_t stream) {
     std::lock_guard<std::mutex> lk(g_timer_mu);
     if (!g_timer_on) return nullptr;
   }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return nullptr;  // a captured launch sequence carries no timing events
   TimedLaunch* t = new TimedLaunch();
   if (hipEventCreate(&t->a) != hipSuccess || hipEventCreate(&t->b) != hipSuccess) {
     delete t;
@@ -759,7 +762,18 @@ struct dawn_tile {
   bool f32 = false;
   int32_t k = 0;
   const void* tgraph = nullptr;  // reverse graph for pull steps, or null
+  // a captured run (dawn_tile_capture)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
+
+static void tile_graph_free(dawn_tile* t) {
+  if (t->exec) hipGraphExecDestroy(t->exec);
+  if (t->graph) hipGraphDestroy(t->graph);
+  t->exec = nullptr;
+  t->graph = nullptr;
+}
 
 extern "C" size_t dawn_tile_bytes(int32_t n, int32_t m, int32_t k) {
   if (n < 1 || m < 0 || k < 1 || k > DAWN_TILE_K_MAX) return 0;
@@ -802,10 +816,9 @@ extern "C" dawn_status dawn_tile_admit(dawn_tile* t, int32_t col, int32_t source
   return tile_admit(t->A, t->f32, col, source, stream);
 }
 
-extern "C" dawn_status dawn_tile_run(dawn_tile* t, int32_t max_steps, uint32_t* done_bits,
-                                     hipStream_t stream) {
-  if (!t) return set_error(DAWN_E_INVALID, "null tile");
-  if (max_steps < 1) return set_error(DAWN_E_INVALID, "max_steps must be >= 1");
+// The launches of one run: max_steps step launches, then the done bits.
+static dawn_status tile_run_enqueue(dawn_tile* t, int32_t max_steps, uint32_t* done_bits,
+                                    hipStream_t stream) {
   TileArgs a = t->A;
   if (t->tgraph && g_tuning.tile_pull <= 1000) {
     a.T = tgraph_view(t->tgraph, a.n, a.m);
@@ -816,6 +829,48 @@ extern "C" dawn_status dawn_tile_run(dawn_tile* t, int32_t max_steps, uint32_t* 
   if (st != DAWN_OK) return st;
   if (done_bits) st = tile_done_bits(t->A, t->k, done_bits, stream);
   return st;
+}
+
+extern "C" dawn_status dawn_tile_run(dawn_tile* t, int32_t max_steps, uint32_t* done_bits,
+                                     hipStream_t stream) {
+  if (!t) return set_error(DAWN_E_INVALID, "null tile");
+  if (max_steps < 1) return set_error(DAWN_E_INVALID, "max_steps must be >= 1");
+  return tile_run_enqueue(t, max_steps, done_bits, stream);
+}
+
+// The run's launch sequence holds only kernel launches that read the run's
+// state from device memory (step, done flag, masks, column words), so one
+// captured sequence serves every later run of the session, whatever columns
+// were admitted or evicted in between.
+extern "C" dawn_status dawn_tile_capture(dawn_tile* t, int32_t max_steps, uint32_t* done_bits) {
+  if (!t) return set_error(DAWN_E_INVALID, "null tile");
+  if (max_steps < 1) return set_error(DAWN_E_INVALID, "max_steps must be >= 1");
+  tile_graph_free(t);
+  dawn_status st;
+  if (!t->cap_stream &&
+      (st = hip_check(hipStreamCreateWithFlags(&t->cap_stream, hipStreamNonBlocking),
+                      "hipStreamCreate")) != DAWN_OK)
+    return st;
+  if ((st = hip_check(hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeThreadLocal),
+                      "begin capture")) != DAWN_OK)
+    return st;
+  const dawn_status rs = tile_run_enqueue(t, max_steps, done_bits, t->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(t->cap_stream, &g);
+  if (rs != DAWN_OK) {
+    if (g) hipGraphDestroy(g);
+    return rs;
+  }
+  if ((st = hip_check(e, "end capture")) != DAWN_OK) return st;
+  t->graph = g;
+  st = hip_check(hipGraphInstantiate(&t->exec, g, nullptr, nullptr, 0), "graph instantiate");
+  if (st != DAWN_OK) tile_graph_free(t);
+  return st;
+}
+
+extern "C" dawn_status dawn_tile_replay(dawn_tile* t, hipStream_t stream) {
+  if (!t || !t->exec) return set_error(DAWN_E_INVALID, "tile has no captured run");
+  return hip_check(hipGraphLaunch(t->exec, stream), "graph launch");
 }
 
 extern "C" dawn_status dawn_tile_set_tgraph(dawn_tile* t, const void* tgraph) {
@@ -846,6 +901,8 @@ extern "C" dawn_status dawn_tile_evict(dawn_tile* t, int32_t col, hipStream_t st
 
 extern "C" void dawn_tile_destroy(dawn_tile* t) {
   if (!t) return;
+  tile_graph_free(t);
+  if (t->cap_stream) hipStreamDestroy(t->cap_stream);
   hipFree(t->ws);
   delete t;
 }

@@ -12,7 +12,8 @@ ticks:
    their graph; a graph without a free column gets a new tile if the HBM
    budget still holds it, otherwise its queries wait;
 3. run: every tile with live columns that is not already running gets
-   `steps_per_tick` GOVM steps enqueued on its own stream, followed by an
+   `steps_per_tick` GOVM steps enqueued on its own stream (by default as one
+   replay of a HIP graph captured at the tile's first run), followed by an
    asynchronous copy of its done bits and an event.
 
 A tile takes new columns also while a run of it is in flight: the admission
@@ -65,7 +66,7 @@ class Query:
 class GpuTileExecutor:
     """One HIP tile session with its own stream, pinned host buffers and events."""
 
-    def __init__(self, csr: Csr, k: int, device="cuda", tgraph=None):
+    def __init__(self, csr: Csr, k: int, device="cuda", tgraph=None, graphs: bool = True):
         import torch
         self.torch = torch
         self.csr = csr
@@ -78,6 +79,10 @@ class GpuTileExecutor:
         self.done_host = torch.zeros((k + 31) // 32, dtype=torch.int32, pin_memory=True)
         self.nbytes = tile_bytes(csr.n, csr.m, k)
         self._run_event = None
+        # graphs: a run of s steps is captured once as a HIP graph and
+        # replayed (one launch per tick instead of 3 s + 1)
+        self.graphs = graphs
+        self._captured = None
 
     # -- steps ---------------------------------------------------------------
     def admit(self, col: int, source: int):
@@ -88,7 +93,13 @@ class GpuTileExecutor:
 
     def launch(self, steps: int):
         torch = self.torch
-        done = self.tile.run(steps, stream=self.stream)
+        if self.graphs:
+            if self._captured != steps:
+                self.tile.capture(steps)
+                self._captured = steps
+            done = self.tile.replay(stream=self.stream)
+        else:
+            done = self.tile.run(steps, stream=self.stream)
         with torch.cuda.stream(self.stream):
             self.done_host.copy_(done, non_blocking=True)
             ev = torch.cuda.Event()
@@ -155,7 +166,7 @@ class Server:
 
     def __init__(self, hbm_budget: int | None = None, tile_k: int = 64, steps_per_tick: int = 4,
                  max_tiles_per_graph: int = 4, tile_factory=None, clock=time.perf_counter,
-                 device="cuda", pull: bool = True):
+                 device="cuda", pull: bool = True, graphs: bool = True):
         self.graphs: dict[int, Csr] = {}
         # pull steps need each graph's reverse graph, built when the graph is
         # added and resident with it (like the CSR, outside the tile budget);
@@ -168,7 +179,8 @@ class Server:
         self.clock = clock
         self.tile_factory = tile_factory or (
             lambda csr, k: GpuTileExecutor(csr, k, device,
-                                           getattr(csr, "_tgraph", None) if self.pull else None))
+                                           getattr(csr, "_tgraph", None) if self.pull else None,
+                                           graphs))
         if hbm_budget is None:
             import torch
             free, _ = torch.cuda.mem_get_info()

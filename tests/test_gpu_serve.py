@@ -10,31 +10,33 @@ from gpu_helpers import announce, assert_sssp_matches, to_np
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("pull", [False, True])
-def test_server_mix_equals_alone(dawn, pull):
+@pytest.mark.parametrize("pull,graphs", [(False, False), (False, True), (True, True)])
+def test_server_mix_equals_alone(dawn, pull, graphs):
     """pull=True: the tiles take pull steps (from 5 % of the edges in the
-    frontier) while queries join and leave them."""
+    frontier) while queries join and leave them.  graphs=True: each tick's
+    steps are a replay of the tile's captured run."""
     prev = dawn.set_tuning(tile_pull=50, tile_pull_src=0) if pull else None
     try:
-        _mix_equals_alone(dawn, pull)
+        _mix_equals_alone(dawn, pull, graphs)
     finally:
         if prev is not None:
             dawn.set_tuning(**prev)
 
 
-def _mix_equals_alone(dawn, pull):
+def _mix_equals_alone(dawn, pull, graphs):
     import torch
     from paper_2306_07872_amd import serve
     gs = [graphgen.rmat(12, 8, 40, weights="u32"),
           graphgen.rmat(13, 16, 41, weights="f32lognormal"),
           graphgen.grid(48, 40, 0.01, 42, weights="f32unit")]
     csrs = [dawn.Csr.from_graph(g) for g in gs]
-    srv = serve.Server(tile_k=64, steps_per_tick=3, max_tiles_per_graph=2, pull=pull)
+    srv = serve.Server(tile_k=64, steps_per_tick=3, max_tiles_per_graph=2, pull=pull,
+                       graphs=graphs)
     for i, c in enumerate(csrs):
         srv.add_graph(i, c)
     rng = np.random.default_rng(7)
     qs = []
-    announce("server mix: 3 graphs, 90 queries, pull", pull)
+    announce("server mix: 3 graphs, 90 queries, pull", pull, "graphs", graphs)
     for t in range(90):
         gi = int(rng.integers(0, 3))
         src = int(graphgen.pick_sources(gs[gi], 1, 1000 + t)[0])
@@ -94,3 +96,53 @@ def test_server_cancel_running_query(dawn):
     for q in (b, c):
         assert_sssp_matches(g, q.source, q.result, tag=f"cancel-mix q{q.qid}")
     srv.close()
+
+
+@pytest.mark.parametrize("pull", [False, True])
+def test_tile_replay_equals_run(dawn, pull):
+    """A captured run replayed tick after tick, with admissions, reads and
+    eager work on the stream between replays, does what dawn_tile_run does:
+    after every replay, each column it reports done holds the lone query's
+    distances, as in an eagerly run twin tile.  (The step at which a column
+    finishes may differ between the two: a step relaxes in place, so a
+    distance lowered earlier in the same step can carry further.)"""
+    import torch
+    g = graphgen.rmat(12, 16, 61, weights="u32")
+    csr = dawn.Csr.from_graph(g)
+    srcs = [int(s) for s in graphgen.pick_sources(g, 6, 62)]
+    alone = {c: None for c in range(len(srcs))}
+    prev = dawn.set_tuning(tile_pull=50, tile_pull_src=0) if pull else None
+    try:
+        tg = dawn.tgraph(csr) if pull else None
+        tiles = {"replay": dawn.Tile(csr, 64), "run": dawn.Tile(csr, 64)}
+        if pull:
+            for t in tiles.values():
+                t.set_tgraph(tg)
+        tiles["replay"].capture(2)
+        announce("tile replay vs run, pull", pull)
+        done = {name: set() for name in tiles}
+        for tick in range(40):
+            if tick < len(srcs):            # one admission per tick, into both tiles
+                for t in tiles.values():
+                    t.admit(tick, srcs[tick])
+            bits = {"replay": to_np(tiles["replay"].replay()).copy(),
+                    "run": to_np(tiles["run"].run(2)).copy()}
+            torch.cuda.synchronize()
+            for name, t in tiles.items():
+                for c in range(min(tick + 1, len(srcs))):
+                    if c in done[name] or not (int(bits[name][c // 32]) >> (c % 32)) & 1:
+                        continue
+                    done[name].add(c)
+                    if alone[c] is None:
+                        alone[c] = to_np(dawn.sssp(csr, srcs[c]))
+                    x = to_np(t.read(c))
+                    torch.cuda.synchronize()
+                    assert np.array_equal(x, alone[c]), (name, tick, c)
+            if all(len(d) == len(srcs) for d in done.values()):
+                break
+        assert all(len(d) == len(srcs) for d in done.values()), done
+        for t in tiles.values():
+            t.close()
+    finally:
+        if prev is not None:
+            dawn.set_tuning(**prev)
