@@ -128,7 +128,8 @@ typedef struct {
  * mode: 0 auto: single source and batches of graphs run in one workgroup
  * when m <= small_m; with m >= step_min_m edges as `host_check` step launches
  * followed, if the run has not ended by then, by one persistent launch for
- * the rest; otherwise (and when captured) as one persistent launch; tiles: 1.
+ * the rest (a captured run enqueues both without waiting: launches after the
+ * run has ended return at once); otherwise as one persistent launch; tiles: 1.
  * 1 step
  * launches (one kernel per step; the host checks termination every
  * `host_check` steps -- for tiles, the first two checks after host_check / 4
@@ -332,7 +333,8 @@ dawn_status dawn_batch_run(dawn_batch* b, const int32_t* sources_dev, void* dist
                            dawn_run_info* info_dev, hipStream_t stream);
 /* Capture dawn_batch_run(b, sources_dev, dist_out_dev, info_dev) into a HIP
  * graph once; dawn_batch_replay launches it again (the device buffers named
- * at capture are re-read, so new source ids written there take effect). */
+ * at capture are re-read, so new source ids written there take effect).
+ * DAWN_E_UNSUPPORTED under tuning mode 1 (step launches with host checks). */
 dawn_status dawn_batch_capture(dawn_batch* b, const int32_t* sources_dev, void* dist_out_dev,
                                dawn_run_info* info_dev, hipStream_t stream);
 dawn_status dawn_batch_replay(dawn_batch* b, hipStream_t stream);

@@ -707,8 +707,8 @@ extern "C" dawn_status dawn_batch_run(dawn_batch* b, const int32_t* sources, voi
 extern "C" dawn_status dawn_batch_capture(dawn_batch* b, const int32_t* sources, void* dist_out,
                                           dawn_run_info* info, hipStream_t stream) {
   if (!b || !sources || !dist_out) return set_error(DAWN_E_INVALID, "null pointer");
-  const int mode = g_tuning.mode == 0 ? 2 : g_tuning.mode;
-  if (mode != 2) return set_error(DAWN_E_UNSUPPORTED, "capture needs the persistent mode");
+  if (g_tuning.mode == 1)
+    return set_error(DAWN_E_UNSUPPORTED, "step launches alone (mode 1) cannot be captured");
   dawn_status st;
   if (b->exec) {
     hipGraphExecDestroy(b->exec);

@@ -970,7 +970,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
                             hipStream_t stream, bool capture) {
   const Tuning& T = tuning();
   const DevInfo& di = dev_info();
-  const int auto_threads = (T.mode == 0 && !capture && (int64_t)A.m >= (int64_t)T.step_min_m) ||
+  const int auto_threads = (T.mode == 0 && (int64_t)A.m >= (int64_t)T.step_min_m) ||
                                    T.mode == 1
                                ? 512
                                : 1024;
@@ -1015,16 +1015,27 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
   // mode 0 on graphs of at least step_min_m edges: step launches for the
   // first `host_check` steps (such runs, with few large steps, mostly finish
   // there), then -- if the run goes on -- one persistent launch for the rest;
-  // smaller graphs, and captured runs (which cannot wait on the host), use the
-  // persistent launch at once.  Measured on MI355X: on R-MAT scale 22 (67M
-  // edges) step launches of 512-thread workgroups take a third of the time of
-  // the persistent launch; on 16.7M-edge graphs (R-MAT scale 20, the 2048^2
-  // grid) the persistent launch of 1024-thread workgroups is faster.
+  // smaller graphs use the persistent launch at once.  Measured on MI355X: on
+  // R-MAT scale 22 (67M edges) step launches of 512-thread workgroups take a
+  // third of the time of the persistent launch; on 16.7M-edge graphs (R-MAT
+  // scale 20, the 2048^2 grid) the persistent launch of 1024-thread workgroups
+  // is faster.  A captured run cannot wait on the host: it always enqueues the
+  // `host_check` step launches and the persistent launch, and every launch
+  // after the run has finished returns at once.
   int mode = T.mode;
-  if (mode == 0) mode = (capture || (int64_t)A.m < (int64_t)T.step_min_m) ? 2 : 3;
+  if (mode == 0) mode = (int64_t)A.m < (int64_t)T.step_min_m ? 2 : 3;
   bool finished = false;
-  if (mode == 1 || mode == 3) {
-    if (capture) return set_error(DAWN_E_UNSUPPORTED, "step launches cannot be captured");
+  if (mode == 1 && capture)
+    return set_error(DAWN_E_UNSUPPORTED, "step launches alone (mode 1) cannot be captured");
+  if ((mode == 1 || mode == 3) && capture) {
+    const int grid = T.grid > 0 ? T.grid : 4 * di.cus;
+    auto stepk = A.pull_min >= 0 ? ss_step_kernel<WT, true> : ss_step_kernel<WT, false>;
+    const int64_t chunk = std::min<int64_t>(T.host_check, (int64_t)A.n + 1);
+    for (int64_t s = 0; s < chunk; s++)
+      hipLaunchKernelGGL(stepk, dim3(grid), dim3(threads), 0, stream, A);
+    st = hip_check(hipGetLastError(), "step launches");
+    if (st != DAWN_OK) return st;
+  } else if (mode == 1 || mode == 3) {
     const int grid = T.grid > 0 ? T.grid : 4 * di.cus;
     auto stepk = A.pull_min >= 0 ? ss_step_kernel<WT, true> : ss_step_kernel<WT, false>;
     PinnedWord done;

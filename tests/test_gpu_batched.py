@@ -141,9 +141,41 @@ def test_batch_union_matches_each_graph(dawn):
     b.close()
 
 
-def test_batch_graph_capture_replay(dawn):
+# captured: the persistent launch alone; step launches then the persistent
+# launch for the rest (host_check 3); step launches covering every step, the
+# persistent launch returning at once (host_check 64)
+CAPTURE_TUNINGS = [dict(), dict(small_m=0, step_min_m=0, host_check=3),
+                   dict(small_m=0, step_min_m=0, host_check=64)]
+
+
+@pytest.mark.parametrize("ti", range(len(CAPTURE_TUNINGS)))
+def test_batch_graph_capture_replay(dawn, ti):
     """Captured once, replayed with new sources written into the same buffer;
     every replay (with eager work in between) matches a fresh eager run."""
+    prev = dawn.set_tuning(**CAPTURE_TUNINGS[ti]) if CAPTURE_TUNINGS[ti] else None
+    try:
+        _capture_replay(dawn, ti)
+    finally:
+        if prev is not None:
+            dawn.set_tuning(**prev)
+
+
+def test_batch_capture_rejects_step_launches_alone(dawn):
+    import torch
+    gs = _batch_graphs(count=2, seed=3)
+    b = dawn.Batch([dawn.Csr.from_graph(g) for g, _ in gs])
+    srcs = torch.tensor([s for _, s in gs], dtype=torch.int32, device="cuda")
+    out = torch.empty(b.total_n, dtype=torch.float32, device="cuda")
+    prev = dawn.set_tuning(mode=1)
+    try:
+        with pytest.raises(dawn.DawnError):
+            b.capture(srcs, out)
+    finally:
+        dawn.set_tuning(**prev)
+        b.close()
+
+
+def _capture_replay(dawn, ti):
     import torch
     gs = _batch_graphs(count=6, seed=9)
     csrs = [dawn.Csr.from_graph(g) for g, _ in gs]
@@ -151,7 +183,7 @@ def test_batch_graph_capture_replay(dawn):
     srcs = torch.tensor([s for _, s in gs], dtype=torch.int32, device="cuda")
     out = torch.empty(b.total_n, dtype=torch.float32, device="cuda")
     info = dawn.info_tensor()
-    announce("batch capture")
+    announce("batch capture", CAPTURE_TUNINGS[ti])
     b.capture(srcs, out, info=info)
     rng = np.random.default_rng(1)
     for rep in range(4):
