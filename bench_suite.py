@@ -223,7 +223,9 @@ def c4b(args, dawn, torch, np):
             "graphs_per_s_batch": len(gs) / t_batch, "graphs_per_s_replay": len(gs) / t_graph,
             "graphs_per_s_plain": len(gs) / t_plain,
             "aggregate_gteps_batch": work / t_batch / 1e9,
-            "aggregate_gteps_plain": work / t_plain / 1e9}
+            "aggregate_gteps_plain": work / t_plain / 1e9,
+            "edges_scanned": i["edges_scanned"], "mu_e": i["edges_scanned"] / max(work, 1),
+            "frontier_entries": i["frontier_entries"], "improvements": i["improvements"]}
 
 
 def c5(args, dawn, torch, np):
