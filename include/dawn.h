@@ -377,7 +377,8 @@ dawn_status dawn_tile_run(dawn_tile* t, int32_t max_steps, uint32_t* done_bits_d
  * device memory, so admissions, evictions and reads between replays are
  * fine.  The graph keeps the tuning, the attached reverse graph and
  * done_bits_dev as they were at capture: capture again after changing them.
- * A new capture replaces the previous one; dawn_tile_destroy frees it.
+ * A new capture replaces the previous one and dawn_tile_destroy frees it:
+ * call either only once the replays already enqueued have finished.
  * Replay without a capture: DAWN_E_INVALID. */
 dawn_status dawn_tile_capture(dawn_tile* t, int32_t max_steps, uint32_t* done_bits_dev);
 dawn_status dawn_tile_replay(dawn_tile* t, hipStream_t stream);
