@@ -146,3 +146,15 @@ def test_tile_replay_equals_run(dawn, pull):
     finally:
         if prev is not None:
             dawn.set_tuning(**prev)
+
+
+def test_tile_replay_without_capture_is_rejected(dawn):
+    g = graphgen.rmat(8, 8, 63, weights="u32")
+    t = dawn.Tile(dawn.Csr.from_graph(g), 64)
+    try:
+        with pytest.raises(dawn.DawnError):
+            t.replay()
+        with pytest.raises(dawn.DawnError):
+            t.capture(0)
+    finally:
+        t.close()
