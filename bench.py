@@ -36,8 +36,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "tile_step_kernel_rmat20_k256_traffic.md")
+# every source that shapes the relaxation kernels or their launches (grids,
+# launch sequence, tile layout)
 KERNEL_SOURCES = ("paper_2306_07872_amd/csrc/govm_tile.hip",
-                  "paper_2306_07872_amd/csrc/govm_device.hpp")
+                  "paper_2306_07872_amd/csrc/govm_device.hpp",
+                  "paper_2306_07872_amd/csrc/govm_host.hpp",
+                  "paper_2306_07872_amd/csrc/dawn_api.hip")
 
 
 def kernel_sources_sha256() -> str:
@@ -50,7 +54,7 @@ def kernel_sources_sha256() -> str:
 
 # tuning fields that shape the tile's launches (the others only concern
 # single-source runs)
-TILE_TUNING_KEYS = ("wg_threads", "grid", "mode", "host_check", "tile_k", "tile_t_wave",
+TILE_TUNING_KEYS = ("wg_threads", "grid", "mode", "tile_step_launches", "tile_k", "tile_t_wave",
                     "tile_t_chunk", "tile_t_group", "tile_skip", "tile_sparse")
 
 
@@ -80,6 +84,26 @@ def measured_traffic(tuning: dict, workload: str):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def reach_edges(torch, dist, outdeg, inf):
@@ -120,7 +144,13 @@ def main() -> int:
     ap.add_argument("--no-pull", action="store_true",
                     help="no reverse graph: every tile step pushes")
     ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
-                    help="library tuning field (see dawn_tuning), repeatable")
+                    help="library tuning field (see dawn_tuning), repeatable; implies "
+                         "--no-autotune")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the library's default tuning only (no autotuner)")
+    ap.add_argument("--calibration-scale", type=int, default=18,
+                    help="R-MAT scale of the autotuner's calibration graph (same generator, "
+                         "edge factor and weights as the workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of this many MiB (a kernel "
                          "of known traffic, to scale profiler byte counters)")
@@ -166,25 +196,64 @@ def main() -> int:
     src_t = torch.as_tensor(srcs, dtype=torch.int32, device="cuda")
     k = int(src_t.numel())
     out = torch.empty((k, g.n), dtype=torch.uint32, device="cuda")
-    ws = dawn.workspace(dawn.msssp_workspace_bytes(g.n, g.m, k))
     info = dawn.info_tensor()
-    tune = dawn.get_tuning()
 
-    # ---- batched: warmup, then K timed steps --------------------------------
-    for _ in range(args.warmup):
-        dawn.msssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg)
-    torch.cuda.synchronize()
-    dawn.kernel_timer(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        dawn.msssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dawn.kernel_timer(False)
-    k_ms, k_launches = dawn.kernel_time()
-    inf = dawn.read_info(info)
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    # ---- autotuner: launch parameters found on a calibration graph of the same
+    # class (R-MAT, edge factor 16, uint32 [1,255], a smaller scale), applied
+    # to the workload; the default tuning is timed beside it
+    autotuned = None
+    if not args.no_autotune and not args.tune:
+        import tempfile
+
+        from paper_2306_07872_amd import autotune
+        cache_dir = tempfile.mkdtemp(prefix="dawn_tune_")
+        os.environ.setdefault("DAWN_TUNE_CACHE", os.path.join(cache_dir, "tune.json"))
+        gc, sc = workloads.rmat20_tile(seed=18, k=args.k, scale=args.calibration_scale)
+        cal = dawn.Csr.from_graph(gc)
+        tgc = dawn.tgraph(cal) if tg is not None else None
+        t_tune = time.perf_counter()
+        autotuned = autotune.tune_cached(csr, sc, "msssp", calibration=cal, tgraph=tgc, reps=3)
+        t_tune = time.perf_counter() - t_tune
+        log(f"autotune ({t_tune:.1f}s) key {autotuned['key']}: {autotuned['tuning']} "
+            f"({autotuned['sources_per_s']:.0f} vs default "
+            f"{autotuned['default_sources_per_s']:.0f} sources/s on the calibration graph)")
+        del cal, tgc
+
+    def timed(label):
+        """Warmup, then the timed steps of the batched call; kernel events on."""
+        for _ in range(args.warmup):
+            dawn.msssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg, check=False)
+        torch.cuda.synchronize()
+        dawn.kernel_timer(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dawn.msssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg, check=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dawn.kernel_timer(False)
+        k_ms, k_launches = dawn.kernel_time()
+        inf = dawn.read_info(info)
+        ms = (t1 - t0) * 1e3 / args.steps
+        log(f"batched ({label}): {ms:.3f} ms/step, kernel {k_ms / max(k_launches, 1):.3f} "
+            f"ms/launch, info {inf}")
+        return ms, k_ms, k_launches, inf
+
+    default_ms = None
+    if autotuned is not None:
+        dawn.set_tuning(reset=True)
+        ws = dawn.workspace(dawn.msssp_workspace_bytes(g.n, g.m, k))
+        default_ms, _, _, dinf = timed("default tuning")
+        if dinf["converged"] != 1:
+            log(f"batched run did not converge (status {dinf['converged']})")
+            return 1
+        autotune.apply(autotuned)
+    tune = dawn.get_tuning()
+    ws = dawn.workspace(dawn.msssp_workspace_bytes(g.n, g.m, k))
+    ms_step, k_ms, k_launches, inf = timed("autotuned" if autotuned is not None else "as set")
+    if inf["converged"] != 1:
+        log(f"batched run did not converge (status {inf['converged']}): no figure is reported")
+        return 1
     log(f"batched: {ms_step:.3f} ms/step, kernel {k_ms / max(k_launches, 1):.3f} ms/launch, "
         f"info {inf}")
 
@@ -201,13 +270,14 @@ def main() -> int:
         out1 = torch.empty(g.n, dtype=torch.uint32, device="cuda")
         ws1 = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
         for s in srcs[:3]:
-            dawn.sssp(csr, int(s), out=out1, ws=ws1)
+            dawn.sssp(csr, int(s), out=out1, ws=ws1, check=False)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         for s in srcs[:nplain]:
-            dawn.sssp(csr, int(s), out=out1, ws=ws1)
+            dawn.sssp(csr, int(s), out=out1, ws=ws1, check=False)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        dawn.check_runs()   # every plain run converged
         plain_s = (t3 - t2) / nplain
         plain_gteps = float(sum(reach[:nplain])) / (t3 - t2) / 1e9
         log(f"plain: {plain_s * 1e3:.3f} ms/source ({nplain} sources)")
@@ -237,20 +307,30 @@ def main() -> int:
                 "algorithmic_bytes_per_call": int(kbytes_call)}
 
     # ---- CPU oracle on a bounded sample ---------------------------------------
+    # The oracle (binary-heap Dijkstra) is timed on the first cpu_sample sources;
+    # its distances are then compared with the GPU's columns of those sources,
+    # element by element, after the timed region.
     cpu = None
     if not args.no_cpu:
         import oracle
-        threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+        threads = max(1, len(os.sched_getaffinity(0)))
         sample = [int(s) for s in srcs[:args.cpu_sample]]
-        r = oracle.time_sources(g, sample, threads, "u32")
+        r = oracle.time_sources(g, sample, threads, "u32", keep=True)
         sw = float(sum(reach[:len(sample)]))
+        host = out[:len(sample)].cpu().numpy()
+        bad = [j for j, d in enumerate(r["dist"]) if not np.array_equal(host[j], d)]
         cpu = {"value": round(sw / r["seconds"] / 1e9, 4), "unit": "GTEPS", "cores": r["threads"],
                "kind": "oracle",
                "sample": f"binary-heap Dijkstra (uint64 sums) from the first {len(sample)} of the "
                          f"{k} sources on the same graph, one source per thread",
+               "cpu_model": cpu_model(),
                "sources_per_s": round(len(sample) / r["seconds"], 2),
-               "seconds": round(r["seconds"], 2)}
+               "seconds": round(r["seconds"], 2),
+               "columns_checked": len(sample), "columns_mismatched": len(bad)}
         log(f"cpu oracle: {cpu}")
+        if bad:
+            log(f"GPU columns {bad[:8]} differ from the oracle: no figure is reported")
+            return 1
 
     res = {
         "metric": "GTEPS & sources/s, batched k-source GOVM vs plain 1-source GOVM; p50/p99 query ms",
@@ -267,6 +347,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"rmat{args.scale}_ef16_u32_k{k}", "n": g.n, "m": g.m, "k": k,
                    "weights": "uint32 uniform [1,255]", "sources": "uniform among out-degree>=1",
+                   "graph_sha256": g.sha256(), "sources_sha256": hashlib.sha256(
+                       np.ascontiguousarray(srcs, dtype=np.int32).tobytes()).hexdigest(),
                    "reverse_graph": tg is not None,
                    "reverse_graph_build_ms": round(t_tg * 1e3, 2) if tg is not None else None},
         "sources_per_s": round(srcs_per_s, 1),
@@ -278,6 +360,11 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "tuning": tune,
+        "autotune": None if autotuned is None else {
+            "key": autotuned["key"], "calibration": autotuned.get("calibration"),
+            "tuned_fields": autotuned["tuning"],
+            "default_tuning_ms_per_step": round(default_ms, 4),
+            "tuned_vs_default": round(default_ms / ms_step, 3)},
     }
     print(json.dumps(res), flush=True)
     return 0

@@ -30,7 +30,16 @@ mu   the validation experiment of Section 4.2 on synthetic graphs: the same
      steps, and the time ratio of the two weightings.
 
 Every input is synthetic and seeded (graphgen.workloads).  Each section prints
-one JSON line; --out appends them to a file.
+one JSON line; --out appends them to a file.  Every line carries the SHA-256
+of the graph arrays (rowptr, colidx, weights; for several graphs, of their
+hashes in order).  Sections c1, c2, c3 and c4b also run a CPU-baseline leg: the
+oracle (binary-heap Dijkstra) timed on the host's cores (threads = the CPU
+affinity count, one source per thread; the CPU model is printed) over the same
+sources, whose distances are then compared element by element with the GPU's
+(uint32 bit for bit; fp32 bit for bit against the fp32-fold mode and within
+2^-22 * hops * d against the fp64 mode).  c5 compares a sample of the served
+queries the same way.  A section whose results differ from the oracle exits
+non-zero after printing its line.
 """
 from __future__ import annotations
 
@@ -46,6 +55,60 @@ sys.path.insert(0, ROOT)
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+FAILURES = []
+
+
+def threads() -> int:
+    return max(1, len(os.sched_getaffinity(0)))
+
+
+def graphs_sha256(gs) -> str:
+    import hashlib
+    if len(gs) == 1:
+        return gs[0].sha256()
+    h = hashlib.sha256()
+    for g in gs:
+        h.update(g.sha256().encode())
+    return h.hexdigest()
+
+
+def cpu_baseline(g, sources, mode, work_edges=None, what=""):
+    """CPU-baseline leg: the oracle's Dijkstra from each source on the host's
+    cores (timed), returning the baseline record and the distance arrays."""
+    import oracle
+    from bench import cpu_model
+    r = oracle.time_sources(g, [int(s) for s in sources], threads(), mode, keep=True)
+    rec = {"kind": "oracle", "mode": mode, "cores": r["threads"], "cpu_model": cpu_model(),
+           "sources": len(sources), "seconds": round(r["seconds"], 3),
+           "sources_per_s": round(len(sources) / r["seconds"], 2),
+           "sample": f"binary-heap Dijkstra ({mode}) from each of the {len(sources)} sources{what}, "
+                     "one source per thread"}
+    if work_edges is not None:
+        rec["gteps"] = round(work_edges / r["seconds"] / 1e9, 4)
+        rec["unit"] = "GTEPS"
+    return rec, r["dist"]
+
+
+def parity(g, s, got, ref_mode_dist=None):
+    """Mismatch count of one GPU result against the oracle: uint32 bit for bit;
+    fp32 bit for bit against the fp32-fold oracle and within the fp64 tolerance."""
+    import numpy as np
+    import oracle
+    got = np.asarray(got)
+    if g.wtype == "u32":
+        ref = ref_mode_dist if ref_mode_dist is not None else oracle.sssp(g, s, "u32")[0]
+        return int((got.view(np.uint32) != ref).sum())
+    d32, _ = oracle.sssp(g, s, "f32fold")
+    bad = int((got.view(np.uint32) != d32.view(np.uint32)).sum())
+    return bad + int(oracle.f32_tolerance_violations(g, s, got.view(np.float32)).size)
+
+
+def note_parity(section, bad, checked):
+    if bad:
+        FAILURES.append(f"{section}: {bad} mismatches over {checked} checked results")
+    return {"checked": checked, "mismatched": bad}
 
 
 def emit(rec, out):
@@ -84,16 +147,31 @@ def c1(args, dawn, torch, np):
     ws = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
     info = dawn.info_tensor()
     for _ in range(50):
-        dawn.sssp(csr, 0, out=out, ws=ws, info=info)
+        dawn.sssp(csr, 0, out=out, ws=ws, info=info, check=False)
     torch.cuda.synchronize()
     lat = []
     for _ in range(args.c1_reps):
         t0 = time.perf_counter()
-        dawn.sssp(csr, 0, out=out, ws=ws, info=info)
+        dawn.sssp(csr, 0, out=out, ws=ws, info=info, check=False)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
     i = dawn.read_info(info)
-    rec = {"config": "c1_er_n1000_m8000_u32", "reps": args.c1_reps, "steps": i["steps"]}
+    got = out.cpu().numpy()
+    # CPU-baseline leg: per-call latency of the oracle on one host thread
+    import oracle
+    clat = []
+    for _ in range(args.c1_reps):
+        t0 = time.perf_counter()
+        ref, _ = oracle.sssp(g, 0, "u32")
+        clat.append(time.perf_counter() - t0)
+    from bench import cpu_model
+    cpu = {"kind": "oracle", "mode": "u32", "cores": 1, "cpu_model": cpu_model(),
+           "sample": f"binary-heap Dijkstra from source 0, {args.c1_reps} calls",
+           **{k.replace("_ms", "_us"): v * 1e3 for k, v in percentile_ms(clat).items()}}
+    rec = {"config": "c1_er_n1000_m8000_u32", "graph_sha256": g.sha256(), "reps": args.c1_reps,
+           "steps": i["steps"], "converged": i["converged"],
+           "parity": note_parity("c1", int((got != ref).sum()) + (i["converged"] != 1), 1),
+           "cpu_baseline": cpu}
     rec.update({k.replace("_ms", "_us"): v * 1e3 for k, v in percentile_ms(lat).items()})
     return rec
 
@@ -109,13 +187,13 @@ def c2(args, dawn, torch, np):
     ws = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
     info = dawn.info_tensor()
     outdeg = torch.as_tensor(np.diff(g.rowptr.astype(np.int64)), device="cuda")
-    dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info, tgraph=tg)
+    dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info, tgraph=tg, check=False)
     torch.cuda.synchronize()
-    per, gteps, mu, steps, kb, kms = [], [], [], [], 0, 0.0
+    per, gteps, mu, steps, kb, kms, reach, got, conv = [], [], [], [], 0, 0.0, [], [], []
     for s in srcs:
         dawn.kernel_timer(True)
         t0 = time.perf_counter()
-        dawn.sssp(csr, int(s), out=out, ws=ws, info=info, tgraph=tg)
+        dawn.sssp(csr, int(s), out=out, ws=ws, info=info, tgraph=tg, check=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         dawn.kernel_timer(False)
@@ -123,21 +201,29 @@ def c2(args, dawn, torch, np):
         i = dawn.read_info(info)
         r = reach_edges(torch, out, outdeg, 0xFFFFFFFF)
         per.append(dt)
+        reach.append(r)
         gteps.append(r / dt / 1e9)
         mu.append(i["edges_scanned"] / max(r, 1))
         steps.append(i["steps"])
+        conv.append(i["converged"])
         kb += ss_bytes(i, g.n)
         kms += ms
+        got.append(out.cpu().numpy())
+    cpu, dist = cpu_baseline(g, srcs, "u32", sum(reach), " on the same graph")
+    bad = sum(int((a != b).sum()) for a, b in zip(got, dist)) + sum(c != 1 for c in conv)
     rec = {"config": f"c2_rmat{args.c2_scale}_ef16_u32_plain", "n": g.n, "m": g.m,
-           "reverse_graph": tg is not None,
+           "graph_sha256": g.sha256(), "reverse_graph": tg is not None,
            "sources": len(srcs), "gteps_per_source_mean": float(np.mean(gteps)),
            "gteps_per_source_min": float(np.min(gteps)), "mu_e_mean": float(np.mean(mu)),
            "steps_mean": float(np.mean(steps)),
            "roofline": {"bound": "hbm",
-                        "kernel": ("ss_step_kernel<0, false> (uint32 weights)" if g.m >= dawn.get_tuning()["step_min_m"]
+                        "kernel": ("ss_step_kernel<0, false> (uint32 weights) + "
+                                   "ss_persistent_kernel<0> (the steps after the step launches)"
+                                   if g.m >= dawn.get_tuning()["step_min_m"]
                                    else "ss_persistent_kernel<0> (uint32 weights)"),
                         "achieved": kb / (kms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
-                        "frac": kb / (kms * 1e-3) / 1e9 / 8000.0}}
+                        "frac": kb / (kms * 1e-3) / 1e9 / 8000.0},
+           "parity": note_parity("c2", bad, len(srcs)), "cpu_baseline": cpu}
     rec.update(percentile_ms(per))
     return rec
 
@@ -150,24 +236,31 @@ def c3(args, dawn, torch, np):
     ws = dawn.workspace(dawn.sssp_workspace_bytes(g.n, g.m))
     info = dawn.info_tensor()
     outdeg = torch.as_tensor(np.diff(g.rowptr.astype(np.int64)), device="cuda")
-    dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info)
+    dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info, check=False)
     torch.cuda.synchronize()
-    per, steps, gteps = [], [], []
+    per, steps, gteps, reach, got, conv = [], [], [], [], [], []
     for s in srcs:
         t0 = time.perf_counter()
-        dawn.sssp(csr, int(s), out=out, ws=ws, info=info)
+        dawn.sssp(csr, int(s), out=out, ws=ws, info=info, check=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         i = dawn.read_info(info)
         fin = torch.isfinite(out)
         r = int((fin.to(torch.int64) * outdeg).sum().item())
         per.append(dt)
+        reach.append(r)
         steps.append(i["steps"])
+        conv.append(i["converged"])
         gteps.append(r / dt / 1e9)
-    rec = {"config": f"c3_grid{args.c3_side}_f32", "n": g.n, "m": g.m, "sources": len(srcs),
+        got.append(out.cpu().numpy())
+    cpu, _ = cpu_baseline(g, srcs, "f64", sum(reach), " (fp64 sums of the fp32 weights)")
+    bad = sum(parity(g, int(s), d) for s, d in zip(srcs, got)) + sum(c != 1 for c in conv)
+    rec = {"config": f"c3_grid{args.c3_side}_f32", "n": g.n, "m": g.m,
+           "graph_sha256": g.sha256(), "sources": len(srcs),
            "steps_mean": float(np.mean(steps)),
            "ms_per_step": float(np.mean([p * 1e3 / s for p, s in zip(per, steps)])),
-           "gteps_mean": float(np.mean(gteps))}
+           "gteps_mean": float(np.mean(gteps)),
+           "parity": note_parity("c3", bad, len(srcs)), "cpu_baseline": cpu}
     rec.update(percentile_ms(per))
     return rec
 
@@ -208,16 +301,49 @@ def c4b(args, dawn, torch, np):
     wss = [dawn.workspace(dawn.sssp_workspace_bytes(c.n, c.m)) for c in csrs]
     outs = [torch.empty(c.n, dtype=torch.float32, device="cuda") for c in csrs]
     for c, (_, s), w, o in zip(csrs, gs, wss, outs):
-        dawn.sssp(c, s, out=o, ws=w)
+        dawn.sssp(c, s, out=o, ws=w, check=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         for c, (_, s), w, o in zip(csrs, gs, wss, outs):
-            dawn.sssp(c, s, out=o, ws=w)
+            dawn.sssp(c, s, out=o, ws=w, check=False)
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / reps
+    # CPU-baseline leg: the oracle on every graph from its source (fp64 sums);
+    # parity of every graph's distances (batched run) with the oracle
+    import oracle
+    from bench import cpu_model
+    got = [d.cpu().numpy() for d in b.split(out)]
+    import threading
+    lock, nxt, bad = threading.Lock(), [0], [0]
+
+    def worker():
+        while True:
+            with lock:
+                if nxt[0] >= len(gs):
+                    return
+                j = nxt[0]
+                nxt[0] += 1
+            oracle.sssp(gs[j][0], gs[j][1], "f64")
+
+    ts = [threading.Thread(target=worker) for _ in range(threads())]
+    t0 = time.perf_counter()
+    for th in ts:
+        th.start()
+    for th in ts:
+        th.join()
+    t_cpu = time.perf_counter() - t0
+    for (g, s), d in zip(gs, got):
+        bad[0] += parity(g, s, d)
+    cpu = {"kind": "oracle", "mode": "f64", "cores": len(ts), "cpu_model": cpu_model(),
+           "sample": f"binary-heap Dijkstra (fp64) on each of the {len(gs)} graphs from its source",
+           "seconds": round(t_cpu, 3), "graphs_per_s": round(len(gs) / t_cpu, 2),
+           "gteps": round(work / t_cpu / 1e9, 4), "unit": "GTEPS"}
     b.close()
     return {"config": f"c4b_er_batch{len(gs)}_f32lognormal", "total_n": b.total_n,
+            "graph_sha256": graphs_sha256([g for g, _ in gs]),
+            "parity": note_parity("c4b", bad[0] + (i["converged"] != 1), len(gs)),
+            "cpu_baseline": cpu,
             "total_m": b.total_m, "steps": i["steps"],
             "batch_ms": t_batch * 1e3, "graph_replay_ms": t_graph * 1e3, "plain_ms": t_plain * 1e3,
             "graphs_per_s_batch": len(gs) / t_batch, "graphs_per_s_replay": len(gs) / t_graph,
@@ -269,9 +395,21 @@ def c5(args, dawn, torch, np):
     srv.run_until_idle()
     cap = len(qs) / (time.perf_counter() - t0)
     closed = serve.percentiles([q.latency for q in qs])
+    # parity of served queries: every query of the largest graph (scale 22,
+    # edge factor 32 when all 32 graphs are served) and of three more graphs,
+    # at most args.c5_check in all, against the oracle
+    big = max(range(len(graphs)), key=lambda i: graphs[i].m)
+    picks = [q for q in qs if q.gid == big][:args.c5_check // 2]
+    for gi in (0, len(graphs) // 3, 2 * len(graphs) // 3):
+        picks += [q for q in qs if q.gid == gi][:max(1, args.c5_check // 6)]
+    bad = sum(parity(graphs[q.gid], q.source, q.result) for q in picks)
+    bad += sum(q.state != "done" for q in qs)
     recs = [{"config": "c5_serving_closed_loop", "graphs": len(graphs), "queries": len(qs),
-             "pull": not args.c5_no_pull, "graphs": not args.c5_no_graphs, "capacity_qps": cap,
-             **closed}]
+             "graph_sha256": graphs_sha256(graphs),
+             "pull": not args.c5_no_pull, "captured_runs": not args.c5_no_graphs,
+             "capacity_qps": cap, **closed,
+             "parity": {**note_parity("c5", bad, len(picks)),
+                        "largest_graph": {"id": big, "n": graphs[big].n, "m": graphs[big].m}}}]
     log(f"c5 closed-loop capacity {cap:.1f} queries/s")
     for frac in args.c5_rates:
         rate = frac * cap
@@ -296,7 +434,7 @@ def hop(args, dawn, torch, np):
     out = torch.empty((k, g.n), dtype=torch.uint32, device="cuda")
     ws = dawn.workspace(dawn.umsssp_workspace_bytes(g.n, g.m, k))
     info = dawn.info_tensor()
-    dawn.umsssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg)
+    dawn.umsssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg, check=False)
     torch.cuda.synchronize()
     ok = True
     for j in (0, k - 1):
@@ -306,19 +444,19 @@ def hop(args, dawn, torch, np):
     ts = []
     for _ in range(args.hop_reps):
         t0 = time.perf_counter()
-        dawn.umsssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg)
+        dawn.umsssp(csr, src_t, out=out, ws=ws, info=info, tgraph=tg, check=False)
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
     i = dawn.read_info(info)
     t = float(np.median(ts))
     wout = torch.empty((k, g.n), dtype=torch.uint32, device="cuda")
     wws = dawn.workspace(dawn.msssp_workspace_bytes(g.n, g.m, k))
-    dawn.msssp(csr, src_t, out=wout, ws=wws, tgraph=tg)
+    dawn.msssp(csr, src_t, out=wout, ws=wws, tgraph=tg, check=False)
     torch.cuda.synchronize()
     wts = []
     for _ in range(args.hop_reps):
         t0 = time.perf_counter()
-        dawn.msssp(csr, src_t, out=wout, ws=wws, tgraph=tg)
+        dawn.msssp(csr, src_t, out=wout, ws=wws, tgraph=tg, check=False)
         torch.cuda.synchronize()
         wts.append(time.perf_counter() - t0)
     # mu = 1: the edges scanned are exactly the reachable edges of the sources
@@ -328,8 +466,38 @@ def hop(args, dawn, torch, np):
             "weighted_tile_ms_same_sources": float(np.median(wts)) * 1e3}
 
 
+def seq_alg2(g, srcs, np, order=0):
+    """Sequential Algorithm 2 (the oracle's restatement, CPU): mu_e, mu_v, the
+    extra updates per reached vertex, and the share of reached vertices whose
+    distance was lowered more than once (the paper's re-updated paths)."""
+    import oracle
+    od = g.outdeg()
+    es = rows = mr = rr = reached = imp = multi = steps = 0
+    for s in srcs:
+        _, c = oracle.govm(g, int(s), order=order, seed=int(s), per_vertex=True)
+        reach = oracle.bfs(g, int(s)) >= 0
+        es += c["edges_scanned"]
+        rows += c["frontier_entries"]
+        mr += int(od[reach].sum())
+        rr += int((reach & (od > 0)).sum())
+        reached += int(reach.sum()) - 1
+        imp += c["improvements"]
+        multi += int((c["updates"] >= 2).sum())
+        steps += c["steps"]
+    k = len(srcs)
+    return {"order": ["in place, index order", "Jacobi", "in place, random order"][order],
+            "mu_e": es / max(mr, 1), "mu_v": rows / max(rr, 1),
+            "extra_updates_per_reached": imp / max(reached, 1) - 1.0,
+            "share_reached_updated_more_than_once": multi / max(reached, 1),
+            "steps_mean": steps / k}
+
+
 def mu(args, dawn, torch, np):
+    """Section 4.2's experiment on synthetic graphs (GPU single-source runs),
+    each beside sequential Algorithm 2 on the same sources (CPU), plus the C4a
+    tile's mu beside sequential Algorithm 2 for its sources."""
     import graphgen
+    from graphgen import workloads
     graphs = [("rmat18_ef16", lambda wk: graphgen.rmat(18, 16, 180, weights=wk)),
               ("er_n262144_m16n", lambda wk: graphgen.er(1 << 18, 16 << 18, 181, weights=wk)),
               ("grid512_1pct", lambda wk: graphgen.grid(512, 512, 0.01, 182, weights=wk))]
@@ -344,12 +512,12 @@ def mu(args, dawn, torch, np):
             info = dawn.info_tensor()
             outdeg = torch.as_tensor(np.diff(g.rowptr.astype(np.int64)), device="cuda")
             srcs = graphgen.pick_sources(g, args.mu_sources, 7)
-            dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info)
+            dawn.sssp(csr, int(srcs[0]), out=out, ws=ws, info=info, check=False)
             torch.cuda.synchronize()
             tot = dict(t=0.0, reached=0, reached_rows=0, reach_edges=0, imp=0, rows=0, es=0, steps=0)
             for s in srcs:
                 t0 = time.perf_counter()
-                dawn.sssp(csr, int(s), out=out, ws=ws, info=info)
+                dawn.sssp(csr, int(s), out=out, ws=ws, info=info, check=False)
                 torch.cuda.synchronize()
                 tot["t"] += time.perf_counter() - t0
                 i = dawn.read_info(info)
@@ -362,13 +530,34 @@ def mu(args, dawn, torch, np):
                 tot["es"] += i["edges_scanned"]
                 tot["steps"] += i["steps"]
             k = len(srcs)
-            row[wk] = {"update_share": tot["imp"] / max(tot["reached"], 1) - 1.0,
-                       "mu_e": tot["es"] / max(tot["reach_edges"], 1),
-                       "mu_v": tot["rows"] / max(tot["reached_rows"], 1),
-                       "steps_mean": tot["steps"] / k, "ms_mean": tot["t"] * 1e3 / k}
-        row["time_ratio_range02_over_one"] = row["f32range02"]["ms_mean"] / row["f32one"]["ms_mean"]
+            row[wk] = {"graph_sha256": g.sha256(),
+                       "gpu": {"extra_updates_per_reached": tot["imp"] / max(tot["reached"], 1) - 1.0,
+                               "mu_e": tot["es"] / max(tot["reach_edges"], 1),
+                               "mu_v": tot["rows"] / max(tot["reached_rows"], 1),
+                               "steps_mean": tot["steps"] / k, "ms_mean": tot["t"] * 1e3 / k},
+                       "sequential_alg2": seq_alg2(g, srcs, np)}
+        row["time_ratio_range02_over_one"] = (row["f32range02"]["gpu"]["ms_mean"]
+                                              / row["f32one"]["gpu"]["ms_mean"])
         log(f"mu {name}: {row}")
         recs.append(row)
+    # the C4a tile (R-MAT scale 20, uint32 [1,255]) against sequential Algorithm 2
+    g, srcs = workloads.rmat20_tile()
+    csr = dawn.Csr.from_graph(g)
+    tg = dawn.tgraph(csr)
+    info = dawn.info_tensor()
+    out = dawn.msssp(csr, srcs, info=info, tgraph=tg)
+    i = dawn.read_info(info)
+    outdeg = torch.as_tensor(np.diff(g.rowptr.astype(np.int64)), device="cuda")
+    work = sum(reach_edges(torch, out[j], outdeg, 0xFFFFFFFF) for j in range(out.shape[0]))
+    sub = srcs[:args.mu_sources * 2]
+    recs.append({"config": "mu_c4a_rmat20_u32_k256", "graph_sha256": g.sha256(),
+                 "gpu_tile": {"mu_e": i["edges_scanned"] / max(work, 1),
+                              "extra_updates_per_reached":
+                                  i["improvements"] / max(int((out != 0xFFFFFFFF).sum().item())
+                                                          - len(srcs), 1) - 1.0,
+                              "steps": i["steps"]},
+                 "sequential_alg2": [seq_alg2(g, sub, np, order) for order in (0, 1)],
+                 "sequential_sources": len(sub)})
     return recs
 
 
@@ -395,6 +584,8 @@ def main() -> int:
     ap.add_argument("--c5-pull-src", type=int, default=None,
                     help="tuning tile_pull_src while serving (default: the library's)")
     ap.add_argument("--c5-steps-per-tick", type=int, default=4)
+    ap.add_argument("--c5-check", type=int, default=24,
+                    help="served queries compared with the oracle")
     ap.add_argument("--c5-rates", default="0.1,0.25,0.5,0.7,0.8,0.9,1.0,1.2")
     ap.add_argument("--mu-sources", type=int, default=8)
     ap.add_argument("--hop-reps", type=int, default=5)
@@ -418,6 +609,9 @@ def main() -> int:
         for r in (recs if isinstance(recs, list) else [recs]):
             r["section_s"] = round(time.perf_counter() - t, 1)
             emit(r, args.out)
+    if FAILURES:
+        log("results differ from the oracle: " + "; ".join(FAILURES))
+        return 1
     return 0
 
 

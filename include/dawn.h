@@ -51,9 +51,16 @@
  *   pointer after the call's stream work completes, except tile and batch
  *   sessions, which keep their graph pointers until destroyed.
  * - Every call is stream-ordered and asynchronous: it validates its scalar
- *   arguments on the host, enqueues work on `stream` and returns.  The return
- *   code reports host-side validation and launch errors only; a device fault
- *   surfaces at the caller's next synchronisation.
+ *   arguments on the host, enqueues a fixed sequence of launches on `stream`
+ *   and returns; no call waits on the host for device work, so every run can
+ *   be captured into a HIP graph.  The return code reports host-side
+ *   validation and launch errors only; a device fault surfaces at the
+ *   caller's next synchronisation.
+ * - A run that ends without reaching its fixed point (dawn_run_info.converged
+ *   other than 1) is never silent: with a dawn_run_info the caller reads the
+ *   status there; without one (every plain call) the status is recorded on the
+ *   device and dawn_run_status reports it once the stream has been
+ *   synchronised.
  * - Without a caller workspace, scratch memory is taken with hipMallocAsync
  *   and released with hipFreeAsync on the same stream.
  * - With tuning fields out of range a call returns DAWN_E_INVALID.  Tuning
@@ -78,7 +85,8 @@ typedef enum {
   DAWN_E_UNSUPPORTED = 2, /* valid request this build does not handle (mixed weight
                              types in one batch, k above the tile maximum, ...) */
   DAWN_E_WORKSPACE = 3,   /* caller workspace smaller than dawn_*_workspace_bytes() */
-  DAWN_E_HIP = 4          /* a HIP runtime call failed (allocation, launch) */
+  DAWN_E_HIP = 4,         /* a HIP runtime call failed (allocation, launch) */
+  DAWN_E_INCOMPLETE = 5   /* dawn_run_status: a run ended without converging */
 } dawn_status;
 
 typedef enum { DAWN_W_U32 = 0, DAWN_W_F32 = 1, DAWN_W_I32 = 2, DAWN_W_UNIT = 3 } dawn_wtype;
@@ -89,8 +97,11 @@ typedef enum { DAWN_W_U32 = 0, DAWN_W_F32 = 1, DAWN_W_I32 = 2, DAWN_W_UNIT = 3 }
  *                    that changes nothing (Algorithm 2's loop count);
  *   converged        1 = stopped after a step with no change; 0 = stopped at
  *                    the n-step cap; -1 = input validation failed on the
- *                    device; -2 = a persistent launch gave up waiting at a grid
- *                    barrier (the result is then incomplete);
+ *                    device, or a source id outside [0, n) reached a batched
+ *                    run; -2 = a persistent launch gave up waiting at a grid
+ *                    barrier (tuning field barrier_ms); -3 = a frontier queue
+ *                    overflowed (cannot happen on a valid CSR).  Anything but
+ *                    1 means the distances are incomplete;
  *   frontier_entries sum over steps of the frontier rows (changed in the
  *                    previous step and having out-edges);
  *   edges_scanned    sum over steps of the out-degrees of the rows expanded
@@ -125,18 +136,19 @@ typedef struct {
  *   wave tier      d <= t_wave   one wavefront per row (t_wave >= 64);
  *   workgroup tier d >  t_wave   the row is cut into chunks of t_chunk edges,
  *                                one workgroup per chunk.
- * mode: 0 auto: single source and batches of graphs run in one workgroup
- * when m <= small_m; with m >= step_min_m edges as `host_check` step launches
- * followed, if the run has not ended by then, by one persistent launch for
- * the rest (a captured run enqueues both without waiting: launches after the
- * run has ended return at once); otherwise as one persistent launch; tiles: 1.
- * 1 step
- * launches (one kernel per step; the host checks termination every
- * `host_check` steps -- for tiles, the first two checks after host_check / 4
- * steps each -- so such a call waits for its stream), 2 one persistent
- * launch for all steps with a grid
- * barrier between steps (the barrier gives up after a few seconds, so a grid
- * that cannot be co-resident ends with converged = -2 instead of hanging).
+ * mode: how the step loop (Algorithm 2's `while`) is launched.  No mode waits
+ * on the host: a run is a fixed launch sequence, and a launch that finds the
+ * run already ended returns at once.
+ *   0 auto: single source and batches of graphs run in one workgroup when
+ *     m <= small_m, as mode 1 when m >= step_min_m, else as mode 2; tiles
+ *     (dawn_msssp, dawn_apsp, dawn_umsssp_ws) as mode 1;
+ *   1 `step_launches` (tiles: `tile_step_launches`) launches of one step
+ *     each, then one persistent launch for the steps that remain;
+ *   2 one persistent launch for all steps, with a grid barrier between steps.
+ * A persistent launch's grid is what the compute units hold at once, by the
+ * kernel's compiled VGPR and LDS use (dawn_device_query); a grid barrier that
+ * waits longer than barrier_ms ends the run with converged = -2, never a hang.
+ * Tile sessions always take step launches.
  * wg_threads: 256, 512 or 1024, or 0 = auto (single source: 512 for step launches,
  * 1024 for persistent launches; tiles 256).
  * grid: workgroups per launch, 0 = auto (persistent: what the device holds at
@@ -152,14 +164,15 @@ typedef struct {
   int32_t wg_threads; /* default 0 (auto) */
   int32_t grid;       /* default 0 (auto) */
   int32_t mode;       /* default 0 (auto) */
-  int32_t host_check; /* 1..4096, default 32 */
+  int32_t step_launches; /* single source, mode 1: step launches before the persistent
+                            launch, 0..4096, default 20 */
   int32_t tile_k;     /* default 256 */
   int32_t tile_t_wave;  /* workgroup-tier threshold of the tile kernel, 32..65536, default 64 */
   int32_t tile_t_chunk; /* edges per workgroup chunk in the tile kernel, 64..65536, default 256 */
   int32_t validate;     /* 1 = check the CSR on the device before running */
-  int32_t coop;         /* 1 = launch persistent kernels with hipLaunchCooperativeKernel;
-                           0 (default) = an ordinary launch of a grid sized to what the
-                           device holds at once (half the occupancy query's figure) */
+  int32_t coop;         /* 1 = launch persistent kernels with hipLaunchCooperativeKernel
+                           (not under graph capture); 0 (default) = an ordinary launch of
+                           the same grid */
   int32_t tile_t_group; /* tile rows of out-degree <= this go one per 16-lane group,
                            0..64, default 8 (0: none) */
   int32_t tile_skip;    /* 1: in a tile step, a (row, source) pair whose distance was
@@ -190,6 +203,13 @@ typedef struct {
                            launches: a step whose frontier rows hold at least ss_pull / 1000
                            of the m edges pulls over the in-edges of every vertex; 1001 =
                            never (default) */
+  int32_t tile_step_launches; /* tiles, mode 0 or 1: step launches (each one step, with pull
+                           steps on dense frontiers) before the persistent launch that
+                           finishes the run, 0..4096, default 16 (R-MAT scale 20 with 256
+                           sources takes 15 steps) */
+  int32_t barrier_ms;   /* persistent launches: a grid barrier that waits longer than this
+                           gives up and ends the run with converged = -2; 0..600000,
+                           default 4000 (0: give up at the first wait, for tests) */
 } dawn_tuning;
 
 #define DAWN_TILE_K_MAX 512
@@ -201,6 +221,16 @@ const char* dawn_status_str(dawn_status s);
 /* Last error text of this thread (HIP error string or validation message). */
 const char* dawn_last_error(void);
 
+/* Status of the runs launched on the current device without a dawn_run_info
+ * (every dawn_sssp / dawn_msssp / dawn_apsp call, and the *_ws calls given
+ * info = NULL) whose stream work has completed: call it after synchronising
+ * those streams.  Returns DAWN_OK when each of them converged (status 1), else
+ * DAWN_E_INCOMPLETE with *incomplete_runs = how many did not and
+ * *last_status = the dawn_run_info.converged code of the last one; the record
+ * is cleared by the call.  Either output pointer may be NULL.  Blocking (it
+ * copies two words from the device). */
+dawn_status dawn_run_status(int32_t* incomplete_runs, int32_t* last_status);
+
 /* ---------------------------------------------------------------------------
  * Single source (Algorithm 2).  dist_out_dev: n elements (uint32 or float32
  * per wt), fully written.
@@ -211,6 +241,7 @@ dawn_status dawn_sssp(const int32_t* rowptr_dev, const int32_t* colidx_dev,
 
 /* Bytes of scratch a single-source call needs for this graph. */
 size_t dawn_sssp_workspace_bytes(int32_t n, int32_t m);
+
 
 /* Same, with caller scratch (>= dawn_sssp_workspace_bytes, 256-byte aligned
  * device memory, contents ignored) and an optional DEVICE pointer to a
@@ -333,8 +364,7 @@ dawn_status dawn_batch_run(dawn_batch* b, const int32_t* sources_dev, void* dist
                            dawn_run_info* info_dev, hipStream_t stream);
 /* Capture dawn_batch_run(b, sources_dev, dist_out_dev, info_dev) into a HIP
  * graph once; dawn_batch_replay launches it again (the device buffers named
- * at capture are re-read, so new source ids written there take effect).
- * DAWN_E_UNSUPPORTED under tuning mode 1 (step launches with host checks). */
+ * at capture are re-read, so new source ids written there take effect). */
 dawn_status dawn_batch_capture(dawn_batch* b, const int32_t* sources_dev, void* dist_out_dev,
                                dawn_run_info* info_dev, hipStream_t stream);
 dawn_status dawn_batch_replay(dawn_batch* b, hipStream_t stream);
@@ -349,13 +379,16 @@ void dawn_batch_destroy(dawn_batch* b);
  * ------------------------------------------------------------------------- */
 typedef struct dawn_tile dawn_tile;
 
-/* Device bytes a tile of k columns needs (allocated by dawn_tile_create). */
+/* Device bytes a tile of k columns needs (its workspace). */
 size_t dawn_tile_bytes(int32_t n, int32_t m, int32_t k);
-/* k: 1..DAWN_TILE_K_MAX (rounded up to a multiple of 64 internally).  The CSR
- * arrays must stay valid until dawn_tile_destroy. */
+/* k: 1..DAWN_TILE_K_MAX (rounded up to a multiple of 64 internally).
+ * ws_dev: the session's device memory, owned by the caller, 256-byte aligned,
+ * at least dawn_tile_bytes(n, m, k) bytes; the session keeps it (and the CSR
+ * arrays) until dawn_tile_destroy, which frees neither.  The library allocates
+ * no device memory for a session.  The tile is reset on `stream`. */
 dawn_status dawn_tile_create(dawn_tile** out, const int32_t* rowptr_dev, const int32_t* colidx_dev,
                              const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
-                             int32_t k, hipStream_t stream);
+                             int32_t k, void* ws_dev, size_t ws_bytes, hipStream_t stream);
 /* Start query `source` in free column col (0..k-1). */
 dawn_status dawn_tile_admit(dawn_tile* t, int32_t col, int32_t source, hipStream_t stream);
 /* Attach the reverse graph of the session's CSR (dawn_tgraph_build, with
@@ -399,11 +432,21 @@ void dawn_tile_destroy(dawn_tile* t);
 dawn_status dawn_kernel_timer(int32_t enable);
 dawn_status dawn_kernel_time(double* total_ms, int32_t* launches);
 
-/* Device query for tuning, about the current device: out[0] = compute units,
- * out[1] = cooperative launch supported (0/1), out[2] / out[3] = workgroups
- * per compute unit the single-source / tile persistent kernels can hold at the
- * current wg_threads, out[4] / out[5] = the persistent grid each would use,
- * out[6] = device id, out[7] = wg_threads.  `out` is a host array of 8. */
+/* Device query for tuning, about the current device.  `out` is a host array
+ * of DAWN_DEVICE_QUERY_LEN:
+ *   [0] compute units, [1] cooperative launch supported (0/1),
+ *   [2] / [3] workgroups per compute unit the single-source / tile persistent
+ *   kernels are launched with at the current wg_threads, [4] / [5] their
+ *   persistent grids, [6] device id, [7] wg_threads,
+ *   [8] / [9] VGPRs and LDS bytes of the single-source persistent kernel as
+ *   compiled, [10] the runtime occupancy API's workgroups per CU for it,
+ *   [11] / [12] / [13] the same for the tile persistent kernel,
+ *   [14] / [15] workgroups per CU and VGPRs of the hop-count-tile persistent
+ *   kernel.
+ * The per-CU figure is the smaller of the residency rule applied to the
+ * compiled VGPRs and LDS (512 VGPRs per SIMD lane in granules of 8, at most 8
+ * waves per SIMD, 4 SIMDs, 160 KiB LDS) and the occupancy API's figure. */
+#define DAWN_DEVICE_QUERY_LEN 16
 dawn_status dawn_device_query(int32_t* out);
 
 /* Build information: "gfx950 <compile options>". */

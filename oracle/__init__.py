@@ -85,7 +85,7 @@ def _L():
         L.oracle_check_f32.argtypes = [_i32, _i32p, _i32p, _f32p, _i32, _f32p, _i32p]
         L.oracle_check_f32.restype = _i32
         L.oracle_govm.argtypes = [_i32, _i32p, _i32p, _vp, _i32, _i32, _i32, ctypes.c_uint64,
-                                  _vp, _i64p]
+                                  _vp, _i64p, _i32p]
         L.oracle_govm.restype = _i32
         _lib = L
     return _lib
@@ -198,18 +198,25 @@ def check(g, s: int, d) -> tuple[int, int]:
     return int(rc), int(bad.value)
 
 
-def govm(g, s: int, order: int = 0, seed: int = 0):
-    """Algorithm 2 restated (see oracle.c).  Returns (dist, counters dict)."""
+def govm(g, s: int, order: int = 0, seed: int = 0, per_vertex: bool = False):
+    """Algorithm 2 restated (see oracle.c).  Returns (dist, counters dict); with
+    per_vertex=True the dict also holds ``updates``, the number of times each
+    vertex's distance was lowered (int32[n])."""
     n, rp, ci = _csr(g)
     is_f32 = 1 if g.wtype == "f32" else 0
     d = np.empty(n, dtype=np.float32 if is_f32 else np.uint32)
     c = np.zeros(5, dtype=np.int64)
+    upd = np.zeros(n, dtype=np.int32) if per_vertex else None
     rc = _L().oracle_govm(n, rp, ci, g.w.ctypes.data_as(_vp), is_f32, int(s), int(order),
-                          int(seed), d.ctypes.data_as(_vp), _p(c, _i64p))
+                          int(seed), d.ctypes.data_as(_vp), _p(c, _i64p),
+                          _p(upd, _i32p) if per_vertex else None)
     if rc != 0:
         raise MemoryError("oracle govm failed")
-    return d, {"steps": int(c[0]), "converged": int(c[1]), "frontier_entries": int(c[2]),
-               "edges_scanned": int(c[3]), "improvements": int(c[4])}
+    res = {"steps": int(c[0]), "converged": int(c[1]), "frontier_entries": int(c[2]),
+           "edges_scanned": int(c[3]), "improvements": int(c[4])}
+    if per_vertex:
+        res["updates"] = upd
+    return d, res
 
 
 # ---------------------------------------------------------------------------
@@ -246,21 +253,25 @@ def m_reach(g, s: int) -> int:
     return int(g.outdeg()[lvl >= 0].sum())
 
 
-def time_sources(g, sources, threads: int, mode: str | None = None) -> dict:
+def time_sources(g, sources, threads: int, mode: str | None = None, keep: bool = False) -> dict:
     """Run Dijkstra from each source on `threads` host threads (ctypes releases
-    the GIL).  Returns wall time and the reachable-edge work."""
+    the GIL).  Returns the wall time (and, with keep=True, the distance array
+    of each source, in the order given)."""
     sources = list(int(x) for x in sources)
     idx = [0]
     lock = threading.Lock()
+    dist = [None] * len(sources)
 
     def worker():
         while True:
             with lock:
                 if idx[0] >= len(sources):
                     return
-                s = sources[idx[0]]
+                i = idx[0]
                 idx[0] += 1
-            sssp(g, s, mode)
+            d, _ = sssp(g, sources[i], mode)
+            if keep:
+                dist[i] = d
 
     ts = [threading.Thread(target=worker) for _ in range(max(1, threads))]
     t0 = time.perf_counter()
@@ -268,4 +279,7 @@ def time_sources(g, sources, threads: int, mode: str | None = None) -> dict:
         t.start()
     for t in ts:
         t.join()
-    return {"seconds": time.perf_counter() - t0, "sources": len(sources), "threads": len(ts)}
+    res = {"seconds": time.perf_counter() - t0, "sources": len(sources), "threads": len(ts)}
+    if keep:
+        res["dist"] = dist
+    return res

@@ -486,13 +486,16 @@ int32_t oracle_check_f32(int32_t n, const int32_t* rowptr, const int32_t* colidx
 /*          reads the values the step started with); order 2: rows of each      */
 /*          step visited in a seeded random order, in place.                      */
 /* Outputs: dist (u32, or f32 as bits), and counters[5] = {steps, converged,     */
-/* sum_t |delta_t| over rows with out-edges, edges scanned, improvements}.       */
+/* sum_t |delta_t| over rows with out-edges, edges scanned, improvements};       */
+/* updates (optional, n entries): how many times each vertex's distance was     */
+/* lowered (the paper's path updates, Section 4.2: 1 for a vertex whose first  */
+/* path found is already shortest).                                              */
 /* ------------------------------------------------------------------------- */
 static uint64_t lcg_next(uint64_t* x) { *x = *x * 6364136223846793005ULL + 1442695040888963407ULL; return *x >> 33; }
 
 int32_t oracle_govm(int32_t n, const int32_t* rowptr, const int32_t* colidx, const void* w,
                     int32_t is_f32, int32_t source, int32_t order, uint64_t seed, void* dist,
-                    int64_t* counters) {
+                    int64_t* counters, int32_t* updates) {
   uint32_t* au = (uint32_t*)dist;
   float* af = (float*)dist;
   uint8_t* delta = (uint8_t*)calloc((size_t)n, 1);
@@ -503,6 +506,7 @@ int32_t oracle_govm(int32_t n, const int32_t* rowptr, const int32_t* colidx, con
   for (int32_t v = 0; v < n; v++) {
     if (is_f32) af[v] = INFINITY; else au[v] = OR_INF32;
     perm[v] = v;
+    if (updates) updates[v] = 0;
   }
   if (is_f32) af[source] = 0.0f; else au[source] = 0;
   delta[source] = 1;
@@ -535,6 +539,7 @@ int32_t oracle_govm(int32_t n, const int32_t* rowptr, const int32_t* colidx, con
             beta[index] = 1;
             ptr = 1;
             impr++;
+            if (updates) updates[index]++;
           }
         } else {
           const uint32_t cand = sat_add_u32(aju, ((const uint32_t*)w)[k]);
@@ -543,6 +548,7 @@ int32_t oracle_govm(int32_t n, const int32_t* rowptr, const int32_t* colidx, con
             beta[index] = 1;
             ptr = 1;
             impr++;
+            if (updates) updates[index]++;
           }
         }
       }

@@ -26,7 +26,9 @@ W_U32, W_F32, W_I32, W_UNIT = 0, 1, 2, 3
 TILE_K_MAX = 512
 
 _STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "workspace too small",
-           4: "HIP error"}
+           4: "HIP error", 5: "run did not converge"}
+E_INCOMPLETE = 5
+DEVICE_QUERY_LEN = 16
 
 
 class DawnError(RuntimeError):
@@ -44,10 +46,10 @@ class RunInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
-                ("t_lane", "t_wave", "t_chunk", "wg_threads", "grid", "mode", "host_check",
+                ("t_lane", "t_wave", "t_chunk", "wg_threads", "grid", "mode", "step_launches",
                  "tile_k", "tile_t_wave", "tile_t_chunk", "validate", "coop", "tile_t_group",
                  "tile_skip", "small_m", "step_min_m", "tile_sparse", "tile_pull",
-                 "tile_pull_src", "ss_skip", "ss_pull")]
+                 "tile_pull_src", "ss_skip", "ss_pull", "tile_step_launches", "barrier_ms")]
 
 
 INFO_BYTES = ctypes.sizeof(RunInfo)
@@ -102,8 +104,9 @@ def load():
         "dawn_batch_replay": ([_vp, _vp], _i32),
         "dawn_batch_destroy": ([_vp], None),
         "dawn_tile_bytes": ([_i32, _i32, _i32], _sz),
-        "dawn_tile_create": ([ctypes.POINTER(_vp), _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp],
-                             _i32),
+        "dawn_tile_create": ([ctypes.POINTER(_vp), _vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp,
+                              _sz, _vp], _i32),
+        "dawn_run_status": ([ctypes.POINTER(_i32), ctypes.POINTER(_i32)], _i32),
         "dawn_tile_admit": ([_vp, _i32, _i32, _vp], _i32),
         "dawn_tile_run": ([_vp, _i32, _vp, _vp], _i32),
         "dawn_tile_capture": ([_vp, _i32, _vp], _i32),
@@ -138,7 +141,7 @@ def exported_symbols() -> list[str]:
         "dawn_tile_replay", "dawn_tile_read",
         "dawn_tile_set_tgraph",
         "dawn_tile_steps", "dawn_tile_evict", "dawn_tile_destroy", "dawn_kernel_timer",
-        "dawn_kernel_time", "dawn_device_query"]
+        "dawn_kernel_time", "dawn_device_query", "dawn_run_status"]
 
 
 def _check(status: int):
@@ -149,6 +152,46 @@ def _check(status: int):
 def _torch():
     import torch
     return torch
+
+
+def run_status() -> tuple[int, int]:
+    """(runs that ended without converging, status of the last one) among the
+    runs launched without run info on the current device whose work has
+    completed (``dawn_run_status``; synchronise first).  Clears the record."""
+    cnt, last = _i32(), _i32()
+    st = load().dawn_run_status(ctypes.byref(cnt), ctypes.byref(last))
+    if st not in (0, E_INCOMPLETE):
+        _check(st)
+    return int(cnt.value), int(last.value)
+
+
+def check_runs(stream=None):
+    """Synchronise `stream` and raise DawnError if a run launched without run
+    info on this device ended without converging."""
+    torch = _torch()
+    (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+    cnt, last = run_status()
+    if cnt:
+        raise DawnError(E_INCOMPLETE, f"{cnt} run(s) ended without converging "
+                                      f"(last status {last})")
+
+
+def _check_info(info, stream=None):
+    """Synchronise and raise DawnError if the run in `info` did not converge."""
+    torch = _torch()
+    (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+    conv = read_info(info)["converged"]
+    if conv != 1:
+        raise DawnError(E_INCOMPLETE, f"run ended with status {conv}")
+
+
+def _finish(info, stream, check):
+    if not check:
+        return
+    if info is None:
+        check_runs(stream)
+    else:
+        _check_info(info, stream)
 
 
 def _stream(stream):
@@ -281,12 +324,16 @@ def _aligned(buf):
     return ctypes.c_void_p((p + 255) & ~255), buf.numel() - (((p + 255) & ~255) - p)
 
 
-def sssp(csr: Csr, source: int, out=None, stream=None, ws=None, info=None, tgraph=None):
+def sssp(csr: Csr, source: int, out=None, stream=None, ws=None, info=None, tgraph=None,
+         check: bool = True):
     """Distances from `source` (tensor of length n, of the graph's distance type).
     With `ws` (a buffer from ``workspace``) and/or `info` (from
     ``info_tensor``) the ``dawn_sssp_ws`` entry point is used; with `tgraph`
     (from ``tgraph(csr)``) ``dawn_sssp_tg_ws``, whose dense steps may pull
-    (tuning field ss_pull)."""
+    (tuning field ss_pull).  check=True synchronises the stream and raises
+    DawnError if the run did not converge (from `info`, or from
+    ``dawn_run_status`` when no info is given); check=False leaves the call
+    asynchronous."""
     torch = _torch()
     if out is None:
         out = torch.empty(csr.n, dtype=dist_dtype(csr.wtype), device=csr.rowptr.device)
@@ -297,16 +344,15 @@ def sssp(csr: Csr, source: int, out=None, stream=None, ws=None, info=None, tgrap
         p, nb = _aligned(ws)
         _check(L.dawn_sssp_tg_ws(*_csr_args(csr), _aligned(tgraph)[0], int(source), _ptr(out), p,
                                  nb, _ptr(info), _stream(stream)))
-        return out
-    if ws is None and info is None:
+    elif ws is None and info is None:
         _check(L.dawn_sssp(*_csr_args(csr), int(source), _ptr(out), _stream(stream)))
-        return out
-    own = ws is None
-    if own:
-        ws = workspace(sssp_workspace_bytes(csr.n, csr.m), csr.rowptr.device)
-    p, nb = _aligned(ws)
-    _check(L.dawn_sssp_ws(*_csr_args(csr), int(source), _ptr(out), p, nb,
-                          _ptr(info), _stream(stream)))
+    else:
+        if ws is None:
+            ws = workspace(sssp_workspace_bytes(csr.n, csr.m), csr.rowptr.device)
+        p, nb = _aligned(ws)
+        _check(L.dawn_sssp_ws(*_csr_args(csr), int(source), _ptr(out), p, nb,
+                              _ptr(info), _stream(stream)))
+    _finish(info, stream, check)
     return out
 
 
@@ -338,11 +384,13 @@ def umsssp_workspace_bytes(n: int, m: int, k: int) -> int:
     return int(load().dawn_umsssp_workspace_bytes(n, m, k))
 
 
-def umsssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None, tgraph=None):
+def umsssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None, tgraph=None,
+           check: bool = True):
     """Hop counts from each source, every edge weight taken as 1
     (``dawn_umsssp_ws``): uint32 [k, n] tensor, row j = sources[j],
     0xFFFFFFFF where unreachable.  The weights of `csr` are not read.  With
-    `tgraph` (from ``tgraph(csr)``) dense steps run as pull steps."""
+    `tgraph` (from ``tgraph(csr)``) dense steps run as pull steps.  `check`
+    as in ``sssp``."""
     torch = _torch()
     dev = csr.rowptr.device
     if not torch.is_tensor(sources):
@@ -358,12 +406,15 @@ def umsssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None, tgraph=
     L = load()
     _check(L.dawn_umsssp_ws(_ptr(csr.rowptr), _ptr(csr.colidx), csr.n, csr.m, tp, _ptr(sources),
                             k, _ptr(out), p, nb, _ptr(info), _stream(stream)))
+    _finish(info, stream, check)
     return out
 
 
-def msssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None, tgraph=None):
+def msssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None, tgraph=None,
+          check: bool = True):
     """Distances from each source: [k, n] tensor, row j = sources[j].  With
-    `tgraph` (from ``tgraph(csr)``) dense steps run as pull steps."""
+    `tgraph` (from ``tgraph(csr)``) dense steps run as pull steps.  `check` as
+    in ``sssp``."""
     torch = _torch()
     dev = csr.rowptr.device
     if not torch.is_tensor(sources):
@@ -380,24 +431,26 @@ def msssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None, tgraph=N
         tp, _ = _aligned(tgraph)
         _check(L.dawn_msssp_tg_ws(*_csr_args(csr), tp, _ptr(sources), k, _ptr(out), p, nb,
                                   _ptr(info), _stream(stream)))
-        return out
-    if ws is None and info is None:
+    elif ws is None and info is None:
         _check(L.dawn_msssp(*_csr_args(csr), _ptr(sources), k, _ptr(out), _stream(stream)))
-        return out
-    if ws is None:
-        ws = workspace(msssp_workspace_bytes(csr.n, csr.m, k), dev)
-    p, nb = _aligned(ws)
-    _check(L.dawn_msssp_ws(*_csr_args(csr), _ptr(sources), k, _ptr(out), p, nb, _ptr(info),
-                           _stream(stream)))
+    else:
+        if ws is None:
+            ws = workspace(msssp_workspace_bytes(csr.n, csr.m, k), dev)
+        p, nb = _aligned(ws)
+        _check(L.dawn_msssp_ws(*_csr_args(csr), _ptr(sources), k, _ptr(out), p, nb, _ptr(info),
+                               _stream(stream)))
+    _finish(info, stream, check)
     return out
 
 
-def apsp(csr: Csr, out=None, stream=None):
-    """All pairs: [n, n] tensor, row s = distances from s."""
+def apsp(csr: Csr, out=None, stream=None, check: bool = True):
+    """All pairs: [n, n] tensor, row s = distances from s.  `check` as in
+    ``sssp``."""
     torch = _torch()
     if out is None:
         out = torch.empty((csr.n, csr.n), dtype=dist_dtype(csr.wtype), device=csr.rowptr.device)
     _check(load().dawn_apsp(*_csr_args(csr), _ptr(out), _stream(stream)))
+    _finish(None, stream, check)
     return out
 
 
@@ -477,11 +530,19 @@ def tile_bytes(n: int, m: int, k: int) -> int:
 class Tile:
     """Per-query distance state for up to k queries on one resident graph."""
 
-    def __init__(self, csr: Csr, k: int, stream=None):
+    def __init__(self, csr: Csr, k: int, stream=None, ws=None):
+        """ws: the session's device memory (a buffer from ``workspace`` of at
+        least ``tile_bytes(n, m, k)``); allocated here when None.  The buffer is
+        kept referenced while the session lives."""
         self.csr = csr
         self.k = int(k)
+        if ws is None:
+            ws = workspace(tile_bytes(csr.n, csr.m, self.k), csr.rowptr.device)
+        self.ws = ws
+        p, nb = _aligned(ws)
         h = _vp()
-        _check(load().dawn_tile_create(ctypes.byref(h), *_csr_args(csr), self.k, _stream(stream)))
+        _check(load().dawn_tile_create(ctypes.byref(h), *_csr_args(csr), self.k, p, nb,
+                                       _stream(stream)))
         self._h = h
         torch = _torch()
         self.done_buf = torch.zeros((self.k + 31) // 32, dtype=torch.int32,
@@ -543,10 +604,11 @@ class Tile:
 def device_query() -> dict:
     """Compute units, cooperative-launch support and persistent-kernel
     occupancy of the current device (see dawn_device_query)."""
-    out = (_i32 * 8)()
+    out = (_i32 * DEVICE_QUERY_LEN)()
     _check(load().dawn_device_query(out))
     keys = ("cus", "coop", "ss_blocks_per_cu", "tile_blocks_per_cu", "ss_grid", "tile_grid",
-            "device", "wg_threads")
+            "device", "wg_threads", "ss_vgprs", "ss_lds", "ss_api_blocks_per_cu", "tile_vgprs",
+            "tile_lds", "tile_api_blocks_per_cu", "utile_blocks_per_cu", "utile_vgprs")
     return dict(zip(keys, list(out)))
 
 

@@ -1,12 +1,15 @@
 """Project autotuner for the GOVM launch parameters.
 
-Picks the tile width, degree-tier thresholds, workgroup shape, grid size and
-step-loop mode that maximise sources/s on a calibration graph of the same
-class as the target, by coordinate descent from the library defaults: each
-parameter in turn is swept over a short candidate list with the others held,
-and the best value is kept.  Every candidate runs the real HIP path; since
-the distances are unique (the fixed point of Algorithm 2 does not depend on
-how the work is split), tuning never changes results, only time.
+Picks the tile width, degree-tier thresholds, the pull-step rule (frontier
+share and source density), the sparse and group tiers, workgroup shape, grid
+size, step launches and step-loop mode that maximise sources/s on a
+calibration graph of the same class as the target, by coordinate descent from
+the library defaults: each parameter in turn is swept over a short candidate
+list (which always holds the current value) with the others held, and the best
+value is kept.  Every candidate runs the real HIP path (with the reverse graph
+when one is given, so pull steps are part of the search); since the distances
+are unique (the fixed point of Algorithm 2 does not depend on how the work is
+split), tuning never changes results, only time.
 
 Results are cached as JSON keyed by (GPU architecture, compute units, graph
 class, weight type, call kind) in $DAWN_TUNE_CACHE (default
@@ -21,7 +24,7 @@ import time
 
 import numpy as np
 
-from . import Csr, get_tuning, msssp, set_tuning, sssp, workspace
+from . import Csr, check_runs, get_tuning, msssp, set_tuning, sssp, workspace
 from . import sssp_workspace_bytes, tile_bytes
 
 SSSP_SPACE = {
@@ -34,10 +37,15 @@ SSSP_SPACE = {
 
 MSSSP_SPACE = {
     "tile_k": [64, 128, 256, 512],
-    "wg_threads": [256, 512],
-    "grid_per_cu": [8, 16, 32],
+    "tile_pull": [200, 300, 400, 600],
+    "tile_pull_src": [4, 8, 16, 32],
+    "tile_sparse": [0, 4, 8, 16],
+    "tile_t_group": [0, 8, 16],
     "tile_t_wave": [32, 64, 256],
     "tile_t_chunk": [128, 256, 1024],
+    "tile_step_launches": [12, 16, 24],
+    "wg_threads": [256, 512],
+    "grid_per_cu": [2, 4, 8],
 }
 
 
@@ -102,9 +110,13 @@ def _time_calls(fn, reps: int) -> float:
 
 
 def tune(csr: Csr, sources, kind: str = "msssp", reps: int = 2, rounds: int = 1,
-         space: dict | None = None, verbose: bool = False) -> dict:
-    """Coordinate-descent search; returns {'tuning': ..., 'sources_per_s': ...}.
-    The library tuning is restored to what it was before the call."""
+         space: dict | None = None, verbose: bool = False, tgraph=None,
+         min_gain: float = 0.03) -> dict:
+    """Coordinate-descent search; returns {'tuning': ..., 'sources_per_s': ...,
+    'default_sources_per_s': ...}.  A candidate replaces the value held only
+    when it is faster by more than `min_gain` (a fraction), so timing noise does
+    not move the result.  The library tuning is restored to what it was before
+    the call."""
     import torch
     cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
     sources = np.asarray(sources, dtype=np.int32)
@@ -120,7 +132,7 @@ def tune(csr: Csr, sources, kind: str = "msssp", reps: int = 2, rounds: int = 1,
                               else torch.float32, device=dev)
 
             def call():
-                msssp(csr, src_t, out=out, ws=ws)
+                msssp(csr, src_t, out=out, ws=ws, tgraph=tgraph, check=False)
             units = len(sources)
         else:
             ws = workspace(sssp_workspace_bytes(csr.n, csr.m), dev)
@@ -129,13 +141,21 @@ def tune(csr: Csr, sources, kind: str = "msssp", reps: int = 2, rounds: int = 1,
 
             def call():
                 for s in sources:
-                    sssp(csr, int(s), out=out, ws=ws)
+                    sssp(csr, int(s), out=out, ws=ws, tgraph=tgraph, check=False)
             units = len(sources)
 
+        set_tuning(reset=True)
+        base = get_tuning()
+        t_default = _time_calls(call, reps)
         best = {}
-        best_t = None
+        best_t = t_default
         for _ in range(rounds):
             for key, cands in space.items():
+                cur = best.get(key, base.get(key, base["grid"] // cus if key == "grid_per_cu"
+                                         else None))
+                cands = list(cands)
+                if cur is not None and cur not in cands:
+                    cands.append(cur)   # the value held now is always a candidate
                 results = []
                 for c in cands:
                     trial = dict(best)
@@ -146,10 +166,17 @@ def tune(csr: Csr, sources, kind: str = "msssp", reps: int = 2, rounds: int = 1,
                     results.append((t, c))
                     if verbose:
                         print(f"  {kind} {trial}: {units / t:.1f} sources/s", flush=True)
+                held = [t for t, c in results if c == cur]
+                t_held = held[0] if held else best_t
                 t, c = min(results)
-                best[key] = c
-                best_t = t
-        return {"tuning": _to_tuning(best, cus), "sources_per_s": units / best_t, "kind": kind}
+                if t < t_held * (1.0 - min_gain):
+                    best[key] = c
+                    best_t = t
+                else:
+                    best_t = min(best_t, t_held)
+        check_runs()
+        return {"tuning": _to_tuning(best, cus), "sources_per_s": units / best_t,
+                "default_sources_per_s": units / t_default, "kind": kind}
     finally:
         set_tuning(reset=True)
         set_tuning(**saved)
@@ -158,13 +185,16 @@ def tune(csr: Csr, sources, kind: str = "msssp", reps: int = 2, rounds: int = 1,
 def tune_cached(csr: Csr, sources, kind: str = "msssp", calibration: Csr | None = None,
                 force: bool = False, **kw) -> dict:
     """Tuning for `csr` from the cache, or found on `calibration` (a smaller
-    graph of the same class; default: `csr` itself) and stored."""
+    graph of the same class, with `sources` valid on it; default: `csr`
+    itself) and stored under `csr`'s key."""
     key = f"{device_key()}|{graph_class(csr)}|{csr.wtype}|{kind}"
     cache = _load_cache()
     if key in cache and not force:
         return cache[key]
-    res = tune(calibration if calibration is not None else csr, sources, kind, **kw)
+    target = calibration if calibration is not None else csr
+    res = tune(target, sources, kind, **kw)
     res["key"] = key
+    res["calibration"] = {"n": target.n, "m": target.m, "class": graph_class(target)}
     cache[key] = res
     _store_cache(cache)
     return res

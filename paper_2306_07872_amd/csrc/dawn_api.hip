@@ -9,7 +9,9 @@
 
 #include <algorithm>
 #include <climits>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "govm_host.hpp"
@@ -40,6 +42,12 @@ dawn_status hip_check(hipError_t e, const char* what) {
 static std::mutex g_dev_mu;
 static DevInfo g_dev[64];
 
+// Per-device run-status latch: [0] runs given no run info that ended with a
+// status other than 1, [1] the last such status.  Each device holds its own
+// copy of this array; host code reaches it only through the device address
+// hipGetSymbolAddress returns with that device current (DevInfo::latch).
+__device__ __align__(256) uint32_t g_run_latch[64];
+
 const DevInfo& dev_info() {
   int d = 0;
   if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) d = 0;
@@ -51,17 +59,68 @@ const DevInfo& dev_info() {
     hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, d);
     di.cus = cus > 0 ? cus : 1;
     di.coop = coop != 0;
+    void* p = nullptr;
+    di.latch = hipGetSymbolAddress(&p, HIP_SYMBOL(g_run_latch)) == hipSuccess
+                   ? static_cast<uint32_t*>(p) : nullptr;
     di.device = d;
   }
   return di;
+}
+
+// Residency rule of a gfx950 compute unit: 4 SIMDs, each with 512 VGPRs per
+// lane for wave64 (allocated in granules of 8) and at most 8 waves, and 160 KiB
+// of LDS shared by the CU's workgroups; a workgroup's waves are spread evenly
+// over the 4 SIMDs.  At most 16 workgroups per CU are assumed.  SGPRs are not
+// counted: every persistent kernel here is limited by its VGPRs first (the
+// compiler's own occupancy figure for each is checked against this rule).
+int resident_per_cu(int vgprs, size_t lds_bytes, int threads) {
+  if (vgprs <= 0 || threads <= 0) return 0;
+  const int waves = (threads + kWave - 1) / kWave;
+  const int per_simd = (waves + 3) / 4;
+  const int alloc = std::max(8, (vgprs + 7) / 8 * 8);
+  const int waves_per_simd = std::min(8, 512 / alloc);
+  const int by_regs = waves_per_simd / per_simd;
+  const int by_lds = lds_bytes > 0 ? (int)((size_t)160 * 1024 / lds_bytes) : 16;
+  return std::max(0, std::min(std::min(by_regs, by_lds), 16));
+}
+
+Residency residency_compute(const void* kernel, int threads, int api_per_cu) {
+  Residency r;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, kernel) == hipSuccess) {
+    r.vgprs = fa.numRegs;
+    r.lds = (int)fa.sharedSizeBytes;
+  }
+  r.api_per_cu = api_per_cu;
+  r.rule_per_cu = resident_per_cu(r.vgprs, (size_t)r.lds, threads);
+  int pc = r.rule_per_cu;
+  if (api_per_cu > 0 && api_per_cu < pc) pc = api_per_cu;
+  r.per_cu = pc < 1 ? 1 : pc;
+  r.grid = r.per_cu * dev_info().cus;
+  return r;
+}
+
+static std::mutex g_res_mu;
+static std::map<std::tuple<const void*, int, int>, Residency> g_res;
+
+// api_per_cu < 0: look up only (a miss returns an entry with grid 0).
+const Residency& residency_cached(const void* kernel, int threads, int api_per_cu) {
+  static const Residency miss{};
+  const int dev = dev_info().device;
+  std::lock_guard<std::mutex> lk(g_res_mu);
+  auto key = std::make_tuple(kernel, threads, dev);
+  auto it = g_res.find(key);
+  if (it != g_res.end()) return it->second;
+  if (api_per_cu < 0) return miss;
+  return g_res.emplace(key, residency_compute(kernel, threads, api_per_cu)).first->second;
 }
 
 static bool tuning_ok(const Tuning& t) {
   return t.t_lane >= 1 && t.t_lane <= 64 && t.t_wave >= std::max(64, t.t_lane) &&
          t.t_wave <= 65536 && t.t_chunk >= 256 && t.t_chunk <= (1 << 20) &&
          (t.wg_threads == 0 || t.wg_threads == 256 || t.wg_threads == 512 || t.wg_threads == 1024) && t.grid >= 0 &&
-         t.grid <= (1 << 20) && t.mode >= 0 && t.mode <= 2 && t.host_check >= 1 &&
-         t.host_check <= 4096 && t.tile_k >= 64 && t.tile_k <= DAWN_TILE_K_MAX &&
+         t.grid <= (1 << 20) && t.mode >= 0 && t.mode <= 2 && t.step_launches >= 0 &&
+         t.step_launches <= 4096 && t.tile_k >= 64 && t.tile_k <= DAWN_TILE_K_MAX &&
          t.tile_k % 64 == 0 && t.tile_t_wave >= 32 && t.tile_t_wave <= 65536 &&
          t.tile_t_chunk >= 64 && t.tile_t_chunk <= 65536 && (t.validate == 0 || t.validate == 1) &&
          (t.coop == 0 || t.coop == 1) && t.tile_t_group >= 0 && t.tile_t_group <= 64 &&
@@ -69,12 +128,12 @@ static bool tuning_ok(const Tuning& t) {
          t.small_m >= 0 && t.step_min_m >= 0 && t.tile_sparse >= 0 && t.tile_sparse <= 512 &&
          t.tile_pull >= 0 && t.tile_pull <= 1001 && t.tile_pull_src >= 0 &&
          t.tile_pull_src <= 512 && (t.ss_skip == 0 || t.ss_skip == 1) && t.ss_pull >= 0 &&
-         t.ss_pull <= 1001;
+         t.ss_pull <= 1001 && t.tile_step_launches >= 0 && t.tile_step_launches <= 4096 &&
+         t.barrier_ms >= 0 && t.barrier_ms <= 600000;
 }
 
-static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
-                               dawn_wtype wt, int32_t n, int32_t m, bool need_w = true,
-                               bool allow_i32 = false) {
+dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
+                        dawn_wtype wt, int32_t n, int32_t m, bool need_w, bool allow_i32) {
   if (n < 1) return set_error(DAWN_E_INVALID, "n must be >= 1 (got %d)", n);
   if (n == INT32_MAX) return set_error(DAWN_E_INVALID, "n too large");
   if (m < 0) return set_error(DAWN_E_INVALID, "m must be >= 0 (got %d)", m);
@@ -87,26 +146,6 @@ static dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, con
     return set_error(DAWN_E_UNSUPPORTED, "int32 weights: single-source calls only");
   if (!tuning_ok(g_tuning)) return set_error(DAWN_E_INVALID, "tuning out of range");
   return DAWN_OK;
-}
-
-static std::mutex g_pin_mu;
-static std::vector<uint32_t*> g_pin_free;
-
-PinnedWord::PinnedWord() {
-  std::lock_guard<std::mutex> lk(g_pin_mu);
-  if (!g_pin_free.empty()) {
-    p = g_pin_free.back();
-    g_pin_free.pop_back();
-    return;
-  }
-  void* q = nullptr;
-  if (hipHostMalloc(&q, 64, hipHostMallocDefault) == hipSuccess) p = static_cast<uint32_t*>(q);
-}
-
-PinnedWord::~PinnedWord() {
-  if (!p) return;
-  std::lock_guard<std::mutex> lk(g_pin_mu);
-  g_pin_free.push_back(p);
 }
 
 // Scratch owned for the duration of one call: hipMallocAsync / hipFreeAsync
@@ -206,6 +245,7 @@ extern "C" const char* dawn_status_str(dawn_status s) {
     case DAWN_E_UNSUPPORTED: return "unsupported";
     case DAWN_E_WORKSPACE: return "workspace too small";
     case DAWN_E_HIP: return "HIP error";
+    case DAWN_E_INCOMPLETE: return "run did not converge";
   }
   return "unknown status";
 }
@@ -215,18 +255,35 @@ extern "C" const char* dawn_last_error(void) { return g_err; }
 extern "C" dawn_status dawn_device_query(int32_t* out) {
   if (!out) return set_error(DAWN_E_INVALID, "null output");
   const DevInfo& di = dev_info();
-  int pc = 0, g = 0;
-  out[0] = di.cus;
-  out[1] = di.coop ? 1 : 0;
-  ss_persistent_occupancy(g_tuning.wg_threads, &pc, &g);
-  out[2] = pc;
-  out[4] = g;
-  tile_persistent_occupancy(g_tuning.wg_threads, &pc, &g);
-  out[3] = pc;
-  out[5] = g;
-  out[6] = di.device;
-  out[7] = g_tuning.wg_threads;  /* 0 = auto */
+  const Residency ss = ss_persistent_residency(g_tuning.wg_threads);
+  const Residency tl = tile_persistent_residency(g_tuning.wg_threads);
+  const Residency ut = utile_persistent_residency(g_tuning.wg_threads);
+  const int32_t v[DAWN_DEVICE_QUERY_LEN] = {
+      di.cus,        di.coop ? 1 : 0, ss.per_cu,    tl.per_cu,    ss.grid,      tl.grid,
+      di.device,     g_tuning.wg_threads, ss.vgprs, ss.lds,       ss.api_per_cu, tl.vgprs,
+      tl.lds,        tl.api_per_cu,   ut.per_cu,    ut.vgprs};
+  memcpy(out, v, sizeof(v));
   return DAWN_OK;
+}
+
+extern "C" dawn_status dawn_run_status(int32_t* incomplete_runs, int32_t* last_status) {
+  const DevInfo& di = dev_info();
+  if (!di.latch) return set_error(DAWN_E_HIP, "run-status latch unavailable");
+  uint32_t w[2] = {0u, 0u};
+  dawn_status st = hip_check(hipMemcpy(w, di.latch, sizeof(w), hipMemcpyDeviceToHost),
+                             "read run status");
+  if (st != DAWN_OK) return st;
+  if (w[0] != 0u) {
+    const uint32_t z[2] = {0u, 0u};
+    if ((st = hip_check(hipMemcpy(di.latch, z, sizeof(z), hipMemcpyHostToDevice),
+                        "clear run status")) != DAWN_OK)
+      return st;
+  }
+  if (incomplete_runs) *incomplete_runs = (int32_t)w[0];
+  if (last_status) *last_status = w[0] ? (int32_t)w[1] : 1;
+  if (w[0] == 0u) return DAWN_OK;
+  return set_error(DAWN_E_INCOMPLETE, "%u run(s) ended without converging (last status %d)", w[0],
+                   (int32_t)w[1]);
 }
 
 extern "C" const char* dawn_build_info(void) {
@@ -242,7 +299,7 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->wg_threads = t.wg_threads;
   out->grid = t.grid;
   out->mode = t.mode;
-  out->host_check = t.host_check;
+  out->step_launches = t.step_launches;
   out->tile_k = t.tile_k;
   out->tile_t_wave = t.tile_t_wave;
   out->tile_t_chunk = t.tile_t_chunk;
@@ -257,6 +314,8 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->tile_pull_src = t.tile_pull_src;
   out->ss_skip = t.ss_skip;
   out->ss_pull = t.ss_pull;
+  out->tile_step_launches = t.tile_step_launches;
+  out->barrier_ms = t.barrier_ms;
   return DAWN_OK;
 }
 
@@ -269,7 +328,7 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.wg_threads = in->wg_threads;
     t.grid = in->grid;
     t.mode = in->mode;
-    t.host_check = in->host_check;
+    t.step_launches = in->step_launches;
     t.tile_k = in->tile_k;
     t.tile_t_wave = in->tile_t_wave;
     t.tile_t_chunk = in->tile_t_chunk;
@@ -284,6 +343,8 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.tile_pull_src = in->tile_pull_src;
     t.ss_skip = in->ss_skip;
     t.ss_pull = in->ss_pull;
+    t.tile_step_launches = in->tile_step_launches;
+    t.barrier_ms = in->barrier_ms;
   }
   if (!tuning_ok(t)) return set_error(DAWN_E_INVALID, "tuning out of range");
   g_tuning = t;
@@ -378,6 +439,12 @@ __global__ void dawn_info_add_kernel(dawn_run_info* acc, const dawn_run_info* pa
   acc->union_edges += part->union_edges;
 }
 
+// A multi-source run, tile by tile.  Each tile: reset, seeding,
+// `tile_step_launches` step launches (a step launch returns at once once the
+// tile's run has ended), then one persistent launch for whatever steps remain
+// (tuning mode 2: the persistent launch alone), the transposed store and the
+// run summary.  Nothing waits on the host, so the whole call is a fixed launch
+// sequence on `stream` that a HIP graph can capture.
 static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, const void* weights,
                               dawn_wtype wt, int32_t n, int32_t m, const int32_t* sources,
                               int32_t k, void* dist_out, void* ws, dawn_run_info* info,
@@ -396,40 +463,27 @@ static dawn_status msssp_impl(const int32_t* rowptr, const int32_t* colidx, cons
   // per-tile summary, inside the workspace (no allocation on this path)
   dawn_run_info* part = reinterpret_cast<dawn_run_info*>(static_cast<char*>(ws) + L.info);
   dawn_status st;
-  // auto: step launches (a tile step has plenty of work to fill the device
-  // at full occupancy, and R-MAT-like graphs take few steps); hop-count
-  // tiles always take step launches
-  const int mode = unweighted || g_tuning.mode == 0 ? 1 : g_tuning.mode;
+  const int32_t launches =
+      g_tuning.mode == 2 ? 0 : (int32_t)std::min<int64_t>(g_tuning.tile_step_launches, (int64_t)n + 1);
   for (int32_t j0 = 0; j0 < k; j0 += kt) {
     const int32_t cnt = std::min(kt, k - j0);
     if ((st = tile_reset(A, f32, stream)) != DAWN_OK) return st;
     if ((st = tile_seed_all(A, sources + j0, cnt, g_tuning.validate != 0, f32, stream)) != DAWN_OK)
       return st;
-    if (mode == 2) {
-      if ((st = tile_steps(A, f32, true, INT32_MAX, stream)) != DAWN_OK) return st;
-    } else {
-      PinnedWord done;
-      if (!done.p) return set_error(DAWN_E_HIP, "hipHostMalloc failed");
-      *done.p = 0;
-      // the first two checks come after host_check / 4 launches each: a
-      // small-world graph's tile takes about 8 to 16 steps, and every launch
-      // queued past the end costs a few microseconds for nothing
-      for (int64_t launched = 0, i = 0; launched <= n; i++) {
-        const int chunk = i < 2 ? std::max(1, g_tuning.host_check / 4) : g_tuning.host_check;
-        st = unweighted ? utile_steps(A, chunk, stream) : tile_steps(A, f32, false, chunk, stream);
-        if (st != DAWN_OK) break;
-        launched += chunk;
-        hipMemcpyAsync(done.p, &A.ctl->done, 4, hipMemcpyDeviceToHost, stream);
-        if (hipStreamSynchronize(stream) != hipSuccess || *done.p) break;
-      }
+    if (launches > 0) {
+      st = unweighted ? utile_steps(A, launches, stream) : tile_steps(A, f32, false, launches, stream);
       if (st != DAWN_OK) return st;
     }
+    st = unweighted ? utile_persistent(A, stream) : tile_steps(A, f32, true, INT32_MAX, stream);
+    if (st != DAWN_OK) return st;
     char* out = static_cast<char*>(dist_out) + (size_t)j0 * (size_t)n * 4;
     st = unweighted ? utile_store(A, 0, cnt, reinterpret_cast<uint32_t*>(out), n, stream)
                     : tile_store(A, 0, cnt, out, n, stream);
     if (st != DAWN_OK) return st;
+    // with run info: this tile's summary, summed into the caller's; without:
+    // the tile's status into the run-status latch
+    if ((st = tile_info(A, info ? part : nullptr, stream)) != DAWN_OK) return st;
     if (info) {
-      if ((st = tile_info(A, part, stream)) != DAWN_OK) return st;
       hipLaunchKernelGGL(dawn_info_add_kernel, dim3(1), dim3(64), 0, stream, info, part,
                          (int)(j0 == 0));
       if ((st = hip_check(hipGetLastError(), "info")) != DAWN_OK) return st;
@@ -707,8 +761,6 @@ extern "C" dawn_status dawn_batch_run(dawn_batch* b, const int32_t* sources, voi
 extern "C" dawn_status dawn_batch_capture(dawn_batch* b, const int32_t* sources, void* dist_out,
                                           dawn_run_info* info, hipStream_t stream) {
   if (!b || !sources || !dist_out) return set_error(DAWN_E_INVALID, "null pointer");
-  if (g_tuning.mode == 1)
-    return set_error(DAWN_E_UNSUPPORTED, "step launches alone (mode 1) cannot be captured");
   dawn_status st;
   if (b->exec) {
     hipGraphExecDestroy(b->exec);
@@ -758,7 +810,7 @@ extern "C" void dawn_batch_destroy(dawn_batch* b) { batch_free(b); }
 struct dawn_tile {
   TileLayout L;
   TileArgs A;
-  void* ws = nullptr;
+  void* ws = nullptr;            // the caller's workspace (not owned)
   bool f32 = false;
   int32_t k = 0;
   const void* tgraph = nullptr;  // reverse graph for pull steps, or null
@@ -782,7 +834,8 @@ extern "C" size_t dawn_tile_bytes(int32_t n, int32_t m, int32_t k) {
 
 extern "C" dawn_status dawn_tile_create(dawn_tile** out, const int32_t* rowptr,
                                         const int32_t* colidx, const void* weights, dawn_wtype wt,
-                                        int32_t n, int32_t m, int32_t k, hipStream_t stream) {
+                                        int32_t n, int32_t m, int32_t k, void* ws, size_t ws_bytes,
+                                        hipStream_t stream) {
   if (!out) return set_error(DAWN_E_INVALID, "null output");
   *out = nullptr;
   dawn_status st = check_graph(rowptr, colidx, weights, wt, n, m);
@@ -790,17 +843,19 @@ extern "C" dawn_status dawn_tile_create(dawn_tile** out, const int32_t* rowptr,
   if (wt == DAWN_W_UNIT) return set_error(DAWN_E_UNSUPPORTED, "unit weights: not in a tile session");
   if (k < 1) return set_error(DAWN_E_INVALID, "k must be >= 1");
   if (k > DAWN_TILE_K_MAX) return set_error(DAWN_E_UNSUPPORTED, "k above %d", DAWN_TILE_K_MAX);
+  if (!ws) return set_error(DAWN_E_INVALID, "workspace is null");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0)
+    return set_error(DAWN_E_INVALID, "workspace must be 256-byte aligned");
+  const TileLayout L = tile_layout(n, m, k);
+  if (ws_bytes < L.total)
+    return set_error(DAWN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
   dawn_tile* t = new dawn_tile();
-  t->L = tile_layout(n, m, k);
+  t->L = L;
   t->f32 = wt == DAWN_W_F32;
   t->k = k;
-  if ((st = hip_check(hipMalloc(&t->ws, t->L.total), "hipMalloc tile")) != DAWN_OK) {
-    delete t;
-    return st;
-  }
+  t->ws = ws;
   t->A = tile_args(rowptr, colidx, weights, n, m, t->L, t->ws);
   if ((st = tile_reset(t->A, t->f32, stream)) != DAWN_OK) {
-    hipFree(t->ws);
     delete t;
     return st;
   }
@@ -903,6 +958,5 @@ extern "C" void dawn_tile_destroy(dawn_tile* t) {
   if (!t) return;
   tile_graph_free(t);
   if (t->cap_stream) hipStreamDestroy(t->cap_stream);
-  hipFree(t->ws);
   delete t;
 }

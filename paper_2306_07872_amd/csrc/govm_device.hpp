@@ -240,12 +240,15 @@ __device__ __forceinline__ void wave_push(bool pred, int32_t val, int32_t* q, ui
 // write before the barrier visible to every read after it, across the L2s of
 // all XCDs.  The wait is bounded by wall-clock time (s_memrealtime runs at
 // 100 MHz): past the bound the block raises `abort` and every block leaves, so
-// the kernel always terminates.
+// the kernel always terminates.  The bound (`ticks`, tuning field barrier_ms)
+// is a kernel argument; 0 gives up at the first wait that is not already
+// satisfied, which lets a test force the failure path from the host.
 // ---------------------------------------------------------------------------
-constexpr unsigned long long kBarrierTimeoutTicks = 400000000ull;  // 4 s at 100 MHz
+constexpr unsigned long long kTicksPerMs = 100000ull;  // s_memrealtime: 100 MHz
 
 __device__ __forceinline__ bool grid_sync(uint32_t* bar, uint32_t* abort_flag, uint32_t nblocks,
-                                          uint32_t base, uint32_t& epoch) {
+                                          uint32_t base, uint32_t& epoch,
+                                          unsigned long long ticks) {
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -263,7 +266,7 @@ __device__ __forceinline__ bool grid_sync(uint32_t* bar, uint32_t* abort_flag, u
       const uint32_t cur = ld_agent(bar);
       if ((int32_t)(cur - target) >= 0) break;
       if ((it & 7u) == 7u && ld_agent(abort_flag)) { ok = 0; break; }
-      if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks) {
+      if (__builtin_amdgcn_s_memrealtime() - t0 > ticks) {
         st_agent(abort_flag, 1u);
         ok = 0;
         break;
@@ -404,6 +407,8 @@ struct SsArgs {
   uint32_t* bm[2];        // beta dedup bitmaps [step % 2]
   uint32_t cap_v, cap_wg;
   SsCtl* ctl;
+  unsigned long long bar_ticks;  // grid-barrier wait bound (persistent launches)
+  uint32_t* latch;               // run-status latch of the device (runs without run info)
 };
 
 
@@ -432,6 +437,8 @@ struct TileArgs {
   // that reached each pair, [nplanes][n][nseg]; D is null there
   unsigned long long* planes;
   int32_t nplanes;
+  unsigned long long bar_ticks;  // grid-barrier wait bound (persistent launches)
+  uint32_t* latch;               // run-status latch of the device (runs without run info)
 };
 
 }  // namespace dawn

@@ -17,7 +17,7 @@ struct Tuning {
   int32_t wg_threads = 0;
   int32_t grid = 0;
   int32_t mode = 0;
-  int32_t host_check = 32;
+  int32_t step_launches = 20;
   int32_t tile_k = 256;
   int32_t tile_t_wave = 64;
   int32_t tile_t_chunk = 256;
@@ -32,6 +32,8 @@ struct Tuning {
   int32_t tile_pull_src = 16;
   int32_t ss_skip = 1;
   int32_t ss_pull = 1001;
+  int32_t tile_step_launches = 16;
+  int32_t barrier_ms = 4000;
 };
 
 Tuning& tuning();
@@ -40,8 +42,53 @@ struct DevInfo {
   int device = -1;
   int cus = 0;
   bool coop = false;
+  uint32_t* latch = nullptr;  // this device's run-status latch (device address)
 };
 const DevInfo& dev_info();
+
+// Run-status latch of the current device: runs that are given no
+// dawn_run_info record here a status other than 1 (converged), for
+// dawn_run_status.  latch[0] counts such runs, latch[1] holds the last status.
+__device__ __forceinline__ void latch_status(uint32_t* latch, int32_t conv) {
+  if (conv != 1 && latch) {
+    atomicAdd(&latch[0], 1u);
+    atomicExch(&latch[1], (uint32_t)conv);
+  }
+}
+
+// Status of a run from its control words: 1 converged, 0 step cap, -1 failed
+// validation or a bad source, -2 a persistent launch gave up at a grid
+// barrier, -3 a frontier queue overflowed (cannot happen on a valid CSR).
+__device__ __forceinline__ int32_t run_status(int32_t converged, uint32_t abort,
+                                              uint32_t overflow) {
+  if (abort) return -2;
+  if (overflow) return -3;
+  return converged;
+}
+
+// Workgroups of `threads` threads one compute unit holds at once for a kernel
+// with these compiled resources (see resident_per_cu in dawn_api.hip).
+int resident_per_cu(int vgprs, size_t lds_bytes, int threads);
+
+// Persistent-grid sizing of a kernel: the smaller of the residency derived from
+// its compiled resources and the runtime's occupancy figure, times the CUs.
+struct Residency {
+  int vgprs = 0, lds = 0, api_per_cu = 0, rule_per_cu = 0, per_cu = 0, grid = 0;
+};
+Residency residency_compute(const void* kernel, int threads, int api_per_cu);
+// Cached per (kernel, threads, device): the queries run once, outside any
+// graph capture that a later call may be part of.
+const Residency& residency_cached(const void* kernel, int threads, int api_per_cu);
+template <typename K>
+Residency residency_of(K kernel, int threads) {
+  const void* key = reinterpret_cast<const void*>(kernel);
+  int api = -1;  // queried only on a cache miss
+  const Residency* r = &residency_cached(key, threads, api);
+  if (r->grid > 0) return *r;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&api, kernel, threads, 0) != hipSuccess)
+    api = 0;
+  return residency_cached(key, threads, api);
+}
 
 // Carves a workspace into 256-byte aligned pieces.
 struct Carver {
@@ -70,8 +117,9 @@ struct SsSeeds {
   int32_t source = 0;
 };
 
-// Enqueue a full single-source (or many-seed) GOVM run on `stream`.
-// capture=true: never use a cooperative launch (HIP graph capture).
+// Enqueue a full single-source (or many-seed) GOVM run on `stream`; nothing
+// waits on the host.  capture=true: never use a cooperative launch (HIP graph
+// capture).  Without `info` the run's status goes to the run-status latch.
 dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, int wt,
                    int32_t n, int32_t m, const SsSeeds& seeds, bool guard_source, void* dist,
                    void* ws, dawn_run_info* info, hipStream_t stream, bool capture,
@@ -106,6 +154,8 @@ dawn_status tile_done_bits(const TileArgs& a, int32_t k, uint32_t* done_bits, hi
 dawn_status tile_store(const TileArgs& a, int32_t col0, int32_t count, void* out, int64_t ld,
                        hipStream_t stream);
 dawn_status tile_read_col(const TileArgs& a, int32_t col, void* out, hipStream_t stream);
+// The run summary into `info`, or, with info == NULL, the run's status into the
+// run-status latch (when it is not 1).
 dawn_status tile_info(const TileArgs& a, dawn_run_info* info, hipStream_t stream);
 dawn_status tile_col_steps(const TileArgs& a, int32_t k, int32_t* out, hipStream_t stream);
 // Hop-count tiles (unit weights): `max_steps` step launches; distances out
@@ -114,9 +164,14 @@ dawn_status utile_steps(const TileArgs& a, int32_t max_steps, hipStream_t stream
 dawn_status utile_store(const TileArgs& a, int32_t col0, int32_t count, uint32_t* out, int64_t ld,
                         hipStream_t stream);
 
-// Persistent grid sizes (workgroups per CU, total) at `threads` per workgroup.
-void ss_persistent_occupancy(int threads, int* per_cu, int* grid);
-void tile_persistent_occupancy(int threads, int* per_cu, int* grid);
+// Persistent grid sizing of the single-source, tile and hop-count-tile
+// persistent kernels at `threads` per workgroup (0: the default).
+Residency ss_persistent_residency(int threads);
+Residency tile_persistent_residency(int threads);
+Residency utile_persistent_residency(int threads);
+// Hop-count tiles: the rest of the run (until no column is active, at most n
+// steps) in one persistent launch (returns at once when the run has ended).
+dawn_status utile_persistent(const TileArgs& a, hipStream_t stream);
 
 // ----- measurement -------------------------------------------------------------
 // Bracket a main launch with events when the kernel timer is on.
@@ -130,19 +185,11 @@ dawn_status tgraph_build(const int32_t* rowptr, const int32_t* colidx, const voi
                          int64_t m, void* buf, void* scratch, hipStream_t stream);
 TGraph tgraph_view(const void* buf, int64_t n, int64_t m);
 
-// ----- host polling -----------------------------------------------------------
-// A pinned host word for reading a device flag after a stream synchronisation.
-// Pinned allocations cost far more than a step, so words come from a
-// process-wide pool and go back to it (the pool lives until the process ends).
-struct PinnedWord {
-  uint32_t* p = nullptr;
-  PinnedWord();
-  ~PinnedWord();
-  PinnedWord(const PinnedWord&) = delete;
-  PinnedWord& operator=(const PinnedWord&) = delete;
-};
-
 // ----- misc ------------------------------------------------------------------
+// Host-side checks of a call's graph arguments and of the current tuning.
+dawn_status check_graph(const int32_t* rowptr, const int32_t* colidx, const void* w,
+                        dawn_wtype wt, int32_t n, int32_t m, bool need_w = true,
+                        bool allow_i32 = false);
 dawn_status set_error(dawn_status s, const char* fmt, ...);
 dawn_status hip_check(hipError_t e, const char* what);
 

@@ -23,8 +23,9 @@
 //   the candidate is smaller.  Order of updates inside a step does not matter:
 //   the fixed point is unique (Section 3.5: the method does not care in which
 //   order paths appear).
-// - Step loop: one persistent cooperative launch with a grid barrier per step
-//   (used by default), or one launch per step with last-block bookkeeping.
+// - Step loop: one persistent launch with a grid barrier per step, or a fixed
+//   number of launches of one step each (last-block bookkeeping) followed by
+//   the persistent launch for the remaining steps.  The host never waits.
 #include <stdio.h>
 
 #include <algorithm>
@@ -106,26 +107,28 @@ __global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* 
   }
 }
 
-// int32 weights: keys back to int32 values (INF -> INT32_MAX), and a path sum
-// that left the int32 range makes the run count as not converged.
-__global__ void ss_decode_i32_kernel(uint32_t* dist, int64_t n, const SsCtl* C,
-                                     dawn_run_info* info) {
+// int32 weights: keys back to int32 values (INF -> INT32_MAX).
+__global__ void ss_decode_i32_kernel(uint32_t* dist, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
     dist[i] ^= 0x80000000u;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && info && ld_agent(&C->negfloor) &&
-      info->converged == 1)
-    info->converged = 0;
 }
 
+// The end of a run's bookkeeping (one thread): the run's status (see
+// run_status; with int32 weights a path sum that left the int32 range also
+// makes the run count as not converged) and counters go to `info`, or, when
+// the caller gave none, a status other than 1 goes to the run-status latch.
 template <int WT>
-__global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void ss_report(SsCtl* C, dawn_run_info* info, uint32_t* latch) {
+  int32_t conv = run_status(ld_agent_i(&C->converged), ld_agent(&C->abort), ld_agent(&C->overflow));
+  if (WT == kWI32 && conv == 1 && ld_agent(&C->negfloor)) conv = 0;
+  if (!info) {
+    latch_status(latch, conv);
+    return;
+  }
   const unsigned long long fe = ld_agent64(&C->ctr.fe);
   const unsigned long long es = ld_agent64(&C->ctr.es);
   const unsigned long long im = ld_agent64(&C->ctr.im);
-  int32_t conv = ld_agent_i(&C->converged);
-  if (ld_agent(&C->abort)) conv = -2;
   info->steps = (int32_t)ld_agent(&C->step);
   info->converged = conv;
   info->frontier_entries = (int64_t)fe;
@@ -133,6 +136,12 @@ __global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info) {
   info->improvements = (int64_t)im;
   info->union_rows = (int64_t)fe;
   info->union_edges = (int64_t)es;
+}
+
+template <int WT>
+__global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info, uint32_t* latch) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  ss_report<WT>(C, info, latch);
 }
 
 // ---------------------------------------------------------------------------
@@ -520,7 +529,9 @@ __device__ __forceinline__ void ss_zero_rotation(SsCtl* C, uint32_t step) {
 }
 
 // All steps in one launch; a grid barrier separates the steps.  The grid must
-// be co-resident (its size comes from the occupancy query, halved).
+// be co-resident: its size is what the compute units hold at once by the
+// kernel's compiled resources (residency_of); should a barrier wait still give
+// up, the run ends with status -2, reported to the caller.
 template <int WT>
 __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
   __shared__ SsShared sh;
@@ -534,7 +545,7 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
   for (;;) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
     ss_step<WT, false>(A, step, blockIdx.x, gridDim.x, acc, sh);
-    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch)) {
+    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch, A.bar_ticks)) {
       status = -2;
       break;
     }
@@ -742,15 +753,7 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
       st_agent_i(&C->converged, status);
       st_agent(&C->done, 1u);
     }
-    if (info) {
-      info->steps = (int32_t)ld_agent(&C->step);
-      info->converged = ld_agent_i(&C->converged);
-      info->frontier_entries = (int64_t)ld_agent64(&S.fe);
-      info->edges_scanned = (int64_t)ld_agent64(&S.es);
-      info->improvements = (int64_t)ld_agent64(&S.im);
-      info->union_rows = info->frontier_entries;
-      info->union_edges = info->edges_scanned;
-    }
+    ss_report<WT>(C, info, A.latch);
   }
 }
 
@@ -912,15 +915,7 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
       st_agent_i(&C->converged, status);
       st_agent(&C->done, 1u);
     }
-    if (info) {
-      info->steps = (int32_t)ld_agent(&C->step);
-      info->converged = ld_agent_i(&C->converged);
-      info->frontier_entries = (int64_t)ld_agent64(&S.fe);
-      info->edges_scanned = (int64_t)ld_agent64(&S.es);
-      info->improvements = (int64_t)ld_agent64(&S.im);
-      info->union_rows = info->frontier_entries;
-      info->union_edges = info->edges_scanned;
-    }
+    ss_report<WT>(C, info, A.latch);
   }
 }
 
@@ -944,24 +939,9 @@ SsLayout ss_layout(int64_t n, int64_t m) {
   return L;
 }
 
-template <typename K>
-static int persistent_grid(K kernel, int threads, int* per_cu_out = nullptr) {
-  const DevInfo& di = dev_info();
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  // Measured on MI355X: the occupancy query reports twice the workgroups per CU
-  // that are resident together (a 2048-workgroup grid of 256 threads never
-  // completed its first barrier; 1024 did), so a persistent grid takes half.
-  per_cu = std::max(1, per_cu / 2);
-  if (per_cu_out) *per_cu_out = per_cu;
-  return per_cu * di.cus;
-}
-
-void ss_persistent_occupancy(int threads, int* per_cu, int* grid) {
+Residency ss_persistent_residency(int threads) {
   if (threads <= 0) threads = 1024;
-  *grid = persistent_grid(ss_persistent_kernel<kWU32>, threads, per_cu);
+  return residency_of(ss_persistent_kernel<kWU32>, threads);
 }
 
 template <int WT>
@@ -970,13 +950,19 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
                             hipStream_t stream, bool capture) {
   const Tuning& T = tuning();
   const DevInfo& di = dev_info();
-  const int auto_threads = (T.mode == 0 && (int64_t)A.m >= (int64_t)T.step_min_m) ||
-                                   T.mode == 1
-                               ? 512
-                               : 1024;
-  const int threads = T.wg_threads > 0 ? T.wg_threads : auto_threads;
+  // mode 0 picks: one workgroup when m <= small_m; step launches first when
+  // m >= step_min_m; otherwise the persistent launch alone.  Measured on
+  // MI355X: on R-MAT scale 22 (67M edges) step launches of 512-thread
+  // workgroups take a third of the time of the persistent launch; on
+  // 16.7M-edge graphs (R-MAT scale 20, the 2048^2 grid) the persistent launch
+  // of 1024-thread workgroups is faster.
+  int mode = T.mode;
+  if (mode == 0) mode = (int64_t)A.m <= (int64_t)T.small_m ? 3
+                        : (int64_t)A.m >= (int64_t)T.step_min_m ? 1 : 2;
+  const int threads = T.wg_threads > 0 ? T.wg_threads : mode == 1 ? 512 : 1024;
   const int fill_blocks = (int)std::min<int64_t>(4096, (A.n + 255) / 256 + 1);
-  if (T.mode == 0 && (int64_t)A.m <= (int64_t)T.small_m) {
+  dawn_status st;
+  if (mode == 3) {
     // one workgroup, one launch (after the optional device validation)
     if (T.validate) {
       hipLaunchKernelGGL(ss_fill_kernel<WT>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
@@ -997,7 +983,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
     ktimer_end(tk, stream, 1);
     if constexpr (WT == kWI32)
       hipLaunchKernelGGL(ss_decode_i32_kernel, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
-                         (int64_t)A.n, A.ctl, info);
+                         (int64_t)A.n);
     return hip_check(hipGetLastError(), "small-graph launch");
   }
   hipLaunchKernelGGL(ss_fill_kernel<WT>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
@@ -1009,57 +995,25 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
   }
   hipLaunchKernelGGL(ss_seed_kernel<WT>, dim3(1), dim3(256), 0, stream, A, seeds.sources_dev,
                      seeds.voff_dev, seeds.count, seeds.source);
-  dawn_status st = hip_check(hipGetLastError(), "init launch");
-  if (st != DAWN_OK) return st;
+  if ((st = hip_check(hipGetLastError(), "init launch")) != DAWN_OK) return st;
 
-  // mode 0 on graphs of at least step_min_m edges: step launches for the
-  // first `host_check` steps (such runs, with few large steps, mostly finish
-  // there), then -- if the run goes on -- one persistent launch for the rest;
-  // smaller graphs use the persistent launch at once.  Measured on MI355X: on
-  // R-MAT scale 22 (67M edges) step launches of 512-thread workgroups take a
-  // third of the time of the persistent launch; on 16.7M-edge graphs (R-MAT
-  // scale 20, the 2048^2 grid) the persistent launch of 1024-thread workgroups
-  // is faster.  A captured run cannot wait on the host: it always enqueues the
-  // `host_check` step launches and the persistent launch, and every launch
-  // after the run has finished returns at once.
-  int mode = T.mode;
-  if (mode == 0) mode = (int64_t)A.m < (int64_t)T.step_min_m ? 2 : 3;
-  bool finished = false;
-  if (mode == 1 && capture)
-    return set_error(DAWN_E_UNSUPPORTED, "step launches alone (mode 1) cannot be captured");
-  if ((mode == 1 || mode == 3) && capture) {
+  // Mode 1: `step_launches` step launches, then one persistent launch for
+  // whatever steps remain.  Nothing waits on the host: every launch after the
+  // run has ended returns at once, so the call is a fixed launch sequence that
+  // a HIP graph can capture.
+  if (mode == 1) {
     const int grid = T.grid > 0 ? T.grid : 4 * di.cus;
     auto stepk = A.pull_min >= 0 ? ss_step_kernel<WT, true> : ss_step_kernel<WT, false>;
-    const int64_t chunk = std::min<int64_t>(T.host_check, (int64_t)A.n + 1);
-    for (int64_t s = 0; s < chunk; s++)
+    const int chunk = (int)std::min<int64_t>(T.step_launches, (int64_t)A.n + 1);
+    void* tk = capture ? nullptr : ktimer_begin(stream);
+    for (int s = 0; s < chunk; s++)
       hipLaunchKernelGGL(stepk, dim3(grid), dim3(threads), 0, stream, A);
-    st = hip_check(hipGetLastError(), "step launches");
-    if (st != DAWN_OK) return st;
-  } else if (mode == 1 || mode == 3) {
-    const int grid = T.grid > 0 ? T.grid : 4 * di.cus;
-    auto stepk = A.pull_min >= 0 ? ss_step_kernel<WT, true> : ss_step_kernel<WT, false>;
-    PinnedWord done;
-    if (!done.p) return set_error(DAWN_E_HIP, "hipHostMalloc failed");
-    *done.p = 0;
-    int64_t launched = 0;
-    const int64_t cap = (int64_t)A.n + 1;
-    while (launched < cap) {
-      const int chunk = (int)std::min<int64_t>(T.host_check, cap - launched);
-      void* tk = ktimer_begin(stream);
-      for (int s = 0; s < chunk; s++)
-        hipLaunchKernelGGL(stepk, dim3(grid), dim3(threads), 0, stream, A);
-      ktimer_end(tk, stream, chunk);
-      launched += chunk;
-      hipMemcpyAsync(done.p, &A.ctl->done, 4, hipMemcpyDeviceToHost, stream);
-      if (hipStreamSynchronize(stream) != hipSuccess) break;
-      if (*done.p) { finished = true; break; }
-      if (mode == 3) break;
-    }
-    st = hip_check(hipGetLastError(), "step launches");
-    if (st != DAWN_OK) return st;
+    ktimer_end(tk, stream, chunk);
+    if ((st = hip_check(hipGetLastError(), "step launches")) != DAWN_OK) return st;
   }
-  if (mode == 2 || (mode == 3 && !finished)) {
-    int grid = persistent_grid(ss_persistent_kernel<WT>, threads);
+  {
+    const Residency r = residency_of(ss_persistent_kernel<WT>, threads);
+    int grid = r.grid;
     if (T.grid > 0 && T.grid < grid) grid = T.grid;
     SsArgs a = A;
     a.pull_min = -1;  // pull steps need step launches (the last workgroup clears the bitmap)
@@ -1074,16 +1028,13 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
       e = hipGetLastError();
     }
     ktimer_end(tk, stream, 1);
-    st = hip_check(e, "persistent launch");
-    if (st != DAWN_OK) return st;
+    if ((st = hip_check(e, "persistent launch")) != DAWN_OK) return st;
   }
-  if (info) {
-    hipLaunchKernelGGL(ss_finalize_kernel<WT>, dim3(1), dim3(64), 0, stream, A.ctl, info);
-    st = hip_check(hipGetLastError(), "finalize launch");
-  }
+  hipLaunchKernelGGL(ss_finalize_kernel<WT>, dim3(1), dim3(64), 0, stream, A.ctl, info, A.latch);
+  if ((st = hip_check(hipGetLastError(), "finalize launch")) != DAWN_OK) return st;
   if constexpr (WT == kWI32) {
     hipLaunchKernelGGL(ss_decode_i32_kernel, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
-                       (int64_t)A.n, A.ctl, info);
+                       (int64_t)A.n);
     st = hip_check(hipGetLastError(), "decode launch");
   }
   return st;
@@ -1123,6 +1074,11 @@ dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.cap_v = L.cap_v;
   A.cap_wg = L.cap_wg;
   A.ctl = reinterpret_cast<SsCtl*>(base + L.ctl);
+  A.bar_ticks = (unsigned long long)T.barrier_ms * kTicksPerMs;
+  A.latch = dev_info().latch;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    capture = true;
   if (wt == kWF32) return ss_run_t<kWF32>(A, rowptr, colidx, seeds, L, info, stream, capture);
   if (wt == kWUNIT) return ss_run_t<kWUNIT>(A, rowptr, colidx, seeds, L, info, stream, capture);
   if (wt == kWI32) return ss_run_t<kWI32>(A, rowptr, colidx, seeds, L, info, stream, capture);

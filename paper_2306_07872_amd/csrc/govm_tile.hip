@@ -694,13 +694,13 @@ __global__ void __launch_bounds__(1024) tile_persistent_kernel(TileArgs A, int32
   for (;;) {
     if (blockIdx.x == 0) tile_prologue(C, step, A.K);
     tile_compact<false>(A, step, blockIdx.x, gridDim.x, acc, csh);
-    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch)) {
+    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch, A.bar_ticks)) {
       status = -2;
       finished = true;
       break;
     }
     tile_relax<F32>(A, step, blockIdx.x, gridDim.x, sh_colact);
-    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch)) {
+    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch, A.bar_ticks)) {
       status = -2;
       finished = true;
       break;
@@ -1057,19 +1057,18 @@ __device__ __forceinline__ void utile_push_rows(const TileArgs& A, int q, int qn
   }
 }
 
+// One push step of a hop-count tile over workgroups gb of nb (every thread of
+// the workgroup calls it).
 template <int S>
-__global__ void __launch_bounds__(1024) utile_push_kernel(TileArgs A, int32_t cap_n) {
-  __shared__ unsigned long long sh_colact[kSegMax];
+__device__ void utile_push_step(const TileArgs& A, uint32_t step, uint32_t gb, uint32_t nb,
+                                unsigned long long* sh_colact) {
   TileCtl* C = A.ctl;
-  if (ld_agent(&C->done)) return;
-  const uint32_t step = ld_agent(&C->step);
-  if (tile_is_pull_step(A, step)) return;  // the pull kernel runs this step
   const int q = step % 3, qn = (step + 1) % 3, rc = step % kRot, rn = (step + 1) % kRot;
-  tile_clear_prev(A, step, blockIdx.x, gridDim.x);
+  tile_clear_prev(A, step, gb, nb);
   if (threadIdx.x < kSegMax) sh_colact[threadIdx.x] = 0ull;
   __syncthreads();
   const int lane = lane_id(), W = blockDim.x >> 6;
-  const uint32_t gw = blockIdx.x * W + (threadIdx.x >> 6), nwv = gridDim.x * W;
+  const uint32_t gw = gb * W + (threadIdx.x >> 6), nwv = nb * W;
   const uint32_t n0 = min(ld_agent(&C->cnt[rc][0].v), A.cap_v);
   const uint32_t n1 = min(ld_agent(&C->cnt[rc][1].v), A.cap_v);
   const uint32_t n2 = min(ld_agent(&C->cnt[rc][2].v), A.cap_wg);
@@ -1112,7 +1111,58 @@ __global__ void __launch_bounds__(1024) utile_push_kernel(TileArgs A, int32_t ca
   __syncthreads();
   if ((int)threadIdx.x < A.nseg && sh_colact[threadIdx.x])
     or_new_bits(&C->colact[rn][threadIdx.x], sh_colact[threadIdx.x]);
+}
+
+template <int S>
+__global__ void __launch_bounds__(1024) utile_push_kernel(TileArgs A, int32_t cap_n) {
+  __shared__ unsigned long long sh_colact[kSegMax];
+  TileCtl* C = A.ctl;
+  if (ld_agent(&C->done)) return;
+  const uint32_t step = ld_agent(&C->step);
+  if (tile_is_pull_step(A, step)) return;  // the pull kernel runs this step
+  utile_push_step<S>(A, step, blockIdx.x, gridDim.x, sh_colact);
   tile_end_step(A, step, cap_n);
+}
+
+// The remaining steps of a hop-count tile in one launch (push steps only),
+// with a grid barrier after each compaction and each push step; at most n
+// steps in all.  As tile_persistent_kernel.
+template <int S>
+__global__ void __launch_bounds__(1024) utile_persistent_kernel(TileArgs A) {
+  __shared__ unsigned long long sh_colact[kSegMax];
+  __shared__ CompactShared csh;
+  TileCtl* C = A.ctl;
+  if (ld_agent(&C->done)) return;
+  Acc acc;
+  uint32_t epoch = 0;
+  const uint32_t bar_base = ld_agent(&C->bar_base);
+  uint32_t step = ld_agent(&C->step);
+  int32_t status = 1;
+  for (;;) {
+    if (blockIdx.x == 0) tile_prologue(C, step, A.K);
+    tile_compact<true>(A, step, blockIdx.x, gridDim.x, acc, csh);
+    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch, A.bar_ticks)) {
+      status = -2;
+      break;
+    }
+    utile_push_step<S>(A, step, blockIdx.x, gridDim.x, sh_colact);
+    if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch, A.bar_ticks)) {
+      status = -2;
+      break;
+    }
+    const bool act = any_active(C, (step + 1) % kRot, A.nseg);
+    step++;
+    if (!act) break;
+    if (step >= (uint32_t)A.n) { status = 0; break; }
+  }
+  CtrStripe& Sx = C->ctr[blockIdx.x % kCtrStripes];
+  flush_acc(acc, &Sx.fe, &Sx.es, &Sx.im, &Sx.sa, &Sx.se);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st_agent(&C->step, step);
+    st_agent(&C->bar_base, bar_base + epoch * gridDim.x);
+    st_agent_i(&C->converged, status);
+    st_agent(&C->done, 1u);
+  }
 }
 
 // Pull: each 16-lane group takes one in-edge chunk of a target v, 16 in-edges
@@ -1272,7 +1322,10 @@ __global__ void tile_done_bits_kernel(const TileCtl* C, int32_t k, uint32_t* don
   done[w] = live & ~act & valid;
 }
 
-__global__ void tile_info_kernel(const TileCtl* C, int32_t K, dawn_run_info* info) {
+// The run summary (info non-null), or the run's status into the run-status
+// latch when it is not 1 (info null).
+__global__ void tile_info_kernel(const TileCtl* C, int32_t K, dawn_run_info* info,
+                                 uint32_t* latch) {
   __shared__ int32_t s_max;
   if (threadIdx.x == 0) s_max = 0;
   __syncthreads();
@@ -1281,8 +1334,12 @@ __global__ void tile_info_kernel(const TileCtl* C, int32_t K, dawn_run_info* inf
   atomicMax(&s_max, mx);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  int32_t conv = ld_agent_i(&C->converged);
-  if (ld_agent(&C->abort)) conv = -2;
+  const int32_t conv = run_status(ld_agent_i(&C->converged), ld_agent(&C->abort),
+                                  ld_agent(&C->overflow));
+  if (!info) {
+    latch_status(latch, conv);
+    return;
+  }
   info->steps = s_max;
   info->converged = conv;
   unsigned long long fe = 0, es = 0, im = 0, sa = 0, se = 0;
@@ -1371,6 +1428,8 @@ TileArgs tile_args(const int32_t* rowptr, const int32_t* colidx, const void* w, 
   A.vis = L.unweighted ? reinterpret_cast<unsigned long long*>(base + L.vis) : nullptr;
   A.planes = L.unweighted ? reinterpret_cast<unsigned long long*>(base + L.planes) : nullptr;
   A.nplanes = L.unweighted ? L.nplanes : 0;
+  A.bar_ticks = (unsigned long long)T.barrier_ms * kTicksPerMs;
+  A.latch = dev_info().latch;
   return A;
 }
 
@@ -1417,24 +1476,45 @@ dawn_status tile_evict(const TileArgs& a, bool f32, int32_t col, hipStream_t str
   return hip_check(hipGetLastError(), "tile evict");
 }
 
-template <typename K>
-static int persistent_grid_t(K kernel, int threads, int* per_cu_out = nullptr, size_t dyn = 0) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, dyn) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  // Measured on MI355X: the occupancy query reports twice the workgroups per CU
-  // that are resident together (a 2048-workgroup grid of 256 threads never
-  // completed its first barrier; 1024 did), so a persistent grid takes half.
-  per_cu = std::max(1, per_cu / 2);
-  if (per_cu_out) *per_cu_out = per_cu;
-  return per_cu * dev_info().cus;
+Residency tile_persistent_residency(int threads) {
+  if (threads <= 0) threads = 256;
+  return residency_of(tile_persistent_kernel<false>, threads);
 }
 
-void tile_persistent_occupancy(int threads, int* per_cu, int* grid) {
+Residency utile_persistent_residency(int threads) {
   if (threads <= 0) threads = 256;
-  *grid = persistent_grid_t(tile_persistent_kernel<false>, threads, per_cu,
-                            0);
+  return residency_of(utile_persistent_kernel<4>, threads);
+}
+
+// Launch a persistent kernel on `grid` x `threads` (cooperatively when asked
+// for and the stream is not being captured).
+template <typename K, typename... Args>
+static hipError_t launch_persistent(K kernel, int grid, int threads, hipStream_t stream,
+                                    Args... args) {
+  const Tuning& T = tuning();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const bool capturing =
+      hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+  if (dev_info().coop && T.coop && !capturing) {
+    void* ptrs[] = {&args...};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kernel), dim3(grid),
+                                      dim3(threads), ptrs, 0, stream);
+  }
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, stream, args...);
+  return hipGetLastError();
+}
+
+dawn_status utile_persistent(const TileArgs& a, hipStream_t stream) {
+  const Tuning& T = tuning();
+  const int threads = T.wg_threads > 0 ? T.wg_threads : 256;
+  auto k = a.nseg <= 1 ? utile_persistent_kernel<1> : a.nseg <= 2 ? utile_persistent_kernel<2>
+         : a.nseg <= 4 ? utile_persistent_kernel<4> : utile_persistent_kernel<8>;
+  int grid = residency_of(k, threads).grid;
+  if (T.grid > 0 && T.grid < grid) grid = T.grid;
+  void* tk = ktimer_begin(stream);
+  const hipError_t e = launch_persistent(k, grid, threads, stream, a);
+  ktimer_end(tk, stream, 1);
+  return hip_check(e, "hop-count tile persistent launch");
 }
 
 template <bool F32>
@@ -1444,22 +1524,13 @@ static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_
   const int threads = T.wg_threads > 0 ? T.wg_threads : 256;
   const int32_t cap_n = persistent ? 1 : 0;
   if (persistent) {
-    int grid = persistent_grid_t(tile_persistent_kernel<F32>, threads, nullptr, 0);
+    int grid = residency_of(tile_persistent_kernel<F32>, threads).grid;
     if (T.grid > 0 && T.grid < grid) grid = T.grid;
     TileArgs aa = a;
     aa.pull_min = -1;  // pull steps need the step-launch path
-    int32_t ms = max_steps, cn = cap_n;
-    void* args[] = {&aa, &ms, &cn};
-    hipError_t e;
     void* tk = ktimer_begin(stream);
-    if (dev_info().coop && T.coop) {
-      e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&tile_persistent_kernel<F32>),
-                                     dim3(grid), dim3(threads), args, 0, stream);
-    } else {
-      hipLaunchKernelGGL(tile_persistent_kernel<F32>, dim3(grid), dim3(threads), 0, stream, aa,
-                         ms, cn);
-      e = hipGetLastError();
-    }
+    const hipError_t e =
+        launch_persistent(tile_persistent_kernel<F32>, grid, threads, stream, aa, max_steps, cap_n);
     ktimer_end(tk, stream, 1);
     return hip_check(e, "tile persistent launch");
   }
@@ -1545,7 +1616,7 @@ dawn_status tile_read_col(const TileArgs& a, int32_t col, void* out, hipStream_t
 }
 
 dawn_status tile_info(const TileArgs& a, dawn_run_info* info, hipStream_t stream) {
-  hipLaunchKernelGGL(tile_info_kernel, dim3(1), dim3(256), 0, stream, a.ctl, a.K, info);
+  hipLaunchKernelGGL(tile_info_kernel, dim3(1), dim3(256), 0, stream, a.ctl, a.K, info, a.latch);
   return hip_check(hipGetLastError(), "tile info");
 }
 

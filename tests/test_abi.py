@@ -51,7 +51,9 @@ def test_tuning_roundtrip_and_range_checks(lib):
                 dict(tile_t_group=65), dict(tile_t_group=64, tile_t_wave=64),
                 dict(tile_skip=2), dict(small_m=-1), dict(step_min_m=-1), dict(tile_pull=1002),
                 dict(tile_pull_src=-1), dict(tile_pull_src=513), dict(ss_skip=2), dict(ss_pull=1002),
-                dict(tile_sparse=513)):
+                dict(tile_sparse=513), dict(step_launches=-1), dict(step_launches=4097),
+                dict(tile_step_launches=-1), dict(tile_step_launches=4097), dict(barrier_ms=-1),
+                dict(barrier_ms=600001)):
         with pytest.raises(dawn.DawnError) as e:
             dawn.set_tuning(**bad)
         assert e.value.status == 1
@@ -137,4 +139,28 @@ def test_int32_weights_are_single_source_only(lib):
     assert lib.dawn_sssp(fake, fake, fake, 4, 5, 3, 0, fake, null) == 1
     # unit weights (3): not in batches or tile sessions
     h = ctypes.c_void_p()
-    assert lib.dawn_tile_create(ctypes.byref(h), fake, fake, null, 3, 5, 3, 64, null) == 2
+    assert lib.dawn_tile_create(ctypes.byref(h), fake, fake, null, 3, 5, 3, 64, ws, 1 << 30,
+                                null) == 2
+
+
+def test_tile_session_takes_caller_workspace(lib):
+    """dawn_tile_create allocates nothing: it needs a caller workspace of at
+    least dawn_tile_bytes, 256-byte aligned (checked before any device call)."""
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)
+    h = ctypes.c_void_p()
+    need = lib.dawn_tile_bytes(100, 1000, 64)
+    assert need > 100 * 64 * 4
+    assert lib.dawn_tile_create(ctypes.byref(h), fake, fake, fake, 0, 100, 1000, 64, null, need,
+                                null) == 1
+    assert lib.dawn_tile_create(ctypes.byref(h), fake, fake, fake, 0, 100, 1000, 64,
+                                ctypes.c_void_p(0x100010), need, null) == 1
+    assert b"aligned" in lib.dawn_last_error()
+    assert lib.dawn_tile_create(ctypes.byref(h), fake, fake, fake, 0, 100, 1000, 64,
+                                ctypes.c_void_p(0x100000), need - 1, null) == 3
+    assert h.value is None
+
+
+def test_incomplete_status_code(lib):
+    assert lib.dawn_status_str(5) == b"run did not converge"
+    assert dawn.E_INCOMPLETE == 5

@@ -43,7 +43,9 @@ TILE_TUNINGS = [
     dict(tile_k=64, tile_t_wave=32, tile_t_chunk=64),
     dict(tile_k=128, tile_t_wave=65536, wg_threads=1024),
     dict(tile_k=512, tile_t_wave=40, tile_t_chunk=100, wg_threads=512, grid=5),
-    dict(mode=1, host_check=3, tile_t_wave=32, tile_t_chunk=64),
+    dict(mode=1, tile_step_launches=3, tile_t_wave=32, tile_t_chunk=64),
+    dict(tile_step_launches=4096),          # every step a step launch
+    dict(tile_step_launches=1, tile_t_wave=32, tile_t_chunk=64),
     dict(tile_t_group=0, tile_skip=0),
     dict(tile_t_group=31, tile_t_wave=32, tile_t_chunk=64, wg_threads=512),
     dict(mode=2, tile_skip=0),
@@ -142,10 +144,11 @@ def test_batch_union_matches_each_graph(dawn):
 
 
 # captured: the persistent launch alone; step launches then the persistent
-# launch for the rest (host_check 3); step launches covering every step, the
-# persistent launch returning at once (host_check 64)
-CAPTURE_TUNINGS = [dict(), dict(small_m=0, step_min_m=0, host_check=3),
-                   dict(small_m=0, step_min_m=0, host_check=64)]
+# launch for the rest (3 step launches); step launches covering every step, the
+# persistent launch returning at once (64 step launches); mode 1 explicitly
+CAPTURE_TUNINGS = [dict(), dict(small_m=0, step_min_m=0, step_launches=3),
+                   dict(small_m=0, step_min_m=0, step_launches=64),
+                   dict(small_m=0, mode=1, step_launches=5)]
 
 
 @pytest.mark.parametrize("ti", range(len(CAPTURE_TUNINGS)))
@@ -158,21 +161,6 @@ def test_batch_graph_capture_replay(dawn, ti):
     finally:
         if prev is not None:
             dawn.set_tuning(**prev)
-
-
-def test_batch_capture_rejects_step_launches_alone(dawn):
-    import torch
-    gs = _batch_graphs(count=2, seed=3)
-    b = dawn.Batch([dawn.Csr.from_graph(g) for g, _ in gs])
-    srcs = torch.tensor([s for _, s in gs], dtype=torch.int32, device="cuda")
-    out = torch.empty(b.total_n, dtype=torch.float32, device="cuda")
-    prev = dawn.set_tuning(mode=1)
-    try:
-        with pytest.raises(dawn.DawnError):
-            b.capture(srcs, out)
-    finally:
-        dawn.set_tuning(**prev)
-        b.close()
 
 
 def _capture_replay(dawn, ti):

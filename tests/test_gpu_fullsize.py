@@ -1,0 +1,88 @@
+"""Parity at the configured sizes of the many-graph launch and the serving
+workload, launched as the measurements launch them.
+
+- 64 uneven directed ER graphs (n = 10^U(4,6), m = 8n, fp32 lognormal; about
+  14.7M vertices and 118M edges in one union): four graphs (the smallest, the
+  largest and two others) are compared element by element with the oracle
+  (bit for bit against the fp32-fold mode, within the fp64 tolerance), and
+  every graph's result is checked with invariants V1-V4, which pin it
+  exactly.
+- Serving: queries on the largest serving graph (R-MAT scale 22, edge factor
+  32, uint32 weights, 134M edges) submitted in a mix with queries on two
+  other serving graphs; two are compared element by element with Dijkstra,
+  the rest with the invariants, and every answer equals the same query run
+  alone."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from graphgen import workloads
+from gpu_helpers import announce, assert_sssp_matches, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.mark.timeout(900)
+def test_many_graph_launch_full_size(dawn):
+    import torch
+    gs = workloads.er_batch(count=64)
+    tot_n = sum(g.n for g, _ in gs)
+    tot_m = sum(g.m for g, _ in gs)
+    announce("c4b full size: 64 graphs, n", tot_n, "m", tot_m)
+    csrs = [dawn.Csr.from_graph(g) for g, _ in gs]
+    b = dawn.Batch(csrs)
+    assert (b.total_n, b.total_m) == (tot_n, tot_m)
+    srcs = torch.tensor([s for _, s in gs], dtype=torch.int32, device="cuda")
+    info = dawn.info_tensor()
+    out = b.run(srcs, info=info)
+    torch.cuda.synchronize()
+    assert dawn.read_info(info)["converged"] == 1
+    parts = [to_np(d) for d in b.split(out)]
+    b.close()
+    order = sorted(range(len(gs)), key=lambda i: gs[i][0].n)
+    full = {order[0], order[-1], order[len(order) // 3], order[2 * len(order) // 3]}
+    for i, ((g, s), d) in enumerate(zip(gs, parts)):
+        if i in full:
+            assert_sssp_matches(g, s, d, tag=f"c4b graph {i} (n={g.n})")
+        else:
+            rc, v = oracle.check(g, s, d)
+            assert rc == 0, f"c4b graph {i}: invariant V{rc} at vertex {v}"
+
+
+@pytest.mark.timeout(1100)
+def test_serving_largest_graph_in_a_mix(dawn):
+    import torch
+    from paper_2306_07872_amd import serve
+    spec = workloads.serving_graph_spec(26)
+    assert (spec["scale"], spec["edge_factor"], spec["weights"]) == (22, 32, "u32")
+    big = workloads.serving_graph(26)
+    others = [workloads.serving_graph(1), workloads.serving_graph(12)]   # fp32 16, u32 20
+    gs = [big] + others
+    announce("c5 largest graph: n", big.n, "m", big.m)
+    csrs = [dawn.Csr.from_graph(g) for g in gs]
+    srv = serve.Server(tile_k=64, steps_per_tick=4, max_tiles_per_graph=2, pull=True,
+                       graphs=True)
+    for i, c in enumerate(csrs):
+        srv.add_graph(i, c)
+    rng = np.random.default_rng(26)
+    pools = [graphgen.pick_sources(g, 16, 260 + i) for i, g in enumerate(gs)]
+    qs = []
+    for t in range(40):
+        gi = 0 if t % 3 == 0 else 1 + int(rng.integers(0, 2))
+        qs.append(srv.submit(gi, int(pools[gi][t % 16])))
+        srv.tick()                               # arrivals interleave with running work
+    srv.run_until_idle()
+    torch.cuda.synchronize()
+    srv.close()
+    assert all(q.state == "done" for q in qs)
+    on_big = [q for q in qs if q.gid == 0]
+    assert len(on_big) >= 10
+    for q in on_big[:2]:
+        assert_sssp_matches(big, q.source, q.result, tag=f"c5 big q{q.qid}")
+    for q in on_big[2:5] + [q for q in qs if q.gid != 0][:6]:
+        rc, v = oracle.check(gs[q.gid], q.source, q.result)
+        assert rc == 0, f"q{q.qid} graph {q.gid}: invariant V{rc} at vertex {v}"
+    for q in on_big[:4]:
+        alone = to_np(dawn.sssp(csrs[0], q.source))
+        assert np.array_equal(np.asarray(q.result).view(np.uint32), alone.view(np.uint32))

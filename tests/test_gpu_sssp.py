@@ -52,15 +52,16 @@ TUNINGS = [
     dict(t_lane=64, t_wave=65536, t_chunk=1 << 20),
     dict(t_lane=4, t_wave=100, t_chunk=300, wg_threads=1024),
     dict(t_lane=8, t_wave=64, t_chunk=256, wg_threads=512, grid=7),
-    dict(mode=1, grid=3, host_check=1),
-    dict(mode=1, t_lane=2, t_wave=64, t_chunk=256, host_check=5),
+    dict(mode=1, grid=3, step_launches=1),
+    dict(mode=1, grid=3, step_launches=4096),  # every step a step launch
+    dict(mode=1, t_lane=2, t_wave=64, t_chunk=256, step_launches=5),
     dict(small_m=1 << 30),                    # one workgroup for the whole graph
     dict(small_m=1 << 30, wg_threads=256),
-    dict(step_min_m=0, host_check=2),         # step launches, then a persistent launch
-    dict(step_min_m=0, host_check=1, wg_threads=1024, t_lane=2, t_wave=64, t_chunk=256),
+    dict(step_min_m=0, step_launches=2),      # step launches, then a persistent launch
+    dict(step_min_m=0, step_launches=1, wg_threads=1024, t_lane=2, t_wave=64, t_chunk=256),
     dict(step_min_m=0),
     dict(ss_skip=0, small_m=0),                # every frontier row expanded in its step
-    dict(ss_skip=0, small_m=0, mode=1, t_lane=2, t_wave=64, t_chunk=256, host_check=3),
+    dict(ss_skip=0, small_m=0, mode=1, t_lane=2, t_wave=64, t_chunk=256, step_launches=3),
 ]
 
 
@@ -215,7 +216,7 @@ def test_device_validation_flags_bad_csr(dawn):
         for gg, exp in ((g, 1), (bad, -1)):
             csr = dawn.Csr.from_graph(gg)
             info = dawn.info_tensor()
-            out = dawn.sssp(csr, 0, info=info)
+            out = dawn.sssp(csr, 0, info=info, check=False)
             torch.cuda.synchronize()
             assert dawn.read_info(info)["converged"] == exp
             if exp == -1:
@@ -260,11 +261,12 @@ def test_full_size_grid_sampled(dawn):
 
 # --- pull steps on the single-source path (dawn_sssp_tg_ws) -------------------
 
-PULL_SS = [dict(small_m=0, mode=1, ss_pull=0),                 # every step a pull step
-           dict(small_m=0, mode=1, ss_pull=200, host_check=3), # by frontier size
-           dict(small_m=0, step_min_m=0, ss_pull=0, host_check=2),  # steps, then persistent
+PULL_SS = [dict(small_m=0, mode=1, ss_pull=0, step_launches=4096),    # every step a pull step
+           dict(small_m=0, mode=1, ss_pull=200, step_launches=3),    # by frontier size
+           dict(small_m=0, step_min_m=0, ss_pull=0, step_launches=2),  # steps, then persistent
            dict(small_m=0, mode=2, ss_pull=0),                 # persistent: never pulls
-           dict(small_m=0, mode=1, ss_pull=0, ss_skip=0, t_lane=2, t_wave=64, t_chunk=256)]
+           dict(small_m=0, mode=1, ss_pull=0, ss_skip=0, t_lane=2, t_wave=64, t_chunk=256,
+                step_launches=4096)]
 
 
 def _sssp_tg(dawn, csr, s, tg, **tune):

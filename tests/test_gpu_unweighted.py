@@ -21,7 +21,7 @@ def _umsssp(dawn, csr, sources, tg=None, **tune):
     prev = dawn.set_tuning(**tune) if tune else None
     try:
         info = dawn.info_tensor()
-        out = dawn.umsssp(csr, sources, info=info, tgraph=tg)
+        out = dawn.umsssp(csr, sources, info=info, tgraph=tg, check=False)
         torch.cuda.synchronize()
         return to_np(out), dawn.read_info(info)
     finally:
@@ -182,8 +182,9 @@ def test_umsssp_full_size_rmat20_sampled(dawn):
 
 # --- the unit weight type (DAWN_W_UNIT): weights never read ------------------
 
-UNIT_SSSP_TUNINGS = [dict(), dict(small_m=0, mode=2), dict(small_m=0, mode=1, host_check=3),
-                     dict(small_m=0, step_min_m=0, host_check=2), dict(small_m=0, ss_skip=0)]
+UNIT_SSSP_TUNINGS = [dict(), dict(small_m=0, mode=2), dict(small_m=0, mode=1, step_launches=3),
+                     dict(small_m=0, step_min_m=0, step_launches=2), dict(small_m=0, ss_skip=0),
+                     dict(small_m=0, mode=1, step_launches=4096)]
 
 
 @pytest.mark.parametrize("ti", range(len(UNIT_SSSP_TUNINGS)))

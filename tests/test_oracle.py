@@ -271,6 +271,31 @@ def test_govm_restatement_equals_dijkstra(wk):
             assert np.array_equal(d.view(np.uint32), ref.view(np.uint32))
 
 
+def test_govm_per_vertex_updates():
+    """Path-update counts (Section 4.2): hand-worked on a triangle (the direct
+    edge 0 -> 1 is found first and replaced a step later by 0 -> 2 -> 1), one
+    update per reached vertex at unit weights (a shortest path found is never
+    updated again), and the counts sum to the improvements."""
+    g = graphgen.from_edges(3, [0, 0, 2], [1, 2, 1], np.array([5, 1, 1], np.uint32), "u32")
+    d, c = oracle.govm(g, 0, per_vertex=True)
+    assert d.tolist() == [0, 2, 1]
+    assert c["updates"].tolist() == [0, 2, 1]
+    assert c["improvements"] == 3 and c["steps"] == 3
+    gu = graphgen.rmat(11, 8, 13, weights="u32one")
+    for s in graphgen.pick_sources(gu, 3, 2):
+        _, c = oracle.govm(gu, int(s), per_vertex=True)
+        reach = oracle.bfs(gu, int(s)) >= 0
+        exp = reach.astype(np.int32)
+        exp[int(s)] = 0
+        assert np.array_equal(c["updates"], exp)
+    gw = graphgen.rmat(11, 8, 13, weights="u32")
+    s = int(graphgen.pick_sources(gw, 1, 4)[0])
+    for order in (0, 1, 2):
+        _, c = oracle.govm(gw, s, order=order, seed=1, per_vertex=True)
+        assert int(c["updates"].sum()) == c["improvements"]
+        assert int(c["updates"].max()) >= 2   # weighted: some paths are updated again
+
+
 # ---------------------------------------------------------------------------
 # invariant checker: accepts the truth, rejects planted mistakes
 # ---------------------------------------------------------------------------
