@@ -638,7 +638,11 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
     if (threadIdx.x == 0) {
       sh.cnt_next = 0u;
       sh.upd = 0u;
-      atomicExch(&C->negfloor, 0u);  // (an atomic, as the later reports are)
+      // the status words the report reads: the workspace may hold an earlier
+      // run's (atomics, as the later reports are)
+      atomicExch(&C->negfloor, 0u);
+      atomicExch(&C->abort, 0u);
+      atomicExch(&C->overflow, 0u);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
@@ -798,7 +802,11 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
     if (threadIdx.x == 0) {
       sh.cnt_next = 0u;
       sh.upd = 0u;
-      atomicExch(&C->negfloor, 0u);  // (an atomic, as the later reports are)
+      // the status words the report reads: the workspace may hold an earlier
+      // run's (atomics, as the later reports are)
+      atomicExch(&C->negfloor, 0u);
+      atomicExch(&C->abort, 0u);
+      atomicExch(&C->overflow, 0u);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
     __syncthreads();

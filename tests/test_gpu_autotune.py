@@ -22,25 +22,32 @@ def test_autotune_keeps_results_and_caches(dawn, tmp_path, monkeypatch):
     prev = dawn.get_tuning()
     try:
         announce("autotune msssp")
-        small = {"tile_k": [64, 128], "grid_per_cu": [8, 16], "tile_t_wave": [32, 256]}
-        r = autotune.tune_cached(csr, srcs, "msssp", space=small, reps=1)
-        assert r["sources_per_s"] > 0 and "tile_k" in r["tuning"]
+        small = {"tile_k": [64, 128], "grid_per_cu": [8, 16], "tile_t_wave": [32, 256],
+                 "tile_pull": [0, 1001]}
+        # min_gain = -1: every field takes its fastest candidate, so the tuning
+        # checked below is one the search chose, not the defaults
+        r = autotune.tune_cached(csr, srcs, "msssp", space=small, reps=1, min_gain=-1.0,
+                                 tgraph=dawn.tgraph(csr))
+        assert r["sources_per_s"] > 0
+        assert {"tile_k", "grid", "tile_t_wave", "tile_pull"} == set(r["tuning"])
         assert json.load(open(tmp_path / "tune.json"))[r["key"]]["tuning"] == r["tuning"]
         autotune.apply(r)
-        tuned = to_np(dawn.msssp(csr, srcs))
+        tuned = to_np(dawn.msssp(csr, srcs, tgraph=dawn.tgraph(csr)))
         torch.cuda.synchronize()
         for j in range(0, len(srcs), 7):
             assert_sssp_matches(g, int(srcs[j]), tuned[j], tag=f"tuned msssp col {j}")
         announce("autotune sssp")
         r1 = autotune.tune_cached(csr, srcs[:4], "sssp",
-                                  space={"wg_threads": [256, 1024], "mode": [1, 2]}, reps=1)
+                                  space={"wg_threads": [256, 1024], "mode": [1, 2]}, reps=1,
+                                  min_gain=-1.0)
+        assert {"wg_threads", "mode"} == set(r1["tuning"])
         autotune.apply(r1)
         for s in srcs[:3]:
             d1 = to_np(dawn.sssp(csr, int(s)))
             ref, _ = oracle.sssp(g, int(s), "u32")
             assert np.array_equal(d1.view(np.uint32), ref)
         # a second call is served from the cache
-        again = autotune.tune_cached(csr, srcs, "msssp", space=small, reps=1)
+        again = autotune.tune_cached(csr, srcs, "msssp", space=small, reps=1, min_gain=-1.0)
         assert again == json.load(open(tmp_path / "tune.json"))[r["key"]]
     finally:
         dawn.set_tuning(reset=True)
