@@ -260,6 +260,25 @@ dawn_status dawn_sssp_tg_ws(const int32_t* rowptr_dev, const int32_t* colidx_dev
                             void* ws_dev, size_t ws_bytes, dawn_run_info* info_dev,
                             hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): dawn_sssp
+ * with its workspace taken from a fixed array of DAWN_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device it runs on until the process ends.
+ * The call allocates nothing (no hipMalloc, hipMallocAsync or hipFree, no
+ * timing events) and launches the same kernels as dawn_sssp; the kernels clear
+ * what must start at zero, so the array's contents from earlier calls do not
+ * matter.  Graphs whose dawn_sssp_workspace_bytes exceeds the array return
+ * DAWN_E_WORKSPACE before anything is launched (about 16 bytes per vertex plus
+ * 0.62 bytes per edge: R-MAT scale 21 with 33.5M edges fits).  Every call on a
+ * device shares that device's array: calls that overlap on one device (two
+ * streams, two threads) race and give wrong distances; order them on one
+ * stream.  A run that does not converge is reported by dawn_run_status, as for
+ * dawn_sssp. */
+#define DAWN_NOALLOC_SCRATCH_BYTES (64u << 20)
+dawn_status dawn_sssp_noalloc(const int32_t* rowptr_dev, const int32_t* colidx_dev,
+                              const void* weights_dev, dawn_wtype wt, int32_t n, int32_t m,
+                              int32_t source, void* dist_out_dev, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Multi source.  sources_dev: int32[k] on the device (duplicates allowed).
  * dist_out_dev: k x n row-major, row j = distances from sources[j].  Sources

@@ -79,6 +79,7 @@ def load():
         "dawn_sssp": ([_vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp], _i32),
         "dawn_sssp_workspace_bytes": ([_i32, _i32], _sz),
         "dawn_sssp_ws": ([_vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _sz, _vp, _vp], _i32),
+        "dawn_sssp_noalloc": ([_vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp], _i32),
         "dawn_msssp": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp], _i32),
         "dawn_msssp_workspace_bytes": ([_i32, _i32, _i32], _sz),
         "dawn_msssp_ws": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _sz, _vp, _vp],
@@ -132,7 +133,7 @@ def exported_symbols() -> list[str]:
     return [
         "dawn_status_str", "dawn_last_error", "dawn_build_info", "dawn_get_tuning",
         "dawn_set_tuning", "dawn_sssp", "dawn_sssp_workspace_bytes", "dawn_sssp_ws",
-        "dawn_sssp_tg_ws",
+        "dawn_sssp_tg_ws", "dawn_sssp_noalloc",
         "dawn_msssp", "dawn_msssp_workspace_bytes", "dawn_msssp_ws", "dawn_apsp",
         "dawn_tgraph_bytes", "dawn_tgraph_build_bytes", "dawn_tgraph_build", "dawn_msssp_tg_ws",
         "dawn_umsssp_workspace_bytes", "dawn_umsssp_ws", "dawn_batch_create", "dawn_batch_sizes", "dawn_batch_vertex_offset", "dawn_batch_run",
@@ -353,6 +354,25 @@ def sssp(csr: Csr, source: int, out=None, stream=None, ws=None, info=None, tgrap
         _check(L.dawn_sssp_ws(*_csr_args(csr), int(source), _ptr(out), p, nb,
                               _ptr(info), _stream(stream)))
     _finish(info, stream, check)
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def sssp_noalloc(csr: Csr, source: int, out, stream=None, check: bool = True):
+    """``dawn_sssp_noalloc``: distances from `source` into the caller's `out`
+    (length n, the graph's distance type), with the library's fixed per-device
+    scratch array as workspace, so the call allocates no device memory.  Graphs
+    needing more than NOALLOC_SCRATCH_BYTES of workspace raise DawnError
+    (workspace too small).  Calls on one device share the array: order them on
+    one stream.  check=True synchronises and raises if the run did not
+    converge (``dawn_run_status``)."""
+    if out.numel() < csr.n or out.element_size() != 4 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous 4-byte tensor of at least n elements")
+    L = load()
+    _check(L.dawn_sssp_noalloc(*_csr_args(csr), int(source), _ptr(out), _stream(stream)))
+    _finish(None, stream, check)
     return out
 
 

@@ -48,6 +48,12 @@ static DevInfo g_dev[64];
 // hipGetSymbolAddress returns with that device current (DevInfo::latch).
 __device__ __align__(256) uint32_t g_run_latch[64];
 
+// Workspace of dawn_sssp_noalloc: one copy per device, held by the loaded code
+// object until the process ends.  Host code never names the array in a launch
+// or copy; it uses the device address that hipGetSymbolAddress returned with
+// that device current (DevInfo::noalloc).
+static __device__ __align__(256) unsigned char g_noalloc_scratch[DAWN_NOALLOC_SCRATCH_BYTES];
+
 const DevInfo& dev_info() {
   int d = 0;
   if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) d = 0;
@@ -62,6 +68,9 @@ const DevInfo& dev_info() {
     void* p = nullptr;
     di.latch = hipGetSymbolAddress(&p, HIP_SYMBOL(g_run_latch)) == hipSuccess
                    ? static_cast<uint32_t*>(p) : nullptr;
+    // The array's name is a host-side stand-in: kernels get this address.
+    void* q = nullptr;
+    di.noalloc = hipGetSymbolAddress(&q, HIP_SYMBOL(g_noalloc_scratch)) == hipSuccess ? q : nullptr;
     di.device = d;
   }
   return di;
@@ -410,6 +419,29 @@ extern "C" dawn_status dawn_sssp(const int32_t* rowptr, const int32_t* colidx, c
   if ((st = ws.alloc(bytes)) != DAWN_OK) return st;
   return dawn_sssp_ws(rowptr, colidx, weights, wt, n, m, source, dist_out, ws.p, bytes, nullptr,
                       stream);
+}
+
+extern "C" dawn_status dawn_sssp_noalloc(const int32_t* rowptr, const int32_t* colidx,
+                                         const void* weights, dawn_wtype wt, int32_t n,
+                                         int32_t m, int32_t source, void* dist_out,
+                                         hipStream_t stream) {
+  dawn_status st = check_graph(rowptr, colidx, weights, wt, n, m, true, true);
+  if (st != DAWN_OK) return st;
+  if (source < 0 || source >= n) return set_error(DAWN_E_INVALID, "source %d out of range", source);
+  if (!dist_out) return set_error(DAWN_E_INVALID, "dist_out is null");
+  const size_t bytes = ss_layout(n, m).total;
+  if (bytes > (size_t)DAWN_NOALLOC_SCRATCH_BYTES)
+    return set_error(DAWN_E_WORKSPACE,
+                     "graph needs %zu bytes of scratch; dawn_sssp_noalloc holds %zu (use dawn_sssp_ws)",
+                     bytes, (size_t)DAWN_NOALLOC_SCRATCH_BYTES);
+  const DevInfo& di = dev_info();
+  if (!di.noalloc) return set_error(DAWN_E_HIP, "no-allocation scratch unavailable on this device");
+  SsSeeds seeds;
+  seeds.source = source;
+  // capture = true: no timing events (creating them may allocate) and no
+  // cooperative launch; the launch sequence is the same as dawn_sssp's.
+  return ss_run(rowptr, colidx, weights, (int)wt, n, m, seeds, true, dist_out, di.noalloc,
+                nullptr, stream, true);
 }
 
 // ---------------------------------------------------------------------------

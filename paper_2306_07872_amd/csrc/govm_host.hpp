@@ -43,6 +43,7 @@ struct DevInfo {
   int cus = 0;
   bool coop = false;
   uint32_t* latch = nullptr;  // this device's run-status latch (device address)
+  void* noalloc = nullptr;    // this device's copy of the no-allocation scratch array
 };
 const DevInfo& dev_info();
 

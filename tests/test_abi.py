@@ -164,3 +164,20 @@ def test_tile_session_takes_caller_workspace(lib):
 def test_incomplete_status_code(lib):
     assert lib.dawn_status_str(5) == b"run did not converge"
     assert dawn.E_INCOMPLETE == 5
+
+
+def test_noalloc_call_host_checks(lib):
+    """dawn_sssp_noalloc rejects, before touching the device, graphs whose
+    workspace exceeds its fixed scratch array (and the usual bad arguments)."""
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)
+    cap = dawn.NOALLOC_SCRATCH_BYTES
+    assert cap == 64 << 20
+    n, m = 4_194_304, 67_108_864
+    assert lib.dawn_sssp_workspace_bytes(n, m) > cap
+    assert lib.dawn_sssp_noalloc(fake, fake, fake, 0, n, m, 0, fake, null) == 3
+    assert b"dawn_sssp_ws" in lib.dawn_last_error()
+    assert lib.dawn_sssp_workspace_bytes(2_097_152, 33_554_432) <= cap
+    assert lib.dawn_sssp_noalloc(fake, fake, fake, 0, 0, 0, 0, fake, null) == 1
+    assert lib.dawn_sssp_noalloc(fake, fake, fake, 0, 5, 3, 5, fake, null) == 1
+    assert lib.dawn_sssp_noalloc(fake, fake, fake, 0, 5, 3, 0, null, null) == 1
