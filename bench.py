@@ -179,6 +179,20 @@ def main() -> int:
         torch.cuda.synchronize()
         log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
         del a, b
+        # a gather of known bytes, shaped like the tile's pull steps: distinct
+        # random 1 KiB rows (256 uint32) of a table of `copy_calibration` MiB
+        rows = args.copy_calibration * 1024
+        src = torch.ones((rows, 256), dtype=torch.int32, device="cuda")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        idx = torch.randperm(rows, device="cuda", generator=g)[:rows // 4]
+        torch.cuda.synchronize()
+        dst = torch.index_select(src, 0, idx)
+        torch.cuda.synchronize()
+        log(f"gather calibration: {rows // 4} distinct random 1 KiB rows: "
+            f"{rows // 4 / 1024:.0f} MiB of rows + {idx.numel() * 8 / 2**20:.1f} MiB of indices "
+            f"read, {rows // 4 / 1024:.0f} MiB written")
+        del src, idx, dst
     t_gen = time.perf_counter()
     g, srcs = workloads.rmat20_tile(k=args.k, scale=args.scale)
     log(f"graph {g.name}: n={g.n} m={g.m} k={len(srcs)} ({time.perf_counter() - t_gen:.1f}s)")
