@@ -380,7 +380,7 @@ def c5(args, dawn, torch, np):
     def new_server():
         srv = serve.Server(tile_k=args.c5_tile_k, steps_per_tick=args.c5_steps_per_tick,
                            max_tiles_per_graph=2, pull=not args.c5_no_pull,
-                           graphs=not args.c5_no_graphs)
+                           graphs=not args.c5_no_graphs, solo=not args.c5_no_solo)
         for i, c in enumerate(csrs):
             srv.add_graph(i, c)
         return srv
@@ -407,6 +407,7 @@ def c5(args, dawn, torch, np):
     recs = [{"config": "c5_serving_closed_loop", "graphs": len(graphs), "queries": len(qs),
              "graph_sha256": graphs_sha256(graphs),
              "pull": not args.c5_no_pull, "captured_runs": not args.c5_no_graphs,
+             "lone_runs": not args.c5_no_solo,
              "capacity_qps": cap, **closed,
              "parity": {**note_parity("c5", bad, len(picks)),
                         "largest_graph": {"id": big, "n": graphs[big].n, "m": graphs[big].m}}}]
@@ -581,6 +582,8 @@ def main() -> int:
     ap.add_argument("--c5-no-pull", action="store_true", help="serve with push steps only")
     ap.add_argument("--c5-no-graphs", action="store_true",
                     help="launch each tick's steps one by one instead of replaying a captured run")
+    ap.add_argument("--c5-no-solo", action="store_true",
+                    help="serve every query from tiles (no lone single-source runs)")
     ap.add_argument("--c5-pull-src", type=int, default=None,
                     help="tuning tile_pull_src while serving (default: the library's)")
     ap.add_argument("--c5-steps-per-tick", type=int, default=4)

@@ -210,6 +210,12 @@ typedef struct {
   int32_t barrier_ms;   /* persistent launches: a grid barrier that waits longer than this
                            gives up and ends the run with converged = -2; 0..600000,
                            default 4000 (0: give up at the first wait, for tests) */
+  int32_t ss_tail_grid; /* single-source and batch runs: at most this many workgroups in the
+                           persistent launch (0 = what the device holds at once).  A persistent
+                           launch waits at grid barriers for all of its workgroups; when kernels
+                           of other streams may hold compute units meanwhile, 1 keeps it from
+                           waiting on workgroups that cannot start (a server's lone queries run
+                           with mode 1 and ss_tail_grid 1); default 0 */
 } dawn_tuning;
 
 #define DAWN_TILE_K_MAX 512

@@ -49,7 +49,8 @@ class Tuning(ctypes.Structure):
                 ("t_lane", "t_wave", "t_chunk", "wg_threads", "grid", "mode", "step_launches",
                  "tile_k", "tile_t_wave", "tile_t_chunk", "validate", "coop", "tile_t_group",
                  "tile_skip", "small_m", "step_min_m", "tile_sparse", "tile_pull",
-                 "tile_pull_src", "ss_skip", "ss_pull", "tile_step_launches", "barrier_ms")]
+                 "tile_pull_src", "ss_skip", "ss_pull", "tile_step_launches", "barrier_ms",
+                 "ss_tail_grid")]
 
 
 INFO_BYTES = ctypes.sizeof(RunInfo)

@@ -138,6 +138,7 @@ static bool tuning_ok(const Tuning& t) {
          t.tile_pull >= 0 && t.tile_pull <= 1001 && t.tile_pull_src >= 0 &&
          t.tile_pull_src <= 512 && (t.ss_skip == 0 || t.ss_skip == 1) && t.ss_pull >= 0 &&
          t.ss_pull <= 1001 && t.tile_step_launches >= 0 && t.tile_step_launches <= 4096 &&
+         t.ss_tail_grid >= 0 && t.ss_tail_grid <= (1 << 20) &&
          t.barrier_ms >= 0 && t.barrier_ms <= 600000;
 }
 
@@ -325,6 +326,7 @@ extern "C" dawn_status dawn_get_tuning(dawn_tuning* out) {
   out->ss_pull = t.ss_pull;
   out->tile_step_launches = t.tile_step_launches;
   out->barrier_ms = t.barrier_ms;
+  out->ss_tail_grid = t.ss_tail_grid;
   return DAWN_OK;
 }
 
@@ -354,6 +356,7 @@ extern "C" dawn_status dawn_set_tuning(const dawn_tuning* in) {
     t.ss_pull = in->ss_pull;
     t.tile_step_launches = in->tile_step_launches;
     t.barrier_ms = in->barrier_ms;
+    t.ss_tail_grid = in->ss_tail_grid;
   }
   if (!tuning_ok(t)) return set_error(DAWN_E_INVALID, "tuning out of range");
   g_tuning = t;

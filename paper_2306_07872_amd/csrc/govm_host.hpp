@@ -34,6 +34,7 @@ struct Tuning {
   int32_t ss_pull = 1001;
   int32_t tile_step_launches = 16;
   int32_t barrier_ms = 4000;
+  int32_t ss_tail_grid = 0;
 };
 
 Tuning& tuning();

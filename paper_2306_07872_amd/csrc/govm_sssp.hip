@@ -1023,6 +1023,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
     const Residency r = residency_of(ss_persistent_kernel<WT>, threads);
     int grid = r.grid;
     if (T.grid > 0 && T.grid < grid) grid = T.grid;
+    if (T.ss_tail_grid > 0 && T.ss_tail_grid < grid) grid = T.ss_tail_grid;
     SsArgs a = A;
     a.pull_min = -1;  // pull steps need step launches (the last workgroup clears the bitmap)
     void* args[] = {&a};

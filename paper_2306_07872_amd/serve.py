@@ -28,6 +28,14 @@ a column does not depend on the other columns (different sources never update
 the same path, Section 3.5), so each answer is the same alone and in the mix.
 The host never waits on the device: it polls events.
 
+A query that finds its graph idle -- no live tile column, no lone run in
+flight, no other query of the graph waiting -- runs alone as a plain
+single-source run (``dawn_sssp_ws``) on the graph's own stream: one column of
+a tile pays for the whole tile's row width on every distance it touches,
+about twice the time of the single-source kernels on the largest graphs.
+Queries of that graph arriving meanwhile go to tiles as usual.  The
+distances are the same either way (they are unique).
+
 The executor is pluggable (``tile_factory``) so the scheduling logic can be
 exercised without a GPU; the default executor is the HIP tile session.
 """
@@ -39,7 +47,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Csr, Tile, dist_dtype, done_columns, tgraph, tile_bytes
+from . import (INFO_BYTES, Csr, Tile, dist_dtype, done_columns, get_tuning, info_tensor,
+               read_info, set_tuning, sssp, sssp_workspace_bytes, tgraph, tile_bytes, workspace)
 
 
 @dataclass
@@ -50,7 +59,7 @@ class Query:
     t_arrive: float
     t_admit: float | None = None
     t_done: float | None = None
-    state: str = "waiting"        # waiting | running | reading | done | cancelled
+    state: str = "waiting"        # waiting | running | reading | done | cancelled | failed
     result: object = None         # host numpy array once done
     steps: int | None = None
     _col: int | None = None
@@ -141,6 +150,65 @@ class GpuTileExecutor:
         self.tile.close()
 
 
+class GpuSoloExecutor:
+    """Lone queries of one graph as plain single-source runs on the graph's
+    own stream, one at a time, with the result copied to pinned host memory."""
+
+    def __init__(self, csr: Csr, device="cuda"):
+        import torch
+        self.torch = torch
+        self.csr = csr
+        self.stream = torch.cuda.Stream(device=device)   # default priority
+        nws = sssp_workspace_bytes(csr.n, csr.m)
+        self.ws = workspace(nws, device)
+        self.out = torch.empty(csr.n, dtype=dist_dtype(csr.wtype), device=device)
+        self.info = info_tensor(device)
+        self.nbytes = nws + 4 * csr.n + INFO_BYTES
+        self._pending = None
+
+    def launch(self, source: int):
+        torch = self.torch
+        # Kernels of other streams (tiles, other lone runs) share the compute
+        # units, so the run must not wait at a grid barrier for workgroups
+        # that cannot start: past the one-workgroup size it takes step
+        # launches and, for the steps after them, a one-workgroup persistent
+        # launch.
+        prev = None
+        if self.csr.m > get_tuning()["small_m"]:
+            prev = set_tuning(mode=1, ss_tail_grid=1)
+        try:
+            with torch.cuda.stream(self.stream):
+                sssp(self.csr, source, out=self.out, ws=self.ws, info=self.info,
+                     stream=self.stream, check=False)
+        finally:
+            if prev is not None:
+                set_tuning(**prev)
+        with torch.cuda.stream(self.stream):
+            host = torch.empty(self.csr.n, dtype=self.out.dtype, pin_memory=True)
+            host.copy_(self.out, non_blocking=True)
+            info_host = torch.empty(INFO_BYTES, dtype=torch.uint8, pin_memory=True)
+            info_host.copy_(self.info, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        self._pending = (ev, host, info_host)
+
+    def busy(self) -> bool:
+        return self._pending is not None
+
+    def finished(self) -> bool:
+        return self._pending is not None and self._pending[0].query()
+
+    def value(self):
+        """(distances, steps, converged) of the finished run."""
+        _, host, info_host = self._pending
+        self._pending = None
+        inf = read_info(info_host)
+        return host.numpy(), inf["steps"], inf["converged"]
+
+    def close(self):
+        self.stream.synchronize()
+
+
 class _ReadHandle:
     def __init__(self, ev, host, steps_host, col, keep):
         self.ev, self.host, self.steps_host, self.col, self._keep = ev, host, steps_host, col, keep
@@ -166,7 +234,8 @@ class Server:
 
     def __init__(self, hbm_budget: int | None = None, tile_k: int = 64, steps_per_tick: int = 4,
                  max_tiles_per_graph: int = 4, tile_factory=None, clock=time.perf_counter,
-                 device="cuda", pull: bool = True, graphs: bool = True):
+                 device="cuda", pull: bool = True, graphs: bool = True, solo: bool = True,
+                 solo_factory=None):
         self.graphs: dict[int, Csr] = {}
         # pull steps need each graph's reverse graph, built when the graph is
         # added and resident with it (like the CSR, outside the tile budget);
@@ -181,6 +250,12 @@ class Server:
             lambda csr, k: GpuTileExecutor(csr, k, device,
                                            getattr(csr, "_tgraph", None) if self.pull else None,
                                            graphs))
+        # lone queries as plain single-source runs (with a custom tile executor
+        # only when a matching solo executor is given too)
+        self.solo = solo and (tile_factory is None or solo_factory is not None)
+        self.solo_factory = solo_factory or (lambda csr: GpuSoloExecutor(csr, device))
+        self.solos: dict[int, object] = {}
+        self.solo_query: dict[int, Query] = {}
         if hbm_budget is None:
             import torch
             free, _ = torch.cuda.mem_get_info()
@@ -204,6 +279,10 @@ class Server:
         c = self.graphs[gid]
         return tile_bytes(c.n, c.m, self.tile_k)
 
+    def solo_cost(self, gid: int) -> int:
+        c = self.graphs[gid]
+        return sssp_workspace_bytes(c.n, c.m) + 4 * c.n + INFO_BYTES
+
     def submit(self, gid: int, source: int, t_arrive: float | None = None) -> Query:
         if gid not in self.graphs:
             raise KeyError(f"graph {gid} is not resident")
@@ -218,6 +297,8 @@ class Server:
         if q.state == "waiting":
             self.waiting.remove(q)
             q.state = "cancelled"
+        elif q.state == "running" and q._tile is None:
+            q.state = "cancelled"     # a lone run: its result is dropped when it ends
         elif q.state == "running":
             slot = q._tile
             slot.ex.evict(q._col)
@@ -228,6 +309,22 @@ class Server:
     # -- scheduling -----------------------------------------------------------
     def _collect(self):
         now = None
+        for gid in list(self.solo_query):
+            ex = self.solos[gid]
+            if not ex.finished():
+                continue
+            q = self.solo_query.pop(gid)
+            d, steps, conv = ex.value()
+            if q.state == "cancelled":
+                continue
+            now = self.clock() if now is None else now
+            q.t_done = now
+            if conv != 1:
+                q.state = "failed"
+                continue
+            q.result, q.steps = d, steps
+            q.state = "done"
+            self.done.append(q)
         for gid, slots in self.tiles.items():
             for slot in slots:
                 if not slot.ex.finished_run():
@@ -271,8 +368,30 @@ class Server:
         self.tiles[gid].append(slot)
         return slot
 
+    def _solo_for(self, gid: int):
+        """The graph's lone-query executor (created within the HBM budget), or None."""
+        ex = self.solos.get(gid)
+        if ex is not None:
+            return ex
+        cost = self.solo_cost(gid)
+        if self.hbm_used + cost > self.hbm_budget:
+            self._reclaim(cost)
+        if self.hbm_used + cost > self.hbm_budget:
+            return None
+        ex = self.solo_factory(self.graphs[gid])
+        self.solos[gid] = ex
+        self.hbm_used += cost
+        return ex
+
     def _reclaim(self, need: int):
-        """Destroy idle tiles (no live columns, not running) until `need` fits."""
+        """Destroy idle tiles (no live columns, not running) and idle lone-query
+        executors until `need` fits."""
+        for gid in list(self.solos):
+            if self.hbm_used + need <= self.hbm_budget:
+                return
+            if gid not in self.solo_query:
+                self.solos.pop(gid).close()
+                self.hbm_used -= self.solo_cost(gid)
         for gid, slots in self.tiles.items():
             for slot in list(slots):
                 if self.hbm_used + need <= self.hbm_budget:
@@ -286,11 +405,23 @@ class Server:
         now = self.clock()
         blocked = set()
         keep = collections.deque()
+        waiting_per_graph = collections.Counter(q.gid for q in self.waiting)
         while self.waiting:
             q = self.waiting.popleft()
             if q.gid in blocked:
                 keep.append(q)
                 continue
+            if (self.solo and waiting_per_graph[q.gid] == 1 and q.gid not in self.solo_query
+                    and not any(s.live for s in self.tiles[q.gid])):
+                ex = self._solo_for(q.gid)
+                if ex is not None:
+                    ex.launch(q.source)
+                    self.solo_query[q.gid] = q
+                    q._tile, q._col = None, None
+                    q.state, q.t_admit = "running", now
+                    waiting_per_graph[q.gid] -= 1
+                    continue
+            waiting_per_graph[q.gid] -= 1
             slot = self._slot_for(q.gid)
             if slot is None:
                 blocked.add(q.gid)
@@ -320,7 +451,7 @@ class Server:
         return len(self.done) - before
 
     def busy(self) -> bool:
-        return bool(self.waiting or self.reading or
+        return bool(self.waiting or self.reading or self.solo_query or
                     any(s.live for slots in self.tiles.values() for s in slots))
 
     def run_until_idle(self, max_ticks: int = 10_000_000):
@@ -334,7 +465,11 @@ class Server:
         for slots in self.tiles.values():
             for slot in slots:
                 slot.ex.close()
+        for ex in self.solos.values():
+            ex.close()
         self.tiles.clear()
+        self.solos.clear()
+        self.solo_query.clear()
         self.hbm_used = 0
 
 

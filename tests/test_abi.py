@@ -53,7 +53,7 @@ def test_tuning_roundtrip_and_range_checks(lib):
                 dict(tile_pull_src=-1), dict(tile_pull_src=513), dict(ss_skip=2), dict(ss_pull=1002),
                 dict(tile_sparse=513), dict(step_launches=-1), dict(step_launches=4097),
                 dict(tile_step_launches=-1), dict(tile_step_launches=4097), dict(barrier_ms=-1),
-                dict(barrier_ms=600001)):
+                dict(barrier_ms=600001), dict(ss_tail_grid=-1)):
         with pytest.raises(dawn.DawnError) as e:
             dawn.set_tuning(**bad)
         assert e.value.status == 1

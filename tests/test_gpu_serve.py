@@ -10,20 +10,21 @@ from gpu_helpers import announce, assert_sssp_matches, to_np
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("pull,graphs", [(False, False), (False, True), (True, True)])
-def test_server_mix_equals_alone(dawn, pull, graphs):
+@pytest.mark.parametrize("pull,graphs,solo", [(False, False, True), (False, True, False),
+                                              (True, True, True)])
+def test_server_mix_equals_alone(dawn, pull, graphs, solo):
     """pull=True: the tiles take pull steps (from 5 % of the edges in the
     frontier) while queries join and leave them.  graphs=True: each tick's
     steps are a replay of the tile's captured run."""
     prev = dawn.set_tuning(tile_pull=50, tile_pull_src=0) if pull else None
     try:
-        _mix_equals_alone(dawn, pull, graphs)
+        _mix_equals_alone(dawn, pull, graphs, solo)
     finally:
         if prev is not None:
             dawn.set_tuning(**prev)
 
 
-def _mix_equals_alone(dawn, pull, graphs):
+def _mix_equals_alone(dawn, pull, graphs, solo):
     import torch
     from paper_2306_07872_amd import serve
     gs = [graphgen.rmat(12, 8, 40, weights="u32"),
@@ -31,7 +32,7 @@ def _mix_equals_alone(dawn, pull, graphs):
           graphgen.grid(48, 40, 0.01, 42, weights="f32unit")]
     csrs = [dawn.Csr.from_graph(g) for g in gs]
     srv = serve.Server(tile_k=64, steps_per_tick=3, max_tiles_per_graph=2, pull=pull,
-                       graphs=graphs)
+                       graphs=graphs, solo=solo)
     for i, c in enumerate(csrs):
         srv.add_graph(i, c)
     rng = np.random.default_rng(7)
@@ -158,3 +159,30 @@ def test_tile_replay_without_capture_is_rejected(dawn):
             t.capture(0)
     finally:
         t.close()
+
+
+def test_lone_queries_run_alone_and_match_the_oracle(dawn):
+    """Queries that find their graph idle run as plain single-source runs; one
+    arriving while such a run is in flight joins a tile; all are exact."""
+    import torch
+    from paper_2306_07872_amd import serve
+    gs = [graphgen.rmat(14, 16, 60, weights="u32"), graphgen.rmat(13, 8, 61, weights="f32lognormal")]
+    csrs = [dawn.Csr.from_graph(g) for g in gs]
+    srv = serve.Server(tile_k=64, steps_per_tick=2, max_tiles_per_graph=1)
+    for i, c in enumerate(csrs):
+        srv.add_graph(i, c)
+    announce("server lone queries")
+    s0 = graphgen.pick_sources(gs[0], 3, 5)
+    a = srv.submit(0, int(s0[0]))
+    srv.tick()
+    assert a.state == "running" and a._tile is None
+    b = srv.submit(0, int(s0[1]))
+    c = srv.submit(1, int(graphgen.pick_sources(gs[1], 1, 6)[0]))
+    srv.tick()
+    assert b._tile is not None and c._tile is None
+    srv.run_until_idle()
+    torch.cuda.synchronize()
+    srv.close()
+    for q in (a, b, c):
+        assert q.state == "done" and q.steps > 0
+        assert_sssp_matches(gs[q.gid], q.source, q.result, tag=f"lone q{q.qid}")

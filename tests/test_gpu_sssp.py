@@ -58,6 +58,8 @@ TUNINGS = [
     dict(small_m=1 << 30),                    # one workgroup for the whole graph
     dict(small_m=1 << 30, wg_threads=256),
     dict(step_min_m=0, step_launches=2),      # step launches, then a persistent launch
+    dict(mode=1, step_launches=2, ss_tail_grid=1),  # ... of one workgroup
+    dict(mode=2, ss_tail_grid=3),             # a persistent launch of three workgroups
     dict(step_min_m=0, step_launches=1, wg_threads=1024, t_lane=2, t_wave=64, t_chunk=256),
     dict(step_min_m=0),
     dict(ss_skip=0, small_m=0),                # every frontier row expanded in its step

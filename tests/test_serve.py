@@ -208,3 +208,104 @@ def test_poisson_arrivals_and_percentiles():
     assert abs(t[-1] / 1000 - 1 / 100.0) < 0.005
     p = serve.percentiles([0.001, 0.002, 0.003])
     assert abs(p["p50_ms"] - 2.0) < 1e-9
+
+
+class FakeSolo:
+    """Stands in for a lone single-source run: done after `lag` polls."""
+    created = 0
+
+    def __init__(self, csr, lag=2):
+        FakeSolo.created += 1
+        self.csr, self.lag = csr, lag
+        self.src, self.polls, self.launches = None, 0, 0
+        self.closed = False
+
+    def launch(self, source):
+        assert self.src is None
+        self.src, self.polls = source, 0
+        self.launches += 1
+
+    def finished(self):
+        if self.src is None:
+            return False
+        self.polls += 1
+        return self.polls > self.lag
+
+    def value(self):
+        d, _ = oracle.sssp(self.csr.g, self.src)
+        steps = 1 + (self.src % 5)
+        self.src = None
+        return d, steps, 1
+
+    def close(self):
+        self.closed = True
+
+
+def make_solo_server(budget, tile_k=4, steps=2, max_tiles=3):
+    import itertools
+    ticks = itertools.count()
+    clock = lambda: next(ticks) * 1e-3
+    srv = serve.Server(hbm_budget=budget, tile_k=tile_k, steps_per_tick=steps,
+                       max_tiles_per_graph=max_tiles,
+                       tile_factory=lambda csr, k: FakeExecutor(csr, k, 1),
+                       solo_factory=lambda csr: FakeSolo(csr), clock=clock)
+    srv.tile_cost = lambda gid: 1
+    srv.solo_cost = lambda gid: 1
+    return srv
+
+
+def test_lone_query_runs_alone_and_later_ones_join_tiles(graphs):
+    srv = make_solo_server(budget=10)
+    for i, g in enumerate(graphs):
+        srv.add_graph(i, FakeCsr(g))
+    a = srv.submit(0, 7)
+    srv.tick()
+    assert a.state == "running" and a._tile is None and 0 in srv.solo_query
+    b = srv.submit(0, 3)             # arrives while the lone run is in flight
+    c = srv.submit(1, 4)             # another graph, idle: runs alone too
+    srv.tick()
+    assert b.state == "running" and b._tile is not None
+    assert c.state == "running" and c._tile is None
+    srv.run_until_idle()
+    for q in (a, b, c):
+        assert q.state == "done"
+        ref, _ = oracle.sssp(graphs[q.gid], q.source)
+        assert np.array_equal(q.result, ref)
+        assert q.steps == 1 + (q.source % 5)
+
+
+def test_queries_arriving_together_share_a_tile(graphs):
+    srv = make_solo_server(budget=10)
+    srv.add_graph(0, FakeCsr(graphs[0]))
+    qs = [srv.submit(0, s) for s in (1, 2, 3)]
+    srv.tick()
+    assert not srv.solo_query and all(q._tile is not None for q in qs)
+    srv.run_until_idle()
+    assert all(q.state == "done" for q in qs)
+
+
+def test_lone_runs_count_against_the_budget_and_are_reclaimed(graphs):
+    srv = make_solo_server(budget=1)
+    for i, g in enumerate(graphs):
+        srv.add_graph(i, FakeCsr(g))
+    qs = []
+    for i in range(9):
+        qs.append(srv.submit(i % 3, i))
+        srv.tick()
+        assert srv.hbm_used <= srv.hbm_budget
+    srv.run_until_idle()
+    assert all(q.state == "done" for q in qs)
+    for q in qs:
+        ref, _ = oracle.sssp(graphs[q.gid], q.source)
+        assert np.array_equal(q.result, ref)
+
+
+def test_cancel_a_lone_run(graphs):
+    srv = make_solo_server(budget=10)
+    srv.add_graph(0, FakeCsr(graphs[0]))
+    a = srv.submit(0, 2)
+    srv.tick()
+    assert a._tile is None
+    srv.cancel(a)
+    srv.run_until_idle()
+    assert a.state == "cancelled" and a.result is None and not srv.solo_query
