@@ -771,20 +771,35 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
 // ---------------------------------------------------------------------------
 constexpr int kTinyN = 6144;
 
+// With m <= kTinyLdsM the CSR itself is copied into LDS as well (column ids
+// as 16-bit values), so a step makes no global-memory round trip at all.
+constexpr int kTinyLdsM = 10240;
+
+template <bool LCSR>
+struct SsTinyCsr {};
+template <>
+struct SsTinyCsr<true> {
+  int32_t rp[kTinyN + 1];
+  uint16_t ci[kTinyLdsM];
+  uint32_t w[kTinyLdsM];
+};
+
+template <bool LCSR>
 struct SsTinyShared {
   int stage[kMaxWavesPerBlock * 3 * kWave];
   uint32_t dist[kTinyN];
   uint16_t q[2][kTinyN];
   uint32_t bm[2][kTinyN / 32];
   uint32_t cnt_next, upd;
+  SsTinyCsr<LCSR> csr;
 };
 
-template <int WT>
+template <int WT, bool LCSR>
 __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* sources,
                                                        const int64_t* voff, int32_t count,
                                                        int32_t single, int32_t check_valid,
                                                        dawn_run_info* info) {
-  __shared__ SsTinyShared sh;
+  __shared__ SsTinyShared<LCSR> sh;
   SsCtl* C = A.ctl;
   const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
   const int n = A.n, nwords = (n + 31) / 32;
@@ -795,6 +810,13 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
     status = -1;
   } else {
     for (int i = threadIdx.x; i < n; i += blockDim.x) sh.dist[i] = inf_key<WT>();
+    if constexpr (LCSR) {
+      for (int i = threadIdx.x; i <= n; i += blockDim.x) sh.csr.rp[i] = A.rowptr[i];
+      for (int e = threadIdx.x; e < A.m; e += blockDim.x) {
+        sh.csr.ci[e] = (uint16_t)A.colidx[e];
+        if constexpr (WT != kWUNIT) sh.csr.w[e] = A.w[e];
+      }
+    }
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
       sh.bm[0][i] = 0u;
       sh.bm[1][i] = 0u;
@@ -834,8 +856,13 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
         uint32_t du = 0;
         if (i < cnt) {
           u = sh.q[cur][i];
-          start = A.rowptr[u];
-          deg = A.rowptr[u + 1] - start;
+          if constexpr (LCSR) {
+            start = sh.csr.rp[u];
+            deg = sh.csr.rp[u + 1] - start;
+          } else {
+            start = A.rowptr[u];
+            deg = A.rowptr[u + 1] - start;
+          }
           du = sh.dist[u];
           sh.bm[cur][u >> 5] = 0u;
           if (deg > 0) {
@@ -865,8 +892,15 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
             cand[j] = 0u;
             if (ok[j]) {
               const int32_t e = l_base[owner] + k;
-              v[j] = A.colidx[e];
-              cand[j] = relax_key<WT>((uint32_t)l_du[owner], WT == kWUNIT ? 1u : A.w[e]);
+              uint32_t we = 1u;
+              if constexpr (LCSR) {
+                v[j] = sh.csr.ci[e];
+                if constexpr (WT != kWUNIT) we = sh.csr.w[e];
+              } else {
+                v[j] = A.colidx[e];
+                if constexpr (WT != kWUNIT) we = A.w[e];
+              }
+              cand[j] = relax_key<WT>((uint32_t)l_du[owner], we);
               if constexpr (WT == kWI32)
                 if (cand[j] == 0u) atomicOr(&A.ctl->negfloor, 1u);  // sum left the int32 range
             }
@@ -980,8 +1014,12 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
                          A.n, A.m, (int32_t)(WT == kWF32), &A.ctl->done, &A.ctl->converged);
     }
     void* tk = capture ? nullptr : ktimer_begin(stream);
-    if (A.n <= kTinyN)
-      hipLaunchKernelGGL(ss_tiny_kernel<WT>, dim3(1), dim3(threads), 0, stream, A,
+    if (A.n <= kTinyN && A.m <= kTinyLdsM)
+      hipLaunchKernelGGL((ss_tiny_kernel<WT, true>), dim3(1), dim3(threads), 0, stream, A,
+                         seeds.sources_dev, seeds.voff_dev, seeds.count, seeds.source,
+                         (int32_t)(T.validate != 0), info);
+    else if (A.n <= kTinyN)
+      hipLaunchKernelGGL((ss_tiny_kernel<WT, false>), dim3(1), dim3(threads), 0, stream, A,
                          seeds.sources_dev, seeds.voff_dev, seeds.count, seeds.source,
                          (int32_t)(T.validate != 0), info);
     else

@@ -88,9 +88,10 @@ def test_grid_f32_small(dawn):
 
 
 def test_grid_f32_tiny_and_small_paths(dawn):
-    """n <= 6144 runs with its whole state in LDS, larger small graphs in one
-    workgroup over global memory; both many-step fp32 cases match the oracle."""
-    for rows, cols in ((60, 60), (90, 90)):
+    """n <= 6144 runs with its whole state in LDS (with m <= 10240 the CSR too),
+    larger small graphs in one workgroup over global memory; every many-step
+    fp32 case matches the oracle."""
+    for rows, cols in ((40, 40), (60, 60), (90, 90)):
         g = graphgen.grid(rows, cols, 0.02, 5, weights="f32unit")
         for s in graphgen.pick_sources(g, 2, 3):
             announce("grid", rows, cols, "f32 source", s)
