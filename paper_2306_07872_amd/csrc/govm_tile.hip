@@ -1249,23 +1249,50 @@ __global__ void __launch_bounds__(kPullThreads) utile_pull_kernel(TileArgs A, in
 // ---------------------------------------------------------------------------
 
 // out[(j) * ld + v] = D[v][col0 + j] for j < count: 64 x 64 tiles through LDS so
-// both the read (rows of D) and the write (rows of out) are contiguous.
-__global__ void tile_store_kernel(const uint32_t* D, int32_t n, int32_t K, int32_t col0,
-                                  int32_t count, uint32_t* out, int64_t ld) {
+// both the read (rows of D) and the write (rows of out) are contiguous.  Rows
+// of D are read 16 bytes per lane (16 lanes per 64-column row segment); rows of
+// out are written 16 bytes per lane when every output row starts 16-byte
+// aligned (VEC), else 4 bytes per lane.
+template <bool VEC>
+__global__ void __launch_bounds__(256) tile_store_kernel(const uint32_t* D, int32_t n, int32_t K,
+                                                         int32_t col0, int32_t count,
+                                                         uint32_t* out, int64_t ld) {
   __shared__ uint32_t t[64][65];
   const int64_t v0 = (int64_t)blockIdx.x * 64;
   const int32_t c0 = blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 256 threads: 4 rows at a time
-  for (int r = ty; r < 64; r += 4) {
+  const int q = threadIdx.x & 15, r16 = threadIdx.x >> 4;  // 16 lanes per row, 16 rows at a time
+  for (int r = r16; r < 64; r += 16) {
     const int64_t v = v0 + r;
-    const int32_t c = c0 + tx;
-    t[r][tx] = (v < n && c < count) ? D[(size_t)v * K + col0 + c] : 0u;
+    uint4 x = make_uint4(0u, 0u, 0u, 0u);
+    // col0 and K are multiples of 64, so the 16-byte load is aligned; columns
+    // past `count` are read (they exist in the tile) but never stored
+    if (v < n) x = *reinterpret_cast<const uint4*>(D + (size_t)v * K + col0 + c0 + 4 * q);
+    t[r][4 * q] = x.x;
+    t[r][4 * q + 1] = x.y;
+    t[r][4 * q + 2] = x.z;
+    t[r][4 * q + 3] = x.w;
   }
   __syncthreads();
-  for (int r = ty; r < 64; r += 4) {
-    const int32_t c = c0 + r;
-    const int64_t v = v0 + tx;
-    if (c < count && v < n) out[(size_t)c * ld + v] = t[tx][r];
+  if constexpr (VEC) {
+    for (int r = r16; r < 64; r += 16) {
+      const int32_t c = c0 + r;
+      const int64_t v = v0 + 4 * q;
+      if (c >= count || v >= n) continue;
+      uint32_t* o = out + (size_t)c * ld + v;
+      if (v + 3 < n) {
+        *reinterpret_cast<uint4*>(o) = make_uint4(t[4 * q][r], t[4 * q + 1][r], t[4 * q + 2][r],
+                                                  t[4 * q + 3][r]);
+      } else {
+        for (int i = 0; v + i < n; i++) o[i] = t[4 * q + i][r];
+      }
+    }
+  } else {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+      const int32_t c = c0 + r;
+      const int64_t v = v0 + tx;
+      if (c < count && v < n) out[(size_t)c * ld + v] = t[tx][r];
+    }
   }
 }
 
@@ -1595,8 +1622,13 @@ dawn_status tile_done_bits(const TileArgs& a, int32_t k, uint32_t* done_bits, hi
 dawn_status tile_store(const TileArgs& a, int32_t col0, int32_t count, void* out, int64_t ld,
                        hipStream_t stream) {
   const dim3 grid((unsigned)((a.n + 63) / 64), (unsigned)((count + 63) / 64));
-  hipLaunchKernelGGL(tile_store_kernel, grid, dim3(256), 0, stream, a.D, a.n, a.K, col0, count,
-                     static_cast<uint32_t*>(out), ld);
+  const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(out) & 15u) == 0;
+  if (vec)
+    hipLaunchKernelGGL(tile_store_kernel<true>, grid, dim3(256), 0, stream, a.D, a.n, a.K, col0,
+                       count, static_cast<uint32_t*>(out), ld);
+  else
+    hipLaunchKernelGGL(tile_store_kernel<false>, grid, dim3(256), 0, stream, a.D, a.n, a.K, col0,
+                       count, static_cast<uint32_t*>(out), ld);
   return hip_check(hipGetLastError(), "tile store");
 }
 
