@@ -566,8 +566,10 @@ class Tile:
                                        _stream(stream)))
         self._h = h
         torch = _torch()
-        self.done_buf = torch.zeros((self.k + 31) // 32, dtype=torch.int32,
-                                    device=csr.rowptr.device)
+        # zeroed on the session's stream, ordered before its first run
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            self.done_buf = torch.zeros((self.k + 31) // 32, dtype=torch.int32,
+                                        device=csr.rowptr.device)
 
     def set_tgraph(self, tgraph):
         """Attach the reverse graph (``tgraph(csr)``) for pull steps, or None."""

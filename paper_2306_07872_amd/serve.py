@@ -62,6 +62,7 @@ class Query:
     state: str = "waiting"        # waiting | running | reading | done | cancelled | failed
     result: object = None         # host numpy array once done
     steps: int | None = None
+    status: int | None = None     # run status of a failed lone run (dawn_run_info.converged)
     _col: int | None = None
     _tile: object = None
     _read: object = None
@@ -160,9 +161,12 @@ class GpuSoloExecutor:
         self.csr = csr
         self.stream = torch.cuda.Stream(device=device)   # default priority
         nws = sssp_workspace_bytes(csr.n, csr.m)
-        self.ws = workspace(nws, device)
-        self.out = torch.empty(csr.n, dtype=dist_dtype(csr.wtype), device=device)
-        self.info = info_tensor(device)
+        # allocated (and the run info zeroed) on the executor's own stream, so
+        # the zeroing is ordered before the first run on that stream
+        with torch.cuda.stream(self.stream):
+            self.ws = workspace(nws, device)
+            self.out = torch.empty(csr.n, dtype=dist_dtype(csr.wtype), device=device)
+            self.info = info_tensor(device)
         self.nbytes = nws + 4 * csr.n + INFO_BYTES
         self._pending = None
 
@@ -320,7 +324,7 @@ class Server:
             now = self.clock() if now is None else now
             q.t_done = now
             if conv != 1:
-                q.state = "failed"
+                q.state, q.status = "failed", conv
                 continue
             q.result, q.steps = d, steps
             q.state = "done"

@@ -75,7 +75,8 @@ def test_serving_largest_graph_in_a_mix(dawn):
     srv.run_until_idle()
     torch.cuda.synchronize()
     srv.close()
-    assert all(q.state == "done" for q in qs)
+    bad = [(q.qid, q.gid, q.state, q.status, q._tile is None) for q in qs if q.state != "done"]
+    assert not bad, bad
     on_big = [q for q in qs if q.gid == 0]
     assert len(on_big) >= 10
     for q in on_big[:2]:
