@@ -771,35 +771,20 @@ __global__ void __launch_bounds__(1024) ss_small_kernel(SsArgs A, const int32_t*
 // ---------------------------------------------------------------------------
 constexpr int kTinyN = 6144;
 
-// With m <= kTinyLdsM the CSR itself is copied into LDS as well (column ids
-// as 16-bit values), so a step makes no global-memory round trip at all.
-constexpr int kTinyLdsM = 10240;
-
-template <bool LCSR>
-struct SsTinyCsr {};
-template <>
-struct SsTinyCsr<true> {
-  int32_t rp[kTinyN + 1];
-  uint16_t ci[kTinyLdsM];
-  uint32_t w[kTinyLdsM];
-};
-
-template <bool LCSR>
 struct SsTinyShared {
   int stage[kMaxWavesPerBlock * 3 * kWave];
   uint32_t dist[kTinyN];
   uint16_t q[2][kTinyN];
   uint32_t bm[2][kTinyN / 32];
   uint32_t cnt_next, upd;
-  SsTinyCsr<LCSR> csr;
 };
 
-template <int WT, bool LCSR>
+template <int WT>
 __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* sources,
                                                        const int64_t* voff, int32_t count,
                                                        int32_t single, int32_t check_valid,
                                                        dawn_run_info* info) {
-  __shared__ SsTinyShared<LCSR> sh;
+  __shared__ SsTinyShared sh;
   SsCtl* C = A.ctl;
   const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
   const int n = A.n, nwords = (n + 31) / 32;
@@ -810,13 +795,6 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
     status = -1;
   } else {
     for (int i = threadIdx.x; i < n; i += blockDim.x) sh.dist[i] = inf_key<WT>();
-    if constexpr (LCSR) {
-      for (int i = threadIdx.x; i <= n; i += blockDim.x) sh.csr.rp[i] = A.rowptr[i];
-      for (int e = threadIdx.x; e < A.m; e += blockDim.x) {
-        sh.csr.ci[e] = (uint16_t)A.colidx[e];
-        if constexpr (WT != kWUNIT) sh.csr.w[e] = A.w[e];
-      }
-    }
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) {
       sh.bm[0][i] = 0u;
       sh.bm[1][i] = 0u;
@@ -856,13 +834,8 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
         uint32_t du = 0;
         if (i < cnt) {
           u = sh.q[cur][i];
-          if constexpr (LCSR) {
-            start = sh.csr.rp[u];
-            deg = sh.csr.rp[u + 1] - start;
-          } else {
-            start = A.rowptr[u];
-            deg = A.rowptr[u + 1] - start;
-          }
+          start = A.rowptr[u];
+          deg = A.rowptr[u + 1] - start;
           du = sh.dist[u];
           sh.bm[cur][u >> 5] = 0u;
           if (deg > 0) {
@@ -893,13 +866,8 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
             if (ok[j]) {
               const int32_t e = l_base[owner] + k;
               uint32_t we = 1u;
-              if constexpr (LCSR) {
-                v[j] = sh.csr.ci[e];
-                if constexpr (WT != kWUNIT) we = sh.csr.w[e];
-              } else {
-                v[j] = A.colidx[e];
-                if constexpr (WT != kWUNIT) we = A.w[e];
-              }
+              v[j] = A.colidx[e];
+              if constexpr (WT != kWUNIT) we = A.w[e];
               cand[j] = relax_key<WT>((uint32_t)l_du[owner], we);
               if constexpr (WT == kWI32)
                 if (cand[j] == 0u) atomicOr(&A.ctl->negfloor, 1u);  // sum left the int32 range
@@ -962,6 +930,240 @@ __global__ void __launch_bounds__(1024) ss_tiny_kernel(SsArgs A, const int32_t* 
 }
 
 // ---------------------------------------------------------------------------
+// graphs that fit whole in LDS: edge-parallel steps
+//
+// With n <= kTinyN and m <= kLdsM a workgroup of kLdsThreads threads holds the
+// whole run: the distances, the frontier bitmaps and the weights in LDS, and
+// each thread's edges t, t + kLdsThreads, ... (at most kLdsEdges) in
+// registers, as packed (source, target) ids.  A step then needs no queue: a thread
+// relaxes each of its edges whose source's bit is set in the step's frontier
+// bitmap.  Those are exactly the out-edges of the frontier, the relaxations
+// Algorithm 2 makes, and every thread gets the same number of edges whatever
+// the degrees.  A target lowered in the step gets its bit in the next bitmap.
+// Three bitmaps and three update flags rotate, so one barrier per step
+// suffices: step t reads bitmap t mod 3, sets bits in (t+1) mod 3 and clears
+// (t+2) mod 3, which step t-1 read and step t+1 fills.
+// ---------------------------------------------------------------------------
+constexpr int kLdsThreads = 1024;
+constexpr int kLdsEdges = 16;  // edges per thread
+constexpr int kLdsM = kLdsThreads * kLdsEdges;
+constexpr int kLdsRows = kTinyN / kLdsThreads;  // vertices per thread
+constexpr int kLdsHalf = kLdsEdges / 2;
+
+struct SsLdsShared {
+  uint32_t dist[kTinyN];
+  uint32_t bm[3][kTinyN / 32];
+  uint32_t upd[3];
+  uint16_t src[kLdsM];  // each edge's source, read once to fill the registers
+  uint32_t w[kLdsM];
+  unsigned long long part[kLdsThreads / kWave][3];
+};
+
+template <int WT>
+__global__ void __launch_bounds__(kLdsThreads) ss_lds_kernel(SsArgs A, const int32_t* sources,
+                                                             const int64_t* voff, int32_t count,
+                                                             int32_t single, int32_t check_valid,
+                                                             dawn_run_info* info) {
+  __shared__ SsLdsShared sh;
+  SsCtl* C = A.ctl;
+  const int n = A.n, m = A.m, nwords = (n + 31) / 32, t = threadIdx.x;
+  uint32_t step = 0;
+  int32_t status = 1;
+  Acc acc;
+  if (check_valid && ld_agent(&C->done)) {
+    status = -1;
+  } else {
+    if (t == 0) {
+      // the status words the report reads: the workspace may hold an earlier
+      // run's
+      atomicExch(&C->negfloor, 0u);
+      atomicExch(&C->abort, 0u);
+      atomicExch(&C->overflow, 0u);
+    }
+    // this thread's edges and rows: every global load issued before any use
+    uint32_t tv[kLdsEdges], we[kLdsEdges];
+#pragma unroll
+    for (int j = 0; j < kLdsEdges; j++) {
+      const int e = t + j * kLdsThreads;
+      tv[j] = e < m ? (uint32_t)A.colidx[e] : 0u;
+      we[j] = (WT != kWUNIT && e < m) ? A.w[e] : 1u;
+    }
+#pragma unroll
+    for (int j = 0; j < kLdsEdges; j++)
+      if (t + j * kLdsThreads < m) sh.w[t + j * kLdsThreads] = we[j];
+    int32_t ra[kLdsRows], rb[kLdsRows];
+#pragma unroll
+    for (int i = 0; i < kLdsRows; i++) {
+      const int u = t + i * kLdsThreads;
+      ra[i] = u < n ? A.rowptr[u] : 0;
+      rb[i] = u < n ? A.rowptr[u + 1] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < kLdsRows; i++) {
+      const int u = t + i * kLdsThreads;
+      if (u < n) {
+        for (int32_t e = ra[i]; e < rb[i]; e++) sh.src[e] = (uint16_t)u;
+        sh.dist[u] = inf_key<WT>();
+      }
+    }
+    for (int i = t; i < nwords; i += kLdsThreads) {
+      sh.bm[0][i] = 0u;
+      sh.bm[1][i] = 0u;
+      sh.bm[2][i] = 0u;
+    }
+    if (t < 3) sh.upd[t] = 0u;
+    __syncthreads();
+    // (source, target) of each edge packed in one register; bit j of `first`:
+    // edge j is its row's first edge (counts the row once per step)
+    uint32_t uv[kLdsEdges];
+    uint32_t first = 0u;
+#pragma unroll
+    for (int j = 0; j < kLdsEdges; j++) {
+      const int e = t + j * kLdsThreads;
+      uv[j] = 0u;
+      if (e < m) {
+        const uint32_t u = sh.src[e];
+        uv[j] = u | (tv[j] << 16);
+        if (e == 0 || sh.src[e - 1] != u) first |= 1u << j;
+      }
+    }
+    for (int j = t; j < count; j += kLdsThreads) {
+      int64_t s = sources ? (int64_t)sources[j] : (int64_t)single;
+      if (voff) s += voff[j];
+      sh.dist[s] = zero_key<WT>();
+      atomicOr(&sh.bm[0][s >> 5], 1u << (s & 31));
+    }
+    __syncthreads();
+    for (;;) {
+      const uint32_t* bc = sh.bm[step % 3];
+      uint32_t* bn = sh.bm[(step + 1) % 3];
+      bool upd = false;
+      // Values derived from the edge ids (word indices, bit masks, LDS
+      // addresses) are recomputed each step rather than kept in registers
+      // across steps, which would not fit: the empty asm marks the ids as
+      // changed here.
+#pragma unroll
+      for (int j = 0; j < kLdsEdges; j++) asm volatile("" : "+v"(uv[j]));
+      // Frontier test of every edge, then the distances of the active ones,
+      // then the atomics.  Every LDS read is unconditional (edges past m read
+      // edge 0's slots, vertex 0), so a round's reads go out back to back and
+      // are waited for once; a read under a branch would be waited for alone.
+      uint32_t act = 0u;
+      {
+        uint32_t wd[kLdsEdges];
+#pragma unroll
+        for (int j = 0; j < kLdsEdges; j++) wd[j] = bc[(uv[j] & 0xFFFFu) >> 5];
+#pragma unroll
+        for (int j = 0; j < kLdsEdges; j++)
+          act |= ((wd[j] >> (uv[j] & 31u)) & (t + j * kLdsThreads < m ? 1u : 0u)) << j;
+      }
+      // the active edges in halves of kLdsHalf (registers for their candidates)
+#pragma unroll
+      for (int h = 0; h < kLdsEdges; h += kLdsHalf) {
+        if (!((act >> h) & ((1u << kLdsHalf) - 1u))) continue;
+        uint32_t cand[kLdsHalf], dv[kLdsHalf];
+#pragma unroll
+        for (int i = 0; i < kLdsHalf; i++) {
+          const int j = h + i, e = t + j * kLdsThreads;
+          cand[i] = relax_key<WT>(sh.dist[uv[j] & 0xFFFFu], sh.w[e < m ? e : 0]);
+          dv[i] = sh.dist[uv[j] >> 16];
+        }
+        uint32_t need = 0u;
+#pragma unroll
+        for (int i = 0; i < kLdsHalf; i++) {
+          const int j = h + i;
+          const uint32_t v = uv[j] >> 16;
+          if ((act >> j) & 1u) {
+            acc.es += 1;
+            acc.fe += (first >> j) & 1u;
+            if constexpr (WT == kWI32)
+              if (cand[i] == 0u) atomicOr(&A.ctl->negfloor, 1u);  // sum left the int32 range
+            if ((int32_t)v != A.src && cand[i] < dv[i]) need |= 1u << i;
+          }
+        }
+        // returning atomics, all issued before any result is used
+        uint32_t old[kLdsHalf];
+#pragma unroll
+        for (int i = 0; i < kLdsHalf; i++) {
+          old[i] = 0u;
+          if ((need >> i) & 1u) old[i] = atomicMin(&sh.dist[uv[h + i] >> 16], cand[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < kLdsHalf; i++) {
+          const uint32_t v = uv[h + i] >> 16;
+          if (((need >> i) & 1u) && cand[i] < old[i]) {
+            acc.im += 1;
+            upd = true;
+            __hip_atomic_fetch_or(&bn[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+      }
+      for (int i = t; i < nwords; i += kLdsThreads) sh.bm[(step + 2) % 3][i] = 0u;
+      if (t == 0) sh.upd[(step + 2) % 3] = 0u;
+      if (upd) sh.upd[(step + 1) % 3] = 1u;
+      __syncthreads();
+      const uint32_t more = sh.upd[(step + 1) % 3];
+      step++;
+      if (!more) { status = 1; break; }
+      if (step >= (uint32_t)n) { status = 0; break; }
+    }
+    for (int i = t; i < n; i += kLdsThreads) A.dist[i] = sh.dist[i];
+  }
+  // One workgroup owns the counters: they are summed in LDS and stored, not
+  // added to, and the report is made from the values this workgroup holds.
+  {
+    const unsigned long long v0 = wave_sum64(acc.fe), v1 = wave_sum64(acc.es),
+                             v2 = wave_sum64(acc.im);
+    if (lane_id() == 0) {
+      sh.part[t / kWave][0] = v0;
+      sh.part[t / kWave][1] = v1;
+      sh.part[t / kWave][2] = v2;
+    }
+  }
+  // the int32 range flag is set by any thread's atomic
+  if (WT == kWI32 || status == -1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long fe = 0, es = 0, im = 0;
+    for (int i = 0; i < kLdsThreads / kWave; i++) {
+      fe += sh.part[i][0];
+      es += sh.part[i][1];
+      im += sh.part[i][2];
+    }
+    SsCounters& S = C->ctr;
+    st_agent64(&S.fe, fe);
+    st_agent64(&S.es, es);
+    st_agent64(&S.im, im);
+    if (status == -1) {
+      // failed validation: report what the control words record
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      ss_report<WT>(C, info, A.latch);
+    } else {
+      if (WT == kWI32) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const uint32_t ab = ld_agent(&C->abort), ov = ld_agent(&C->overflow);
+      const uint32_t nf = WT == kWI32 ? ld_agent(&C->negfloor) : 0u;
+      st_agent(&C->step, step);
+      st_agent_i(&C->converged, status);
+      st_agent(&C->done, 1u);
+      int32_t conv = run_status(status, ab, ov);
+      if (WT == kWI32 && conv == 1 && nf) conv = 0;
+      if (!info) {
+        latch_status(A.latch, conv);
+      } else {
+        info->steps = (int32_t)step;
+        info->converged = conv;
+        info->frontier_entries = (int64_t)fe;
+        info->edges_scanned = (int64_t)es;
+        info->improvements = (int64_t)im;
+        info->union_rows = (int64_t)fe;
+        info->union_edges = (int64_t)es;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 SsLayout ss_layout(int64_t n, int64_t m) {
@@ -1014,12 +1216,12 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
                          A.n, A.m, (int32_t)(WT == kWF32), &A.ctl->done, &A.ctl->converged);
     }
     void* tk = capture ? nullptr : ktimer_begin(stream);
-    if (A.n <= kTinyN && A.m <= kTinyLdsM)
-      hipLaunchKernelGGL((ss_tiny_kernel<WT, true>), dim3(1), dim3(threads), 0, stream, A,
+    if (A.n <= kTinyN && A.m <= kLdsM)  // its own workgroup size (the whole graph in registers)
+      hipLaunchKernelGGL(ss_lds_kernel<WT>, dim3(1), dim3(kLdsThreads), 0, stream, A,
                          seeds.sources_dev, seeds.voff_dev, seeds.count, seeds.source,
                          (int32_t)(T.validate != 0), info);
     else if (A.n <= kTinyN)
-      hipLaunchKernelGGL((ss_tiny_kernel<WT, false>), dim3(1), dim3(threads), 0, stream, A,
+      hipLaunchKernelGGL(ss_tiny_kernel<WT>, dim3(1), dim3(threads), 0, stream, A,
                          seeds.sources_dev, seeds.voff_dev, seeds.count, seeds.source,
                          (int32_t)(T.validate != 0), info);
     else

@@ -88,10 +88,11 @@ def test_grid_f32_small(dawn):
 
 
 def test_grid_f32_tiny_and_small_paths(dawn):
-    """n <= 6144 runs with its whole state in LDS (with m <= 10240 the CSR too),
-    larger small graphs in one workgroup over global memory; every many-step
-    fp32 case matches the oracle."""
-    for rows, cols in ((40, 40), (60, 60), (90, 90)):
+    """n <= 6144 runs in one workgroup with its state in LDS (with m <= 16384
+    the whole graph, edge-parallel steps; 70x70 has more edges and takes the
+    queue kernel), larger small graphs in one workgroup over global memory;
+    every many-step fp32 case matches the oracle."""
+    for rows, cols in ((40, 40), (60, 60), (70, 70), (90, 90)):
         g = graphgen.grid(rows, cols, 0.02, 5, weights="f32unit")
         for s in graphgen.pick_sources(g, 2, 3):
             announce("grid", rows, cols, "f32 source", s)
@@ -151,6 +152,62 @@ def test_chain_step_count(dawn):
 
 def to_np_u32(d):
     return np.asarray(d).view(np.uint32)
+
+
+def _lds_cases():
+    """Graphs at and around the whole-graph-in-LDS limits (n <= 6144, m <= 16384)."""
+    rng = np.random.default_rng(11)
+    cases = [("er-m16384", graphgen.er(6144, 16384, 12, weights="u32", wlo=1, whi=100), 5),
+             ("er-m16385", graphgen.er(6144, 16385, 12, weights="u32", wlo=1, whi=100), 5),
+             ("er-zero-weights", graphgen.er(2000, 12000, 13, weights="u32", wlo=0, whi=2), 7),
+             ("grid60-f32", graphgen.grid(60, 60, 0.02, 14, weights="f32unit"), 100)]
+    # a hub row of 5999 edges (one thread writes its edges' source ids) and a
+    # ring of leaf edges back into the graph
+    n = 6000
+    src = np.concatenate([np.zeros(n - 1, np.int64), np.arange(1, n)])
+    dst = np.concatenate([np.arange(1, n), (np.arange(1, n) * 7) % n])
+    w = rng.integers(1, 1000, size=src.size).astype(np.uint32)
+    cases.append(("hub", graphgen.from_edges(n, src, dst, w, "u32"), 0))
+    cases.append(("hub-leaf", graphgen.from_edges(n, src, dst, w, "u32"), 4321))
+    return cases
+
+
+@pytest.mark.parametrize("wg", [0, 256, 512])
+def test_lds_graph_limits_and_shapes(dawn, wg):
+    """One-workgroup runs of graphs held whole in LDS: at the edge limit and one
+    edge past it (the queue kernel), zero weights, fp32, a hub row; every
+    workgroup size gives the oracle's distances."""
+    for name, g, s in _lds_cases():
+        announce("lds case", name, "n", g.n, "m", g.m, "source", s, "wg", wg)
+        d, info = _run(dawn, g, s, small_m=1 << 30, wg_threads=wg)
+        assert_sssp_matches(g, s, d, tag=name)
+        assert info["converged"] == 1
+
+
+def test_lds_graph_counters_are_algorithm2s(dawn):
+    """Edge-parallel steps count what Algorithm 2 counts: at unit weights the
+    counters of sequential Algorithm 2 exactly, and on a chain L + 1 steps
+    with L edges scanned and L improvements."""
+    g = graphgen.rmat(12, 3, 22, weights="u32one")
+    assert g.n <= 6144 and g.m <= 16384
+    for s in graphgen.pick_sources(g, 3, 5):
+        announce("lds unit weights source", s)
+        d, info = _run(dawn, g, s, small_m=1 << 30)
+        lvl = oracle.bfs(g, s)
+        assert np.array_equal(to_np_u32(d), np.where(lvl < 0, INF32, lvl).astype(np.uint32))
+        _, c = oracle.govm(g, s)
+        for key in ("steps", "edges_scanned", "improvements", "frontier_entries"):
+            assert info[key] == c[key], key
+    L = 3000
+    rng = np.random.default_rng(6)
+    w = rng.integers(1, 100, size=L).astype(np.uint32)
+    g = graphgen.from_edges(L + 1, np.arange(L), np.arange(1, L + 1), w, "u32")
+    announce("lds chain", L)
+    d, info = _run(dawn, g, 0, small_m=1 << 30)
+    assert to_np_u32(d).tolist() == np.concatenate([[0], np.cumsum(w)]).tolist()
+    assert info["steps"] == L + 1
+    assert info["edges_scanned"] == L and info["improvements"] == L
+    assert info["frontier_entries"] == L
 
 
 def test_unit_weights_are_bfs_with_mu_one(dawn):
