@@ -143,6 +143,26 @@ def test_batch_union_matches_each_graph(dawn):
     b.close()
 
 
+def test_batch_union_held_in_lds(dawn):
+    """A union small enough to sit whole in LDS (n <= 6144, m <= 16384) runs in
+    the one-workgroup edge-parallel kernel with one seed per graph (vertex
+    offsets); each graph's distances equal the oracle's."""
+    import torch
+    gs = workloads.er_batch(seed=9, count=4, lo=2.0, hi=2.6)
+    assert sum(g.n for g, _ in gs) <= 6144 and sum(g.m for g, _ in gs) <= 16384
+    csrs = [dawn.Csr.from_graph(g) for g, _ in gs]
+    b = dawn.Batch(csrs)
+    srcs = torch.tensor([s for _, s in gs], dtype=torch.int32, device="cuda")
+    info = dawn.info_tensor()
+    announce("batch in LDS", len(gs), "graphs, total_n", b.total_n)
+    out = b.run(srcs, info=info)
+    torch.cuda.synchronize()
+    for (g, s), d in zip(gs, b.split(out)):
+        assert_sssp_matches(g, s, to_np(d), tag=f"lds batch {g.name}")
+    assert dawn.read_info(info)["converged"] == 1
+    b.close()
+
+
 # captured: the persistent launch alone; step launches then the persistent
 # launch for the rest (3 step launches); step launches covering every step, the
 # persistent launch returning at once (64 step launches); mode 1 explicitly
