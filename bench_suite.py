@@ -262,6 +262,26 @@ def c3(args, dawn, torch, np):
            "gteps_mean": float(np.mean(gteps)),
            "parity": note_parity("c3", bad, len(srcs)), "cpu_baseline": cpu}
     rec.update(percentile_ms(per))
+    # The same sources as one batched call (a tile with one column per
+    # source): the sources/s the library gives on this graph.  Every column is
+    # compared bit for bit with its source's single-source result (checked
+    # against the oracle above).
+    src_t = torch.as_tensor(np.asarray(srcs, dtype=np.int32), device="cuda")
+    tinfo = dawn.info_tensor()
+    tout = dawn.msssp(csr, src_t, info=tinfo, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dawn.msssp(csr, src_t, out=tout, info=tinfo, check=False)
+    torch.cuda.synchronize()
+    t_tile = time.perf_counter() - t0
+    ti = dawn.read_info(tinfo)
+    tb = tout.cpu().numpy()
+    tile_bad = sum(int((tb[j].view(np.uint32) != got[j].view(np.uint32)).sum())
+                   for j in range(len(srcs))) + int(ti["converged"] != 1)
+    rec["batched"] = {"sources": len(srcs), "ms": t_tile * 1e3, "steps": ti["steps"],
+                      "sources_per_s": len(srcs) / t_tile, "gteps": sum(reach) / t_tile / 1e9,
+                      "vs_single_source_sources_per_s": (len(srcs) / t_tile) / (len(srcs) / sum(per)),
+                      "parity": note_parity("c3 batched", tile_bad, len(srcs))}
     return rec
 
 

@@ -150,7 +150,8 @@ typedef struct {
  * waits longer than barrier_ms ends the run with converged = -2, never a hang.
  * Tile sessions always take step launches.
  * wg_threads: 256, 512 or 1024, or 0 = auto (single source: 512 for step launches,
- * 1024 for persistent launches; tiles 256).  One-workgroup single-source runs
+ * 1024 for persistent launches; tiles: 256 for step launches, 1024 for
+ * persistent launches).  One-workgroup single-source runs
  * of graphs held whole in LDS (n <= 6144 and m <= 16384) always take 1024
  * threads: each thread keeps its share of the edges in registers.
  * grid: workgroups per launch, 0 = auto (persistent: what the device holds at

@@ -36,6 +36,12 @@
 namespace dawn {
 
 constexpr int kTileU = 4;  // edges in flight per 16-lane group
+// Persistent tile launches default to one 1024-thread workgroup per compute
+// unit: each workgroup's arrival at a grid barrier costs serial time at the
+// barrier word, and runs with thousands of steps (grids) pay two barriers per
+// step (measured on a 2048 x 2048 grid: about 130 us per step instead of 335
+// with four 256-thread workgroups per compute unit).
+constexpr int kTilePersistentThreads = 1024;
 
 // ---------------------------------------------------------------------------
 // reset / seed / admit / evict
@@ -505,13 +511,14 @@ __device__ __forceinline__ void tile_sparse_relax(const TileArgs& A, int32_t u, 
 __device__ __forceinline__ void tile_row_setup(const TileArgs& A, const int32_t* qq, uint32_t n,
                                                uint32_t b0, int q, int qn, int32_t& u,
                                                int32_t& start, int32_t& deg, uint32_t& act,
-                                               uint32_t& nsrc) {
+                                               uint32_t& nsrc, unsigned long long& mask0) {
   const uint32_t i = b0 + (uint32_t)lane_id();
   u = 0;
   start = 0;
   deg = 0;
   act = 0u;
   nsrc = 0u;
+  mask0 = 0ull;
   if (i >= n) return;
   u = ld_queue(qq + i);
   start = A.rowptr[u];
@@ -519,12 +526,89 @@ __device__ __forceinline__ void tile_row_setup(const TileArgs& A, const int32_t*
   unsigned long long ns = 0ull;
   for (int s = 0; s < A.nseg; s++) {
     const unsigned long long x = tile_row_mask(A, q, qn, u, s);
+    if (s == 0) mask0 = x;
     if (x) {
       act |= 1u << s;
       ns += (unsigned long long)__popcll(x);
     }
   }
   nsrc = (uint32_t)ns;
+}
+
+// Staging of one wavefront's rows for tile_lane_rows.
+struct TileLaneStage {
+  int32_t incl[kWave];
+  int32_t base[kWave];
+  int32_t u[kWave];
+  unsigned long long mask[kWave];
+};
+
+// Short rows of a one-segment tile (K <= 64) with few active sources, one
+// edge per lane: lane i holds row i (its vertex, row bounds and active-source
+// mask); the rows' edges are concatenated through an LDS prefix sum of their
+// degrees and lane l takes edges l, l + 64, ...  For its edge (u, v) a lane
+// relaxes each active source of u, four at a time with their loads in flight
+// together.  A 16-lane group per row would keep only four rows in flight per
+// wavefront, each waiting on its own chain of loads; here 64 edges are.
+// Reached by the whole wavefront; rows with deg = 0 take no edge.
+template <bool F32>
+__device__ __forceinline__ void tile_lane_rows(const TileArgs& A, int32_t u, int32_t start,
+                                               int32_t deg, unsigned long long mask,
+                                               unsigned long long* mk_next,
+                                               unsigned long long* sh_colact, TileLaneStage& st) {
+  const int lane = lane_id();
+  const int incl = wave_incl_scan(deg);
+  const int total = __shfl(incl, kWave - 1, kWave);
+  st.incl[lane] = incl;
+  st.base[lane] = start - (incl - deg);
+  st.u[lane] = u;
+  st.mask[lane] = mask;
+  wave_lds_sync();
+  const int K = A.K;
+  unsigned long long colact = 0ull;
+  for (int k = lane; k < total; k += kWave) {
+    int owner = 0;  // first lane whose inclusive prefix exceeds k
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1)
+      if (st.incl[owner + s - 1] <= k) owner += s;
+    const int32_t e = st.base[owner] + k;
+    const uint32_t* du = A.D + (size_t)st.u[owner] * K;
+    unsigned long long x = st.mask[owner];
+    const int32_t v = A.colidx[e];
+    const uint32_t w = A.w[e];
+    uint32_t* dv = A.D + (size_t)v * K;
+    unsigned long long got = 0ull;
+    while (x) {
+      int c[4];
+      bool ok[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        ok[i] = x != 0ull;
+        c[i] = ok[i] ? __ffsll((long long)x) - 1 : 0;
+        x &= x - 1ull;
+      }
+      uint32_t a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        a[i] = du[c[i]];
+        b[i] = dv[c[i]];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const uint32_t cand = relax_add<F32>(a[i], w);
+        if (ok[i] && cand < b[i]) {
+          atomicMin(dv + c[i], cand);
+          got |= 1ull << c[i];
+        }
+      }
+    }
+    if (got) {
+      atomicOr(mk_next + v, got);  // one segment: row v's only mask word
+      colact |= got;
+    }
+  }
+  if (colact) atomicOr(&sh_colact[0], colact);
+  wave_lds_sync();
 }
 
 // Clear the mask words of the previous step's frontier rows (slot read one
@@ -616,7 +700,8 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
   for (uint32_t b0 = gw * pw; b0 < hw; b0 += kWave) {
     int32_t u, start, deg;
     uint32_t act, nsrc;
-    tile_row_setup(A, A.qwave[q], hw, b0, q, qn, u, start, deg, act, nsrc);
+    unsigned long long mask0;
+    tile_row_setup(A, A.qwave[q], hw, b0, q, qn, u, start, deg, act, nsrc, mask0);
     const int rows = (int)min((uint32_t)kWave, hw - b0);
     for (int r = 0; r < rows; r++) {
       const uint32_t ar = (uint32_t)__builtin_amdgcn_readlane((int)act, r);
@@ -641,15 +726,27 @@ __device__ void tile_relax(const TileArgs& A, uint32_t step, uint32_t gb, uint32
   const uint32_t ng = min(ld_agent(&C->cnt[rc][0].v), A.cap_v);
   const uint32_t pg = (ng + nwv - 1) / nwv, hg = min(ng, gw * pg + pg);
   const int grp = lane >> 4;
+  // one-segment tiles: rows with few active sources go one edge per lane
+  __shared__ TileLaneStage lst[kMaxWavesPerBlock];
+  const bool lane_rows = nseg == 1;
   for (uint32_t b0 = gw * pg; b0 < hg; b0 += kWave) {
     int32_t u, start, deg;
     uint32_t act, nsrc;
-    tile_row_setup(A, A.qgrp[q], hg, b0, q, qn, u, start, deg, act, nsrc);
+    unsigned long long mask0;
+    tile_row_setup(A, A.qgrp[q], hg, b0, q, qn, u, start, deg, act, nsrc, mask0);
     const int rows = (int)min((uint32_t)kWave, hg - b0);
+    bool lr = false;
+    if (lane_rows) {
+      lr = act != 0u && (int)nsrc <= A.sparse;
+      if (__ballot(lr) != 0ull)
+        tile_lane_rows<F32>(A, u, start, lr ? deg : 0, lr ? mask0 : 0ull, mkn, sh_colact,
+                            lst[wave]);
+    }
+    const uint32_t act_g = lr ? 0u : act;  // the rows left to the 16-lane groups
     // group g walks rows b0 + 4 r + g, held by lane 4 r + g
     for (int r = 0; 4 * r < rows; r++) {
       const int src = 4 * r + grp;
-      const uint32_t ar = (uint32_t)__shfl((int)act, src, kWave);
+      const uint32_t ar = (uint32_t)__shfl((int)act_g, src, kWave);
       const int32_t ur = __shfl(u, src, kWave);
       const int32_t sr = __shfl(start, src, kWave);
       const int32_t dr = __shfl(deg, src, kWave);
@@ -1504,12 +1601,12 @@ dawn_status tile_evict(const TileArgs& a, bool f32, int32_t col, hipStream_t str
 }
 
 Residency tile_persistent_residency(int threads) {
-  if (threads <= 0) threads = 256;
+  if (threads <= 0) threads = kTilePersistentThreads;
   return residency_of(tile_persistent_kernel<false>, threads);
 }
 
 Residency utile_persistent_residency(int threads) {
-  if (threads <= 0) threads = 256;
+  if (threads <= 0) threads = kTilePersistentThreads;
   return residency_of(utile_persistent_kernel<4>, threads);
 }
 
@@ -1533,7 +1630,7 @@ static hipError_t launch_persistent(K kernel, int grid, int threads, hipStream_t
 
 dawn_status utile_persistent(const TileArgs& a, hipStream_t stream) {
   const Tuning& T = tuning();
-  const int threads = T.wg_threads > 0 ? T.wg_threads : 256;
+  const int threads = T.wg_threads > 0 ? T.wg_threads : kTilePersistentThreads;
   auto k = a.nseg <= 1 ? utile_persistent_kernel<1> : a.nseg <= 2 ? utile_persistent_kernel<2>
          : a.nseg <= 4 ? utile_persistent_kernel<4> : utile_persistent_kernel<8>;
   int grid = residency_of(k, threads).grid;
@@ -1551,13 +1648,14 @@ static dawn_status tile_steps_t(const TileArgs& a, bool persistent, int32_t max_
   const int threads = T.wg_threads > 0 ? T.wg_threads : 256;
   const int32_t cap_n = persistent ? 1 : 0;
   if (persistent) {
-    int grid = residency_of(tile_persistent_kernel<F32>, threads).grid;
+    const int pthreads = T.wg_threads > 0 ? T.wg_threads : kTilePersistentThreads;
+    int grid = residency_of(tile_persistent_kernel<F32>, pthreads).grid;
     if (T.grid > 0 && T.grid < grid) grid = T.grid;
     TileArgs aa = a;
     aa.pull_min = -1;  // pull steps need the step-launch path
     void* tk = ktimer_begin(stream);
     const hipError_t e =
-        launch_persistent(tile_persistent_kernel<F32>, grid, threads, stream, aa, max_steps, cap_n);
+        launch_persistent(tile_persistent_kernel<F32>, grid, pthreads, stream, aa, max_steps, cap_n);
     ktimer_end(tk, stream, 1);
     return hip_check(e, "tile persistent launch");
   }

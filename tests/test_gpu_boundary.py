@@ -193,7 +193,7 @@ def test_persistent_grids_follow_the_residency_rule(dawn, threads):
         dawn.set_tuning(**prev)
     assert q["cus"] >= 1
     ss_t = threads or 1024
-    tile_t = threads or 256
+    tile_t = threads or 1024
     for key, vg, lds, api, t in (("ss", q["ss_vgprs"], q["ss_lds"], q["ss_api_blocks_per_cu"], ss_t),
                                  ("tile", q["tile_vgprs"], q["tile_lds"],
                                   q["tile_api_blocks_per_cu"], tile_t)):
