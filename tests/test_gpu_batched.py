@@ -56,6 +56,31 @@ TILE_TUNINGS = [
 ]
 
 
+# One-segment tiles (K <= 64): group-tier rows with at most tile_sparse active
+# sources are relaxed one edge per lane.
+ONE_SEG_TUNINGS = [
+    dict(),
+    dict(tile_sparse=64, tile_t_group=64, tile_t_wave=128),  # every group-tier row, up to 64 edges
+    dict(tile_sparse=0),                     # never
+    dict(tile_sparse=64, tile_t_group=64, tile_t_wave=128, mode=2),
+    dict(tile_sparse=2, tile_t_group=16, tile_step_launches=4096, tile_skip=1),
+]
+
+
+@pytest.mark.parametrize("wk", ["u32", "f32lognormal"])
+@pytest.mark.parametrize("ti", range(len(ONE_SEG_TUNINGS)))
+def test_one_segment_tile_rows_one_edge_per_lane(dawn, wk, ti):
+    """Every column of a one-segment tile matches the oracle whichever rows
+    take the lane-per-edge path, on R-MAT and on a many-step grid."""
+    for g in (graphgen.rmat(12, 16, 31, weights=wk), graphgen.grid(40, 30, 0.02, 32)):
+        srcs = graphgen.pick_sources(g, 50, 7 + ti)
+        announce("one-segment tile", g.name, g.wtype, ONE_SEG_TUNINGS[ti])
+        D, info = _msssp(dawn, g, srcs, **ONE_SEG_TUNINGS[ti])
+        for j in range(len(srcs)):
+            assert_sssp_matches(g, int(srcs[j]), D[j], tag=f"{g.name} col {j}")
+        assert info["converged"] == 1
+
+
 @pytest.mark.parametrize("ti", range(len(TILE_TUNINGS)))
 def test_msssp_tuning_invariance_and_sssp_identity(dawn, ti):
     """Column j of a tile equals a lone single-source run from sources[j]
