@@ -384,9 +384,12 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
     sh.upd = 0u;
   }
   __syncthreads();
-  const uint32_t nl = ld_agent(&C->cnt[rc][0].v);
-  const uint32_t nw = ld_agent(&C->cnt[rc][1].v);
-  const uint32_t ng = ld_agent(&C->cnt[rc][2].v);
+  // Entries past a queue's capacity were never written (the pushes that
+  // counted them set the overflow flag, and the run reports -3), so the
+  // counts are read up to the capacities only.
+  const uint32_t nl = min(ld_agent(&C->cnt[rc][0].v), A.cap_v);
+  const uint32_t nw = min(ld_agent(&C->cnt[rc][1].v), A.cap_v);
+  const uint32_t ng = min(ld_agent(&C->cnt[rc][2].v), A.cap_wg);
   const bool pull = PULL && A.T.hdr != nullptr && A.pull_min >= 0 &&
                     ld_agent64(&C->ctr.fedges[rc]) >= (unsigned long long)A.pull_min;
   if (pull) {
