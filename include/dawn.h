@@ -361,6 +361,14 @@ dawn_status dawn_msssp_tg_ws(const int32_t* rowptr_dev, const int32_t* colidx_de
  * distances beyond the initial INF.
  * ------------------------------------------------------------------------- */
 size_t dawn_umsssp_workspace_bytes(int32_t n, int32_t m, int32_t k);
+
+/* Bytes of caller scratch the workspace-taking call for this graph, k sources
+ * and weight type needs: k = 1, dawn_sssp_ws (= dawn_sssp_workspace_bytes);
+ * k > 1, dawn_msssp_ws (= dawn_msssp_workspace_bytes), or for DAWN_W_UNIT the
+ * hop-count tiles (= dawn_umsssp_workspace_bytes).  0 for arguments no such
+ * call accepts: n < 1, m < 0, k < 1, an unknown weight type, or DAWN_W_I32
+ * with k > 1 (signed weights are single-source only).  Host-only. */
+size_t dawn_workspace_bytes(int32_t n, int32_t m, int32_t k, dawn_wtype wt);
 dawn_status dawn_umsssp_ws(const int32_t* rowptr_dev, const int32_t* colidx_dev, int32_t n,
                            int32_t m, const void* tgraph_dev, const int32_t* sources_dev,
                            int32_t k, uint32_t* dist_out_dev, void* ws_dev, size_t ws_bytes,

@@ -92,6 +92,7 @@ def load():
         "dawn_msssp_tg_ws": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp,
                               _vp], _i32),
         "dawn_umsssp_workspace_bytes": ([_i32, _i32, _i32], _sz),
+        "dawn_workspace_bytes": ([_i32, _i32, _i32, _i32], _sz),
         "dawn_sssp_tg_ws": ([_vp, _vp, _vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp, _sz, _vp, _vp],
                             _i32),
         "dawn_tile_set_tgraph": ([_vp, _vp], _i32),
@@ -137,7 +138,7 @@ def exported_symbols() -> list[str]:
         "dawn_sssp_tg_ws", "dawn_sssp_noalloc",
         "dawn_msssp", "dawn_msssp_workspace_bytes", "dawn_msssp_ws", "dawn_apsp",
         "dawn_tgraph_bytes", "dawn_tgraph_build_bytes", "dawn_tgraph_build", "dawn_msssp_tg_ws",
-        "dawn_umsssp_workspace_bytes", "dawn_umsssp_ws", "dawn_batch_create", "dawn_batch_sizes", "dawn_batch_vertex_offset", "dawn_batch_run",
+        "dawn_umsssp_workspace_bytes", "dawn_umsssp_ws", "dawn_workspace_bytes", "dawn_batch_create", "dawn_batch_sizes", "dawn_batch_vertex_offset", "dawn_batch_run",
         "dawn_batch_capture", "dawn_batch_replay", "dawn_batch_destroy", "dawn_tile_bytes",
         "dawn_tile_create", "dawn_tile_admit", "dawn_tile_run", "dawn_tile_capture",
         "dawn_tile_replay", "dawn_tile_read",
@@ -403,6 +404,12 @@ def tgraph(csr: Csr, stream=None):
 
 def umsssp_workspace_bytes(n: int, m: int, k: int) -> int:
     return int(load().dawn_umsssp_workspace_bytes(n, m, k))
+
+
+def workspace_bytes(n: int, m: int, k: int, wtype: str = "u32") -> int:
+    """Scratch bytes of the workspace-taking call for k sources of this weight
+    type (``dawn_workspace_bytes``); 0 when no such call accepts them."""
+    return int(load().dawn_workspace_bytes(n, m, k, wtype_code(wtype)))
 
 
 def umsssp(csr: Csr, sources, out=None, stream=None, ws=None, info=None, tgraph=None,

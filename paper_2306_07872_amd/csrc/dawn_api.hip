@@ -594,6 +594,15 @@ extern "C" size_t dawn_umsssp_workspace_bytes(int32_t n, int32_t m, int32_t k) {
   return tile_layout(n, m, std::min(k, g_tuning.tile_k), true).total;
 }
 
+extern "C" size_t dawn_workspace_bytes(int32_t n, int32_t m, int32_t k, dawn_wtype wt) {
+  if (n < 1 || m < 0 || k < 1) return 0;
+  if (wt != DAWN_W_U32 && wt != DAWN_W_F32 && wt != DAWN_W_I32 && wt != DAWN_W_UNIT) return 0;
+  if (k == 1) return dawn_sssp_workspace_bytes(n, m);
+  if (wt == DAWN_W_I32) return 0;
+  return wt == DAWN_W_UNIT ? dawn_umsssp_workspace_bytes(n, m, k)
+                           : dawn_msssp_workspace_bytes(n, m, k);
+}
+
 extern "C" dawn_status dawn_umsssp_ws(const int32_t* rowptr, const int32_t* colidx, int32_t n,
                                       int32_t m, const void* tgraph, const int32_t* sources,
                                       int32_t k, uint32_t* dist_out, void* ws, size_t ws_bytes,

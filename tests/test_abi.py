@@ -110,6 +110,7 @@ def test_hop_count_entry_point_host_checks(lib):
     # bit planes of n x K/64 words each
     assert 100 * 8 * 8 <= need < lib.dawn_msssp_workspace_bytes(100, 1000, 64)
     assert lib.dawn_umsssp_workspace_bytes(0, 10, 64) == 0
+
     assert lib.dawn_umsssp_workspace_bytes(100, 1000, 0) == 0
     # no weights needed; colidx is (m > 0)
     assert lib.dawn_umsssp_ws(fake, null, 100, 1000, null, fake, 4, fake, ws, need, null,
@@ -181,3 +182,19 @@ def test_noalloc_call_host_checks(lib):
     assert lib.dawn_sssp_noalloc(fake, fake, fake, 0, 0, 0, 0, fake, null) == 1
     assert lib.dawn_sssp_noalloc(fake, fake, fake, 0, 5, 3, 5, fake, null) == 1
     assert lib.dawn_sssp_noalloc(fake, fake, fake, 0, 5, 3, 0, null, null) == 1
+
+
+def test_generic_workspace_size_dispatches_by_call(lib):
+    # k = 1: the single-source call, whatever the weight type
+    for wt in (0, 1, 2, 3):
+        assert lib.dawn_workspace_bytes(1000, 8000, 1, wt) == lib.dawn_sssp_workspace_bytes(1000, 8000)
+    # k > 1: the tile, or the hop-count tile for unit weights
+    for wt in (0, 1):
+        assert lib.dawn_workspace_bytes(1000, 8000, 300, wt) == lib.dawn_msssp_workspace_bytes(1000, 8000, 300)
+    assert lib.dawn_workspace_bytes(1000, 8000, 300, 3) == lib.dawn_umsssp_workspace_bytes(1000, 8000, 300)
+    # arguments no call accepts
+    assert lib.dawn_workspace_bytes(1000, 8000, 300, 2) == 0   # int32 weights: single source only
+    assert lib.dawn_workspace_bytes(0, 8000, 1, 0) == 0
+    assert lib.dawn_workspace_bytes(1000, -1, 1, 0) == 0
+    assert lib.dawn_workspace_bytes(1000, 8000, 0, 0) == 0
+    assert lib.dawn_workspace_bytes(1000, 8000, 1, 9) == 0
