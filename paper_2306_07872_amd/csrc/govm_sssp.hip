@@ -370,9 +370,26 @@ __device__ __forceinline__ bool ss_skip_row(const SsArgs& A, int nxt, int32_t u)
 // Returns true when the step was a pull step.
 // PULL: pull steps may run (step launches with a reverse graph); the push-only
 // instance keeps none of their code.
+// The step's queue counts (lane, wave, workgroup-chunk tiers); read at the
+// start of a step launch, or by the persistent kernel together with the
+// previous step's update flag, right after the barrier that ends that step.
+struct SsCounts {
+  uint32_t l, w, g;
+};
+
+__device__ __forceinline__ SsCounts ss_counts(const SsArgs& A, uint32_t step) {
+  const SsCtl* C = A.ctl;
+  const int rc = step % kRot;
+  // Entries past a queue's capacity were never written (the pushes that
+  // counted them set the overflow flag, and the run reports -3), so the
+  // counts are read up to the capacities only.
+  return SsCounts{min(ld_agent(&C->cnt[rc][0].v), A.cap_v), min(ld_agent(&C->cnt[rc][1].v), A.cap_v),
+                  min(ld_agent(&C->cnt[rc][2].v), A.cap_wg)};
+}
+
 template <int WT, bool PULL>
 __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb, Acc& acc,
-                        SsShared& sh) {
+                        SsShared& sh, SsCounts counts) {
   const int cur = step & 1, nxt = cur ^ 1;
   const int rc = step % kRot, rn = (step + 1) % kRot;
   SsCtl* C = A.ctl;
@@ -384,12 +401,7 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
     sh.upd = 0u;
   }
   __syncthreads();
-  // Entries past a queue's capacity were never written (the pushes that
-  // counted them set the overflow flag, and the run reports -3), so the
-  // counts are read up to the capacities only.
-  const uint32_t nl = min(ld_agent(&C->cnt[rc][0].v), A.cap_v);
-  const uint32_t nw = min(ld_agent(&C->cnt[rc][1].v), A.cap_v);
-  const uint32_t ng = min(ld_agent(&C->cnt[rc][2].v), A.cap_wg);
+  const uint32_t nl = counts.l, nw = counts.w, ng = counts.g;
   const bool pull = PULL && A.T.hdr != nullptr && A.pull_min >= 0 &&
                     ld_agent64(&C->ctr.fedges[rc]) >= (unsigned long long)A.pull_min;
   if (pull) {
@@ -544,15 +556,20 @@ __global__ void __launch_bounds__(1024) ss_persistent_kernel(SsArgs A) {
   uint32_t epoch = 0;
   const uint32_t bar_base = ld_agent(&C->bar_base);
   uint32_t step = ld_agent(&C->step);
+  SsCounts counts = ss_counts(A, step);
   int32_t status = 1;
   for (;;) {
     if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
-    ss_step<WT, false>(A, step, blockIdx.x, gridDim.x, acc, sh);
+    ss_step<WT, false>(A, step, blockIdx.x, gridDim.x, acc, sh, counts);
     if (!grid_sync(&C->bar.v, &C->abort, gridDim.x, bar_base, epoch, A.bar_ticks)) {
       status = -2;
       break;
     }
+    // the step's update flag and the next step's queue counts, one round trip
+    // (all were written before the barrier; nothing writes them during the
+    // next step, whose pushes count in the rotation slot after)
     const uint32_t upd = ld_agent(&C->upd[(step + 1) % kRot]);
+    counts = ss_counts(A, step + 1);
     step++;
     if (!upd) { status = 1; break; }
     if (step >= (uint32_t)A.n) { status = 0; break; }
@@ -576,7 +593,7 @@ __global__ void __launch_bounds__(1024) ss_step_kernel(SsArgs A) {
   const uint32_t step = ld_agent(&C->step);
   if (blockIdx.x == 0 && threadIdx.x == 0) ss_zero_rotation(C, step);
   Acc acc;
-  const bool pulled = ss_step<WT, PULL>(A, step, blockIdx.x, gridDim.x, acc, sh);
+  const bool pulled = ss_step<WT, PULL>(A, step, blockIdx.x, gridDim.x, acc, sh, ss_counts(A, step));
   // counters, and the next frontier's out-edges and rows (its pull decision)
   SsCounters& S = C->ctr;
   flush_acc(acc, &S.fe, &S.es, &S.im, &S.fedges[(step + 1) % kRot], &S.frows[(step + 1) % kRot]);
