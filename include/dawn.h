@@ -132,7 +132,9 @@ typedef struct {
 
 /* Launch tuning, process-wide (set before concurrent use; not thread-safe).
  * Frontier rows are binned by out-degree d into three tiers:
- *   lane tier      d <= t_lane   rows packed 64 per wavefront, one edge per lane;
+ *   lane tier      d <= t_lane   rows packed 64 per wavefront, one edge per lane
+ *                                (single source: taken from a scan of the
+ *                                frontier bitmap rather than from a queue);
  *   wave tier      d <= t_wave   one wavefront per row (t_wave >= 64);
  *   workgroup tier d >  t_wave   the row is cut into chunks of t_chunk edges,
  *                                one workgroup per chunk.

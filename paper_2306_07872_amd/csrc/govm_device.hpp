@@ -401,10 +401,11 @@ struct SsArgs {
   TGraph T;               // reverse graph for pull steps, or hdr == nullptr
   long long pull_min;     // pull when the frontier has >= this many out-edges; < 0: never
   int32_t t_lane, t_wave, t_chunk;
-  int32_t* qlane[2];      // delta, lane tier   [step % 2]
+  int32_t* qlane[2];      // delta of one-workgroup runs [step % 2]
   int32_t* qwave[2];      // delta, wave tier
   int4* qwg[2];           // delta, workgroup tier: {row, first edge, edges, first chunk?}
   uint32_t* bm[2];        // beta dedup bitmaps [step % 2]
+  uint32_t* hv;           // rows with more than t_lane edges (queued; shorter rows are scanned)
   uint32_t cap_v, cap_wg;
   SsCtl* ctl;
   unsigned long long bar_ticks;  // grid-barrier wait bound (persistent launches)

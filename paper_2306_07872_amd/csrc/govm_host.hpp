@@ -104,7 +104,7 @@ struct Carver {
 
 // ----- single source ---------------------------------------------------------
 struct SsLayout {
-  size_t ctl, qlane[2], qwave[2], qwg[2], bm[2], total;
+  size_t ctl, qlane[2], qwave[2], qwg[2], bm[2], hv, total;
   uint32_t cap_v, cap_wg;
   int64_t nwords;
 };

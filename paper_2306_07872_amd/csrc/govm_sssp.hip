@@ -37,13 +37,28 @@ namespace dawn {
 // ---------------------------------------------------------------------------
 // init
 // ---------------------------------------------------------------------------
+// hv (may be null): bit v set when row v has more than t_lane edges, the rows
+// that steps take from the wave and workgroup queues rather than from the bitmap.
 template <int WT>
 __global__ void ss_fill_kernel(uint32_t* dist, int64_t n, uint32_t* bm0, uint32_t* bm1,
-                               int64_t nwords, SsCtl* ctl) {
+                               int64_t nwords, SsCtl* ctl, const int32_t* rowptr, uint32_t* hv,
+                               int32_t t_lane) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = tid; i < n; i += stride) dist[i] = inf_key<WT>();
   for (int64_t i = tid; i < nwords; i += stride) { bm0[i] = 0; bm1[i] = 0; }
+  if (hv) {
+    // a wavefront per 64 vertices: the ballot's halves are two bitmap words
+    // (blockDim and the grid's thread count are multiples of 64)
+    const int lane = lane_id();
+    for (int64_t v0 = tid - lane; v0 < n; v0 += stride) {
+      const int64_t v = v0 + lane;
+      const bool heavy = v < n && rowptr[v + 1] - rowptr[v] > t_lane;
+      const unsigned long long b = __ballot(heavy);
+      const int64_t wi = v0 / 32 + (lane >> 5);
+      if ((lane & 31) == 0 && wi < nwords) hv[wi] = (uint32_t)(b >> (lane & 32));
+    }
+  }
   if (blockIdx.x == 0) {
     uint32_t* c = reinterpret_cast<uint32_t*>(ctl);
     for (int i = threadIdx.x; i < (int)(sizeof(SsCtl) / 4); i += blockDim.x) c[i] = 0;
@@ -90,8 +105,7 @@ __global__ void ss_seed_kernel(SsArgs A, const int32_t* sources, const int64_t* 
     atomicAdd(&C->ctr.fedges[0], (unsigned long long)deg);
     atomicAdd(&C->ctr.frows[0], 1ull);
     if (deg <= A.t_lane) {
-      const uint32_t p = atomicAdd(&C->cnt[0][0].v, 1u);
-      A.qlane[0][p] = (int32_t)s;
+      // short row: step 0 finds it by its bit
     } else if (deg <= A.t_wave) {
       const uint32_t p = atomicAdd(&C->cnt[0][1].v, 1u);
       A.qwave[0][p] = (int32_t)s;
@@ -151,16 +165,15 @@ __global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info, uint32_t* latc
 // Next-frontier entries found by a workgroup are gathered in LDS and written
 // to the global queues once at the end of the step with one atomicAdd per
 // tier per workgroup (a queue that fills up spills straight to global memory).
-constexpr int kLdsQLane = 1536;
 constexpr int kLdsQWave = 512;
 constexpr int kUnroll = 4;      // edges in flight per lane (wave and workgroup tiers)
 constexpr int kUnrollLane = 2;  // edges in flight per lane (lane tier)
 
 struct SsShared {
-  int stage[kMaxWavesPerBlock * 3 * kWave];  // lane-tier batch: prefix, row base, distance
-  int32_t ql[kLdsQLane];
+  int stage[kMaxWavesPerBlock * 3 * kWave];      // lane-tier batch: prefix, row base, distance
+  uint32_t scan[kMaxWavesPerBlock * 2 * kWave];  // bitmap block: short-row bits, their prefix
   int32_t qw[kLdsQWave];
-  uint32_t nql, nqw, upd, gbase_l, gbase_w;
+  uint32_t nqw, upd, gbase_w;
 };
 
 // Push `v` for lanes with `pred` into the workgroup's LDS queue; lanes past
@@ -181,9 +194,11 @@ __device__ __forceinline__ void block_push(bool pred, int32_t v, int32_t* sq, ui
 }
 
 // Record improvements of alpha[v[i]] (lanes with imp[i]): the ptr flag, the
-// beta bitmap, and for the first setter of a bit, the next-step queue of v's
-// degree tier.  Reached by the whole wavefront.  CNT: also count the next
-// frontier's rows and out-edges (the pull decision of the next step).
+// beta bitmap, and for the first setter of a bit whose row has more than
+// t_lane edges, the next-step queue of its degree tier (shorter rows are found
+// by the next step's bitmap scan).  Reached by the whole wavefront.  CNT: also
+// count the next frontier's rows and out-edges (the pull decision of the next
+// step).
 template <int WT, int U, bool CNT>
 __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U],
                                            const int32_t (&v)[U], const uint32_t (&cand)[U],
@@ -195,6 +210,9 @@ __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U]
   SsCtl* C = A.ctl;
   if (any) sh.upd = 1u;
   bool newv[U];
+  uint32_t hvw[U];  // heavy-row words, loaded beside the test-and-set
+#pragma unroll
+  for (int i = 0; i < U; i++) hvw[i] = imp[i] && !CNT ? A.hv[v[i] >> 5] : 0u;
 #pragma unroll
   for (int i = 0; i < U; i++) {
     newv[i] = false;
@@ -221,7 +239,7 @@ __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U]
   for (int i = 0; i < U; i++) {
     start[i] = 0;
     deg[i] = 0;
-    if (newv[i]) {
+    if (newv[i] && (CNT || ((hvw[i] >> (v[i] & 31)) & 1u))) {
       start[i] = A.rowptr[v[i]];
       deg[i] = A.rowptr[v[i] + 1] - start[i];
       if (CNT && deg[i] > 0) {
@@ -232,10 +250,7 @@ __device__ __forceinline__ void ss_enqueue(const SsArgs& A, const bool (&imp)[U]
   }
 #pragma unroll
   for (int i = 0; i < U; i++) {
-    const bool tl = newv[i] && deg[i] > 0 && deg[i] <= A.t_lane;
     const bool tw = newv[i] && deg[i] > A.t_lane && deg[i] <= A.t_wave;
-    block_push(tl, v[i], sh.ql, &sh.nql, kLdsQLane, A.qlane[nxt], &C->cnt[rn][0].v, A.cap_v,
-               &C->overflow);
     block_push(tw, v[i], sh.qw, &sh.nqw, kLdsQWave, A.qwave[nxt], &C->cnt[rn][1].v, A.cap_v,
                &C->overflow);
     if (newv[i] && deg[i] > A.t_wave) {
@@ -363,6 +378,22 @@ __device__ __forceinline__ void ss_pull(const SsArgs& A, int cur, int nxt, int r
 // lowered again during this step is already marked for the next step, where
 // it is expanded with a value at least as low; expanding it now as well would
 // only repeat that work.  Its current-bitmap word is still cleared.
+// Position of the set bit of x that has r set bits below it (x has more than
+// r set bits): a binary search on the population counts of its low halves.
+__device__ __forceinline__ int nth_set_bit(uint32_t x, int r) {
+  int pos = 0;
+#pragma unroll
+  for (int s = 16; s >= 1; s >>= 1) {
+    const int lo = __popc(x & ((1u << s) - 1u));
+    if (r >= lo) {
+      r -= lo;
+      x >>= s;
+      pos += s;
+    }
+  }
+  return pos;
+}
+
 __device__ __forceinline__ bool ss_skip_row(const SsArgs& A, int nxt, int32_t u) {
   return A.skip && ((ld_agent(&A.bm[nxt][u >> 5]) >> (u & 31)) & 1u);
 }
@@ -374,7 +405,7 @@ __device__ __forceinline__ bool ss_skip_row(const SsArgs& A, int nxt, int32_t u)
 // start of a step launch, or by the persistent kernel together with the
 // previous step's update flag, right after the barrier that ends that step.
 struct SsCounts {
-  uint32_t l, w, g;
+  uint32_t w, g;  // wave-tier rows, workgroup-tier chunks
 };
 
 __device__ __forceinline__ SsCounts ss_counts(const SsArgs& A, uint32_t step) {
@@ -383,8 +414,7 @@ __device__ __forceinline__ SsCounts ss_counts(const SsArgs& A, uint32_t step) {
   // Entries past a queue's capacity were never written (the pushes that
   // counted them set the overflow flag, and the run reports -3), so the
   // counts are read up to the capacities only.
-  return SsCounts{min(ld_agent(&C->cnt[rc][0].v), A.cap_v), min(ld_agent(&C->cnt[rc][1].v), A.cap_v),
-                  min(ld_agent(&C->cnt[rc][2].v), A.cap_wg)};
+  return SsCounts{min(ld_agent(&C->cnt[rc][1].v), A.cap_v), min(ld_agent(&C->cnt[rc][2].v), A.cap_wg)};
 }
 
 template <int WT, bool PULL>
@@ -394,14 +424,15 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
   const int rc = step % kRot, rn = (step + 1) % kRot;
   SsCtl* C = A.ctl;
   const int lane = lane_id(), wave = threadIdx.x >> 6, W = blockDim.x >> 6;
-  const uint32_t gw = gb * W + wave, nwv = nb * W;
+  // wave-major: consecutive work items go to different workgroups, so a
+  // frontier smaller than the grid's waves is spread over every compute unit
+  const uint32_t gw = (uint32_t)wave * nb + gb, nwv = nb * W;
   if (threadIdx.x == 0) {
-    sh.nql = 0u;
     sh.nqw = 0u;
     sh.upd = 0u;
   }
   __syncthreads();
-  const uint32_t nl = counts.l, nw = counts.w, ng = counts.g;
+  const uint32_t nw = counts.w, ng = counts.g;
   const bool pull = PULL && A.T.hdr != nullptr && A.pull_min >= 0 &&
                     ld_agent64(&C->ctr.fedges[rc]) >= (unsigned long long)A.pull_min;
   if (pull) {
@@ -417,10 +448,7 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
       const int32_t len = ss_skip_row(A, nxt, u) ? 0 : r.z;
       if (threadIdx.x == 0) {
         acc.es += (unsigned long long)len;
-        if (r.w) {
-          A.bm[cur][u >> 5] = 0u;
-          acc.fe += 1;
-        }
+        if (r.w) acc.fe += 1;
       }
       const int32_t stride = (int32_t)blockDim.x;
       for (int32_t base = 0; base < len; base += stride * kUnroll) {
@@ -446,7 +474,6 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
       const int32_t end = ss_skip_row(A, nxt, u) ? start : A.rowptr[u + 1];
       const uint32_t du = ld_agent(&A.dist[u]);
       if (lane == 0) {
-        A.bm[cur][u >> 5] = 0u;
         acc.fe += 1;
         acc.es += (unsigned long long)(end - start);
       }
@@ -465,68 +492,97 @@ __device__ bool ss_step(const SsArgs& A, uint32_t step, uint32_t gb, uint32_t nb
       }
     }
 
-    // lane tier: 64 short rows per wavefront, their edges dealt out to the lanes
-    // through an LDS prefix sum of the row lengths
+    // lane tier: rows of at most t_lane edges are not queued.  Each wavefront
+    // scans blocks of bw words of the step's bitmap (bw <= 64, halved until
+    // there are at least as many blocks as wavefronts; the rows come in index
+    // order), clears them, and takes their short rows 64 at a time; the rows'
+    // edges are dealt out to the lanes through an LDS prefix sum of the row
+    // lengths.  The scan clears every word, heavy rows' bits included: nothing
+    // else reads this bitmap during a push step.
     int* l_incl = sh.stage + wave * 3 * kWave;
     int* l_base = l_incl + kWave;
     int* l_du = l_base + kWave;
-    for (uint32_t bi = gw; (uint64_t)bi * kWave < nl; bi += nwv) {
-      const uint32_t i = bi * kWave + lane;
-      const bool has = i < nl;
-      int32_t u = 0, start = 0, deg = 0;
-      uint32_t du = 0;
-      if (has) {
-        u = ld_queue(&A.qlane[cur][i]);
-        start = A.rowptr[u];
-        deg = ss_skip_row(A, nxt, u) ? 0 : A.rowptr[u + 1] - start;
-        du = ld_agent(&A.dist[u]);
-        A.bm[cur][u >> 5] = 0u;
-        acc.fe += 1;
-        acc.es += (unsigned long long)deg;
+    uint32_t* s_bits = sh.scan + wave * 2 * kWave;
+    uint32_t* s_pre = s_bits + kWave;
+    const int64_t nwords = ((int64_t)A.n + 31) / 32;
+    int bw = kWave;
+    while (bw > 1 && (nwords + bw - 1) / bw < (int64_t)nwv) bw >>= 1;
+    const uint32_t nblk = (uint32_t)((nwords + bw - 1) / bw);
+    for (uint32_t blk = gw; blk < nblk; blk += nwv) {
+      const int64_t wi = (int64_t)blk * bw + lane;
+      uint32_t bits = 0u;
+      if (lane < bw && wi < nwords) {
+        const uint32_t word = ld_agent(&A.bm[cur][wi]);
+        if (word) {
+          A.bm[cur][wi] = 0u;
+          bits = word & ~A.hv[wi];
+        }
       }
-      const int incl = wave_incl_scan(deg);
-      const int total = __shfl(incl, kWave - 1, kWave);
-      l_incl[lane] = incl;
-      l_base[lane] = start - (incl - deg);
-      l_du[lane] = (int)du;
+      const int cnt = __popc(bits);
+      const int incl = wave_incl_scan(cnt);
+      const int nrows = __shfl(incl, kWave - 1, kWave);
+      if (nrows == 0) continue;
+      s_bits[lane] = bits;
+      s_pre[lane] = (uint32_t)(incl - cnt);
       wave_lds_sync();
-      for (int base = 0; base < total; base += kWave * kUnrollLane) {
-        int32_t e[kUnrollLane], v[kUnrollLane];
-        bool ok[kUnrollLane], imp[kUnrollLane];
-        uint32_t d[kUnrollLane], cand[kUnrollLane];
-  #pragma unroll
-        for (int j = 0; j < kUnrollLane; j++) {
-          const int k = base + j * kWave + lane;
-          int owner = 0;  // first lane whose inclusive prefix exceeds k
+      for (int r0 = 0; r0 < nrows; r0 += kWave) {
+        const int j = r0 + lane;
+        const bool has = j < nrows;
+        int32_t start = 0, deg = 0;
+        uint32_t du = 0;
+        if (has) {
+          int o = 0;  // the last word whose exclusive prefix is <= j (o + s <= 63 throughout)
   #pragma unroll
           for (int s = 32; s >= 1; s >>= 1)
-            if (l_incl[owner + s - 1] <= k) owner += s;
-          ok[j] = k < total;
-          e[j] = l_base[owner] + k;
-          d[j] = (uint32_t)l_du[owner];
+            if (s_pre[o + s] <= (uint32_t)j) o += s;
+          const int pos = nth_set_bit(s_bits[o], j - (int)s_pre[o]);
+          const int32_t u = (int32_t)(((int64_t)blk * bw + o) * 32 + pos);
+          start = A.rowptr[u];
+          deg = A.rowptr[u + 1] - start;
+          du = ld_agent(&A.dist[u]);
+          const bool skipped = ss_skip_row(A, nxt, u);
+          if (deg > 0) acc.fe += 1;  // a frontier row (rows without edges are not counted)
+          if (skipped) deg = 0;
+          acc.es += (unsigned long long)deg;
         }
-        ss_relax_pre<WT, kUnrollLane>(A, e, ok, d, imp, v, cand);
-        ss_enqueue<WT, kUnrollLane, PULL>(A, imp, v, cand, nxt, rn, acc, sh);
+        const int dincl = wave_incl_scan(deg);
+        const int total = __shfl(dincl, kWave - 1, kWave);
+        l_incl[lane] = dincl;
+        l_base[lane] = start - (dincl - deg);
+        l_du[lane] = (int)du;
+        wave_lds_sync();
+        for (int base = 0; base < total; base += kWave * kUnrollLane) {
+          int32_t e[kUnrollLane], v[kUnrollLane];
+          bool ok[kUnrollLane], imp[kUnrollLane];
+          uint32_t d[kUnrollLane], cand[kUnrollLane];
+  #pragma unroll
+          for (int jj = 0; jj < kUnrollLane; jj++) {
+            const int k = base + jj * kWave + lane;
+            int owner = 0;  // first lane whose inclusive prefix exceeds k
+  #pragma unroll
+            for (int s = 32; s >= 1; s >>= 1)
+              if (l_incl[owner + s - 1] <= k) owner += s;
+            ok[jj] = k < total;
+            e[jj] = l_base[owner] + k;
+            d[jj] = (uint32_t)l_du[owner];
+          }
+          ss_relax_pre<WT, kUnrollLane>(A, e, ok, d, imp, v, cand);
+          ss_enqueue<WT, kUnrollLane, PULL>(A, imp, v, cand, nxt, rn, acc, sh);
+        }
+        wave_lds_sync();
       }
-      wave_lds_sync();
     }
 
   }
 
   // publish the workgroup's next-frontier entries and ptr flag
   __syncthreads();
-  const uint32_t n_l = min(sh.nql, (uint32_t)kLdsQLane), n_w = min(sh.nqw, (uint32_t)kLdsQWave);
+  const uint32_t n_w = min(sh.nqw, (uint32_t)kLdsQWave);
   if (threadIdx.x == 0) {
-    if (n_l) sh.gbase_l = atomicAdd(&C->cnt[rn][0].v, n_l);
     if (n_w) sh.gbase_w = atomicAdd(&C->cnt[rn][1].v, n_w);
     if (sh.upd) st_agent(&C->upd[rn], 1u);
   }
   __syncthreads();
-  for (uint32_t j = threadIdx.x; j < n_l; j += blockDim.x) {
-    const uint32_t p = sh.gbase_l + j;
-    if (p < A.cap_v) A.qlane[nxt][p] = sh.ql[j];
-    else atomicOr(&C->overflow, 1u);
-  }
   for (uint32_t j = threadIdx.x; j < n_w; j += blockDim.x) {
     const uint32_t p = sh.gbase_w + j;
     if (p < A.cap_v) A.qwave[nxt][p] = sh.qw[j];
@@ -1199,6 +1255,7 @@ SsLayout ss_layout(int64_t n, int64_t m) {
   for (int i = 0; i < 2; i++) L.qwave[i] = c.take((size_t)n * 4);
   for (int i = 0; i < 2; i++) L.qwg[i] = c.take((size_t)L.cap_wg * 16);
   for (int i = 0; i < 2; i++) L.bm[i] = c.take((size_t)L.nwords * 4);
+  L.hv = c.take((size_t)L.nwords * 4);
   L.total = c.off;
   return L;
 }
@@ -1230,7 +1287,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
     // one workgroup, one launch (after the optional device validation)
     if (T.validate) {
       hipLaunchKernelGGL(ss_fill_kernel<WT>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
-                         (int64_t)A.n, A.bm[0], A.bm[1], L.nwords, A.ctl);
+                         (int64_t)A.n, A.bm[0], A.bm[1], L.nwords, A.ctl, nullptr, nullptr, 0);
       const int vb = (int)std::min<int64_t>(4096, ((int64_t)A.m + 255) / 256 + 1);
       hipLaunchKernelGGL(ss_validate_kernel, dim3(vb), dim3(256), 0, stream, rowptr, colidx, A.w,
                          A.n, A.m, (int32_t)(WT == kWF32), &A.ctl->done, &A.ctl->converged);
@@ -1255,7 +1312,7 @@ static dawn_status ss_run_t(const SsArgs& A, const int32_t* rowptr, const int32_
     return hip_check(hipGetLastError(), "small-graph launch");
   }
   hipLaunchKernelGGL(ss_fill_kernel<WT>, dim3(fill_blocks), dim3(256), 0, stream, A.dist,
-                     (int64_t)A.n, A.bm[0], A.bm[1], L.nwords, A.ctl);
+                     (int64_t)A.n, A.bm[0], A.bm[1], L.nwords, A.ctl, rowptr, A.hv, A.t_lane);
   if (T.validate) {
     const int vb = (int)std::min<int64_t>(4096, ((int64_t)A.m + 255) / 256 + 1);
     hipLaunchKernelGGL(ss_validate_kernel, dim3(vb), dim3(256), 0, stream, rowptr, colidx, A.w,
@@ -1340,6 +1397,7 @@ dawn_status ss_run(const int32_t* rowptr, const int32_t* colidx, const void* w, 
     A.qwg[i] = reinterpret_cast<int4*>(base + L.qwg[i]);
     A.bm[i] = reinterpret_cast<uint32_t*>(base + L.bm[i]);
   }
+  A.hv = reinterpret_cast<uint32_t*>(base + L.hv);
   A.cap_v = L.cap_v;
   A.cap_wg = L.cap_wg;
   A.ctl = reinterpret_cast<SsCtl*>(base + L.ctl);

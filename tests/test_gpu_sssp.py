@@ -78,6 +78,39 @@ def test_tiers_and_geometry_do_not_change_results(dawn, ti):
             assert_sssp_matches(gg, s, d, tag=f"tuning{ti}")
 
 
+# Rows of at most t_lane edges are taken from a scan of the step's frontier
+# bitmap, not from a queue.  Vertex counts that leave a partial last word and
+# block, grids of one to a few workgroups (many bitmap blocks per wavefront),
+# t_lane at both ends of its range, and the last vertex as a source.
+SCAN_GRAPHS = [(31, 3), (33, 3), (2047, 4), (2049, 4), (65537, 6), (200003, 8)]
+SCAN_TUNINGS = [
+    dict(small_m=0, mode=2, ss_tail_grid=1),
+    dict(small_m=0, mode=2, ss_tail_grid=3),
+    dict(small_m=0, mode=1, grid=5, step_launches=4096),
+    dict(small_m=0, t_lane=1),
+    dict(small_m=0, t_lane=64, t_wave=64),
+]
+
+
+@pytest.mark.parametrize("ti", range(len(SCAN_TUNINGS)))
+def test_short_rows_from_the_frontier_bitmap(dawn, ti):
+    for n, deg in SCAN_GRAPHS:
+        g = graphgen.er(n, n * deg, 300 + n, weights="u32")
+        for s in list(graphgen.pick_sources(g, 2, ti + 1)) + [n - 1]:
+            announce("bitmap scan", SCAN_TUNINGS[ti], "n", n, "source", s)
+            d, info = _run(dawn, g, s, **SCAN_TUNINGS[ti])
+            assert info["converged"] == 1
+            assert_sssp_matches(g, int(s), d, tag=f"scan{ti}-n{n}")
+        gu = graphgen.er(n, n * deg, 300 + n, weights="u32one")
+        announce("bitmap scan, unit weights", SCAN_TUNINGS[ti], "n", n)
+        d, info = _run(dawn, gu, n - 1, **SCAN_TUNINGS[ti])
+        lvl = oracle.bfs(gu, n - 1)
+        assert np.array_equal(to_np_u32(d), np.where(lvl < 0, INF32, lvl).astype(np.uint32))
+        _, c = oracle.govm(gu, n - 1)
+        for key in ("steps", "edges_scanned", "improvements", "frontier_entries"):
+            assert info[key] == c[key], key
+
+
 def test_grid_f32_small(dawn):
     g = graphgen.grid(96, 80, 0.01, 31, weights="f32unit")
     for s in graphgen.pick_sources(g, 3, 2):
