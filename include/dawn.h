@@ -163,7 +163,7 @@ typedef struct {
  * tile_k: sources per tile for dawn_msssp / dawn_apsp, a multiple of 64,
  * at most DAWN_TILE_K_MAX. */
 typedef struct {
-  int32_t t_lane;     /* 1..64, default 16 */
+  int32_t t_lane;     /* 1..4096, default 256 */
   int32_t t_wave;     /* max(64,t_lane)..65536, default 2048 */
   int32_t t_chunk;    /* 256..1<<20, default 8192 */
   int32_t wg_threads; /* default 0 (auto) */

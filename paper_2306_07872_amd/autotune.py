@@ -30,7 +30,7 @@ from . import sssp_workspace_bytes, tile_bytes
 SSSP_SPACE = {
     "wg_threads": [256, 512, 1024],
     "mode": [1, 2],
-    "t_lane": [4, 8, 16, 32],
+    "t_lane": [16, 64, 256, 1024],
     "t_wave": [256, 1024, 2048, 8192],
     "t_chunk": [1024, 4096, 8192, 32768],
 }

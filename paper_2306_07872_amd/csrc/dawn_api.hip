@@ -125,7 +125,7 @@ const Residency& residency_cached(const void* kernel, int threads, int api_per_c
 }
 
 static bool tuning_ok(const Tuning& t) {
-  return t.t_lane >= 1 && t.t_lane <= 64 && t.t_wave >= std::max(64, t.t_lane) &&
+  return t.t_lane >= 1 && t.t_lane <= 4096 && t.t_wave >= std::max(64, t.t_lane) &&
          t.t_wave <= 65536 && t.t_chunk >= 256 && t.t_chunk <= (1 << 20) &&
          (t.wg_threads == 0 || t.wg_threads == 256 || t.wg_threads == 512 || t.wg_threads == 1024) && t.grid >= 0 &&
          t.grid <= (1 << 20) && t.mode >= 0 && t.mode <= 2 && t.step_launches >= 0 &&

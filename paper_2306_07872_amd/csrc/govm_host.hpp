@@ -11,7 +11,7 @@
 namespace dawn {
 
 struct Tuning {
-  int32_t t_lane = 16;
+  int32_t t_lane = 256;
   int32_t t_wave = 2048;
   int32_t t_chunk = 8192;
   int32_t wg_threads = 0;

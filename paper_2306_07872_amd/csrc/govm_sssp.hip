@@ -9,15 +9,18 @@
 // after n steps.
 //
 // Mapping to the device:
-// - delta is kept compacted as three queues binned by out-degree:
-//     lane tier (deg <= t_lane): 64 rows per wavefront; the wavefront's rows are
-//       concatenated through an LDS prefix sum so each lane takes one edge;
-//     wave tier (deg <= t_wave): one wavefront per row, lanes stride the row;
-//     workgroup tier: the row is cut into t_chunk-edge chunks, one workgroup each.
-// - beta is a bitmap; the lane whose atomicOr first sets v's bit appends v to
-//   the right next-step queue (wavefront ballot + mbcnt prefix, one atomicAdd
-//   per wavefront).  The bitmap of the current step is cleared by the lanes
-//   that expand its rows, so no O(n) scan is ever needed.
+// - delta is the beta bitmap of the step, split by out-degree:
+//     lane tier (deg <= t_lane): found by scanning the bitmap a block of words
+//       at a time, 64 rows per wavefront; the wavefront's rows are concatenated
+//       through an LDS prefix sum so each lane takes one edge;
+//     wave tier (deg <= t_wave): also queued; one wavefront per row, lanes
+//       stride the row;
+//     workgroup tier: also queued, the row cut into t_chunk-edge chunks, one
+//       workgroup each.
+// - the lane whose atomicOr first sets a long row's bit appends it to the
+//   right next-step queue (wavefront ballot + mbcnt prefix, gathered per
+//   workgroup in LDS, one atomicAdd per tier and workgroup).  The scan clears
+//   the bitmap of the current step, n/32 words per step.
 // - The relaxation reads alpha[v] with a plain load first (a stale value can
 //   only be higher, so skipping on it is safe) and uses atomicMin only when
 //   the candidate is smaller.  Order of updates inside a step does not matter:

@@ -43,7 +43,7 @@ def test_status_strings_and_build_info(lib):
 
 def test_tuning_roundtrip_and_range_checks(lib):
     t0 = dawn.get_tuning()
-    assert t0["t_lane"] == 16 and t0["tile_k"] == 256
+    assert t0["t_lane"] == 256 and t0["tile_k"] == 256
     prev = dawn.set_tuning(t_lane=8, tile_k=128)
     assert dawn.get_tuning()["t_lane"] == 8
     for bad in (dict(t_lane=0), dict(t_wave=10), dict(wg_threads=300), dict(wg_threads=128), dict(tile_k=100),

@@ -88,7 +88,7 @@ SCAN_TUNINGS = [
     dict(small_m=0, mode=2, ss_tail_grid=3),
     dict(small_m=0, mode=1, grid=5, step_launches=4096),
     dict(small_m=0, t_lane=1),
-    dict(small_m=0, t_lane=64, t_wave=64),
+    dict(small_m=0, t_lane=4096, t_wave=4096),
 ]
 
 
