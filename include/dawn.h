@@ -279,8 +279,8 @@ dawn_status dawn_sssp_tg_ws(const int32_t* rowptr_dev, const int32_t* colidx_dev
  * timing events) and launches the same kernels as dawn_sssp; the kernels clear
  * what must start at zero, so the array's contents from earlier calls do not
  * matter.  Graphs whose dawn_sssp_workspace_bytes exceeds the array return
- * DAWN_E_WORKSPACE before anything is launched (about 16.4 bytes per vertex plus
- * 0.62 bytes per edge: R-MAT scale 21 with 33.5M edges fits).  Every call on a
+ * DAWN_E_WORKSPACE before anything is launched (about 8.4 bytes per vertex plus
+ * 0.62 bytes per edge: R-MAT scale 22 with 33.5M edges fits).  Every call on a
  * device shares that device's array: calls that overlap on one device (two
  * streams, two threads) race and give wrong distances; order them on one
  * stream.  A run that does not converge is reported by dawn_run_status, as for

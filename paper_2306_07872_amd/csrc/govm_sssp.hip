@@ -1254,8 +1254,10 @@ SsLayout ss_layout(int64_t n, int64_t m) {
   L.cap_wg = (uint32_t)(m / 65 + m / 256 + 2);
   L.nwords = (n + 31) / 32;
   L.ctl = c.take(sizeof(SsCtl));
-  for (int i = 0; i < 2; i++) L.qlane[i] = c.take((size_t)n * 4);
   for (int i = 0; i < 2; i++) L.qwave[i] = c.take((size_t)n * 4);
+  // The one-workgroup kernel's queues share the wave-tier queues' memory: a
+  // one-workgroup run has no wave tier, and the other runs queue no short rows.
+  for (int i = 0; i < 2; i++) L.qlane[i] = L.qwave[i];
   for (int i = 0; i < 2; i++) L.qwg[i] = c.take((size_t)L.cap_wg * 16);
   for (int i = 0; i < 2; i++) L.bm[i] = c.take((size_t)L.nwords * 4);
   L.hv = c.take((size_t)L.nwords * 4);
