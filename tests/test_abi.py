@@ -46,7 +46,11 @@ def test_tuning_roundtrip_and_range_checks(lib):
     assert t0["t_lane"] == 256 and t0["tile_k"] == 256
     prev = dawn.set_tuning(t_lane=8, tile_k=128)
     assert dawn.get_tuning()["t_lane"] == 8
-    for bad in (dict(t_lane=0), dict(t_wave=10), dict(wg_threads=300), dict(wg_threads=128), dict(tile_k=100),
+    dawn.set_tuning(t_lane=4096, t_wave=4096)  # the lane tier's largest rows
+    assert dawn.get_tuning()["t_lane"] == 4096
+    dawn.set_tuning(t_lane=8, t_wave=2048)
+    for bad in (dict(t_lane=0), dict(t_lane=4097, t_wave=8192), dict(t_lane=256, t_wave=128),
+                dict(t_wave=10), dict(wg_threads=300), dict(wg_threads=128), dict(tile_k=100),
                 dict(tile_k=1024), dict(mode=3), dict(t_chunk=8), dict(tile_t_wave=4),
                 dict(tile_t_group=65), dict(tile_t_group=64, tile_t_wave=64),
                 dict(tile_skip=2), dict(small_m=-1), dict(step_min_m=-1), dict(tile_pull=1002),
