@@ -170,7 +170,7 @@ __global__ void ss_finalize_kernel(SsCtl* C, dawn_run_info* info, uint32_t* latc
 // tier per workgroup (a queue that fills up spills straight to global memory).
 constexpr int kLdsQWave = 512;
 constexpr int kUnroll = 4;      // edges in flight per lane (wave and workgroup tiers)
-constexpr int kUnrollLane = 2;  // edges in flight per lane (lane tier)
+constexpr int kUnrollLane = 4;  // edges in flight per lane (lane tier)
 
 struct SsShared {
   int stage[kMaxWavesPerBlock * 3 * kWave];      // lane-tier batch: prefix, row base, distance
