@@ -24,7 +24,7 @@ import time
 
 import numpy as np
 
-from . import Csr, check_runs, get_tuning, msssp, set_tuning, sssp, workspace
+from . import Csr, DawnError, check_runs, get_tuning, msssp, set_tuning, sssp, workspace
 from . import sssp_workspace_bytes, tile_bytes
 
 SSSP_SPACE = {
@@ -161,7 +161,10 @@ def tune(csr: Csr, sources, kind: str = "msssp", reps: int = 2, rounds: int = 1,
                     trial = dict(best)
                     trial[key] = c
                     set_tuning(reset=True)
-                    set_tuning(**_to_tuning(trial, cus))
+                    try:
+                        set_tuning(**_to_tuning(trial, cus))
+                    except DawnError:
+                        continue  # a combination the library rejects (t_wave below t_lane)
                     t = _time_calls(call, reps)
                     results.append((t, c))
                     if verbose:
