@@ -109,6 +109,43 @@ def _time_calls(fn, reps: int) -> float:
     return (time.perf_counter() - t0) / reps
 
 
+def descend(space: dict, base: dict, cus: int, t_default: float, time_trial,
+            rounds: int = 1, min_gain: float = 0.03):
+    """Coordinate descent over `space` (field -> candidate values), starting
+    from the tuning `base` whose calls take `t_default`.  time_trial(trial)
+    sets the fields of `trial` over the defaults and returns the time of the
+    calls, or None for a combination the library rejects.  A candidate
+    replaces the value held only when it is faster by more than `min_gain` (a
+    fraction).  Returns (the chosen fields, their time)."""
+    best = {}
+    best_t = t_default
+    for _ in range(rounds):
+        for key, cands in space.items():
+            cur = best.get(key, base.get(key, base["grid"] // cus if key == "grid_per_cu"
+                                     else None))
+            cands = list(cands)
+            if cur is not None and cur not in cands:
+                cands.append(cur)   # the value held now is always a candidate
+            results = []
+            for c in cands:
+                trial = dict(best)
+                trial[key] = c
+                t = time_trial(trial)
+                if t is not None:
+                    results.append((t, c))
+            if not results:
+                continue
+            held = [t for t, c in results if c == cur]
+            t_held = held[0] if held else best_t
+            t, c = min(results)
+            if t < t_held * (1.0 - min_gain):
+                best[key] = c
+                best_t = t
+            else:
+                best_t = min(best_t, t_held)
+    return best, best_t
+
+
 def tune(csr: Csr, sources, kind: str = "msssp", reps: int = 2, rounds: int = 1,
          space: dict | None = None, verbose: bool = False, tgraph=None,
          min_gain: float = 0.03) -> dict:
@@ -147,36 +184,19 @@ def tune(csr: Csr, sources, kind: str = "msssp", reps: int = 2, rounds: int = 1,
         set_tuning(reset=True)
         base = get_tuning()
         t_default = _time_calls(call, reps)
-        best = {}
-        best_t = t_default
-        for _ in range(rounds):
-            for key, cands in space.items():
-                cur = best.get(key, base.get(key, base["grid"] // cus if key == "grid_per_cu"
-                                         else None))
-                cands = list(cands)
-                if cur is not None and cur not in cands:
-                    cands.append(cur)   # the value held now is always a candidate
-                results = []
-                for c in cands:
-                    trial = dict(best)
-                    trial[key] = c
-                    set_tuning(reset=True)
-                    try:
-                        set_tuning(**_to_tuning(trial, cus))
-                    except DawnError:
-                        continue  # a combination the library rejects (t_wave below t_lane)
-                    t = _time_calls(call, reps)
-                    results.append((t, c))
-                    if verbose:
-                        print(f"  {kind} {trial}: {units / t:.1f} sources/s", flush=True)
-                held = [t for t, c in results if c == cur]
-                t_held = held[0] if held else best_t
-                t, c = min(results)
-                if t < t_held * (1.0 - min_gain):
-                    best[key] = c
-                    best_t = t
-                else:
-                    best_t = min(best_t, t_held)
+
+        def time_trial(trial):
+            set_tuning(reset=True)
+            try:
+                set_tuning(**_to_tuning(trial, cus))
+            except DawnError:
+                return None  # a combination the library rejects (t_wave below t_lane)
+            t = _time_calls(call, reps)
+            if verbose:
+                print(f"  {kind} {trial}: {units / t:.1f} sources/s", flush=True)
+            return t
+
+        best, best_t = descend(space, base, cus, t_default, time_trial, rounds, min_gain)
         check_runs()
         return {"tuning": _to_tuning(best, cus), "sources_per_s": units / best_t,
                 "default_sources_per_s": units / t_default, "kind": kind}
